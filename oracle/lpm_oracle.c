@@ -1,0 +1,493 @@
+/*
+ * FP64 CPU oracle of the stochastic Lagrangian particle model of
+ * Molnar Jr., Szakaly, Meszaros and Lagzi, "Air pollution modelling using a
+ * graphics processing unit with CUDA" (arXiv:0912.3223).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * HIP library is checked against.  It shares no code, header or table with
+ * the HIP library; only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.  Nothing in the product path calls it.
+ *
+ * Every quantity is computed in double precision with the C library's
+ * functions (no fast-math).  The time loop follows the paper's main loop
+ * (Sec. 3.2 and Fig. 1): in every step, every particle samples the weather,
+ * gets its diffusion coefficient, is moved by the wind and by turbulence and
+ * is tested for deposition; every n-th step the activities are summed on a
+ * rectangular grid.  Particles are independent (Sec. 1 end), so the particle
+ * loop of a step may run on several threads; each thread sums into its own
+ * deposition grid and ledger, added together at the end.
+ *
+ * Readings of points the paper leaves open (all listed in the design notes):
+ *  - random numbers: Philox4x32-10 (Salmon et al., SC'11) replaces the
+ *    Mersenne Twister of Sec. 2; counter (id, step, purpose, 0), key
+ *    (seed low word, scenario).  Uniforms ((r >> 8) + 1) 2^-24 in (0, 1],
+ *    normals by the basic trigonometric Box-Muller form.
+ *  - Eq. (2) is used with the Ito drift dK_z/dz dt and K_z evaluated at the
+ *    midpoint z + K_z' dt / 2 (Visser 1997) so that a height-dependent K_z
+ *    keeps a well-mixed tracer well mixed; with constant K it is Eq. (2).
+ *  - Eq. (3) with Phi = 1 (neutral): exponent 1 ("parabolic") or 2.
+ *  - dry deposition (Sec. 2, details not given): mass depletion at rate
+ *    v_d phi(z), phi(z) = (2/h_s)(1 - z/h_s) on [0, h_s];
+ *    wet deposition: rate Lambda0 inside an elliptical rain region with a
+ *    linear edge; both applied at the post-move position.
+ *  - decay (Sec. 2, Sec. 3.2): deterministic, activity a0 m exp(-lambda age);
+ *    the per-step loss is split between decay and deposition by their rates.
+ *  - ground reflection and a lid: z folded into [0, H_lid].
+ *  - horizontal exit at the edge of a bounded wind domain (Sec. 3.2).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    /* release schedule (Sec. 3.2: emission profile known a priori) */
+    int64_t n_total, n_local, id_base, id_stride;
+    int32_t s_release, pad0;
+    /* source */
+    double xs, ys, h, q, wind_scale, v_d;
+    uint32_t scenario, pad1;
+    uint64_t seed;
+    /* physics */
+    double dt, Kh, Kz_const, kappa_ustar, z0, H_mix, H_lid, h_s;
+    int32_t kz_kind, n_nuc;
+    double lambda[4];
+    double Lambda0, rain_cx, rain_cy, rain_a, rain_b, rain_angle, rain_edge;
+    /* wind field, float [nt][nz][ny][nx][ncomp], cell-centred nodes */
+    const float* f;
+    const float* z_levels; /* NULL: node heights (k + 1/2) fdz */
+    int32_t nx, ny, nz, nt, ncomp, bounded;
+    double fx0, fy0, fdx, fdy, fdz, ft0, fdt;
+    /* concentration grid */
+    int32_t cnx, cny, cnz, cmode, cdensity, pad2;
+    double cx0, cy0, cz0, cdx, cdy, cdz;
+    /* deposition grid */
+    int32_t dnx, dny, dmode, ddensity;
+    double dx0, dy0, ddx, ddy;
+} orc_problem;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), random numbers of Eq. 2 */
+/* ------------------------------------------------------------------------ */
+
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                       uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += W0; k1 += W1; }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Four uniforms in (0, 1] on the 2^-24 lattice for (id, step, purpose). */
+void orc_uniforms(uint64_t seed, uint32_t scenario, uint32_t id, uint32_t step,
+                  uint32_t purpose, double u[4])
+{
+    uint32_t ctr[4] = {id, step, purpose, 0u};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), scenario};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    for (int j = 0; j < 4; ++j)
+        u[j] = ((double)(r[j] >> 8) + 1.0) * (1.0 / 16777216.0);
+}
+
+/* Standard normals for Eq. (2): basic Box-Muller (xi[3] is the spare). */
+void orc_normals(uint64_t seed, uint32_t scenario, uint32_t id, uint32_t step,
+                 uint32_t purpose, double xi[4])
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double u[4];
+    orc_uniforms(seed, scenario, id, step, purpose, u);
+    double r0 = sqrt(-2.0 * log(u[0]));
+    double r2 = sqrt(-2.0 * log(u[2]));
+    xi[0] = r0 * cos(two_pi * u[1]);
+    xi[1] = r0 * sin(two_pi * u[1]);
+    xi[2] = r2 * cos(two_pi * u[3]);
+    xi[3] = r2 * sin(two_pi * u[3]);
+}
+
+/* Normals of n consecutive ids starting at id0 for one step: out[n][4]. */
+void orc_normals_batch(uint64_t seed, uint32_t scenario, uint32_t id0, int64_t n,
+                       uint32_t step, uint32_t purpose, double* out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        orc_normals(seed, scenario, id0 + (uint32_t)i, step, purpose, out + 4 * i);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Weather sampling: linear in x, y, z and t (Sec. 3.2)                       */
+/* ------------------------------------------------------------------------ */
+
+/* Fractional node index of a coordinate on cell-centred nodes, clamped to the
+ * node range; returns the lower node and the weight of the upper one. */
+static void axis_weight(double pos, double origin, double spacing, int n,
+                        int* i0, int* i1, double* w)
+{
+    double fi = (pos - origin) / spacing - 0.5;
+    if (fi < 0.0) fi = 0.0;
+    if (fi > (double)(n - 1)) fi = (double)(n - 1);
+    int i = (int)floor(fi);
+    if (i > n - 2) i = (n >= 2) ? n - 2 : 0;
+    *i0 = i;
+    *i1 = (i + 1 < n) ? i + 1 : i;
+    *w = fi - (double)i;
+}
+
+/* Same for explicitly given (nonuniform) node heights. */
+static void level_weight(double z, const float* lev, int n, int* k0, int* k1,
+                         double* w)
+{
+    if (n == 1 || z <= (double)lev[0]) { *k0 = 0; *k1 = (n > 1); *w = 0.0; return; }
+    if (z >= (double)lev[n - 1]) { *k0 = n - 2; *k1 = n - 1; *w = 1.0; return; }
+    int k = 0;
+    while (k + 1 < n - 1 && (double)lev[k + 1] <= z) ++k;
+    *k0 = k;
+    *k1 = k + 1;
+    *w = (z - (double)lev[k]) / ((double)lev[k + 1] - (double)lev[k]);
+}
+
+static double node(const orc_problem* P, int t, int k, int j, int i, int c)
+{
+    size_t idx = ((((size_t)t * P->nz + k) * P->ny + j) * P->nx + i) * P->ncomp + c;
+    return (double)P->f[idx];
+}
+
+/* Wind (u, v, w) at (x, y, z) and time t, before the wind-scale factor. */
+void orc_wind(const orc_problem* P, double x, double y, double z, double t,
+              double uvw[3])
+{
+    int i0, i1, j0, j1, k0, k1, t0, t1;
+    double wx, wy, wz, wt;
+    axis_weight(x, P->fx0, P->fdx, P->nx, &i0, &i1, &wx);
+    axis_weight(y, P->fy0, P->fdy, P->ny, &j0, &j1, &wy);
+    if (P->z_levels)
+        level_weight(z, P->z_levels, P->nz, &k0, &k1, &wz);
+    else
+        axis_weight(z, 0.0, P->fdz, P->nz, &k0, &k1, &wz);
+    double ft = (P->nt > 1) ? (t - P->ft0) / P->fdt : 0.0;
+    if (ft < 0.0) ft = 0.0;
+    if (ft > (double)(P->nt - 1)) ft = (double)(P->nt - 1);
+    t0 = (int)floor(ft);
+    if (t0 > P->nt - 2) t0 = (P->nt >= 2) ? P->nt - 2 : 0;
+    t1 = (t0 + 1 < P->nt) ? t0 + 1 : t0;
+    wt = ft - (double)t0;
+
+    for (int c = 0; c < 3; ++c) {
+        if (c >= P->ncomp) { uvw[c] = 0.0; continue; }
+        double val[2];
+        int tt[2] = {t0, t1};
+        for (int a = 0; a < 2; ++a) {
+            int T = tt[a];
+            double s = 0.0;
+            s += (1 - wz) * (1 - wy) * (1 - wx) * node(P, T, k0, j0, i0, c);
+            s += (1 - wz) * (1 - wy) * wx * node(P, T, k0, j0, i1, c);
+            s += (1 - wz) * wy * (1 - wx) * node(P, T, k0, j1, i0, c);
+            s += (1 - wz) * wy * wx * node(P, T, k0, j1, i1, c);
+            s += wz * (1 - wy) * (1 - wx) * node(P, T, k1, j0, i0, c);
+            s += wz * (1 - wy) * wx * node(P, T, k1, j0, i1, c);
+            s += wz * wy * (1 - wx) * node(P, T, k1, j1, i0, c);
+            s += wz * wy * wx * node(P, T, k1, j1, i1, c);
+            val[a] = s;
+        }
+        uvw[c] = (1 - wt) * val[0] + wt * val[1];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Vertical diffusivity, Eq. (3) in the neutral limit Phi = 1                 */
+/* ------------------------------------------------------------------------ */
+
+void orc_kz(const orc_problem* P, double z, double* K, double* dK)
+{
+    if (P->kz_kind == 0) { *K = P->Kz_const; *dK = 0.0; return; }
+    double H = P->H_mix, ku = P->kappa_ustar;
+    if (z < 0.0) z = 0.0;
+    if (z >= H) { *K = 0.0; *dK = 0.0; return; }
+    double g = 1.0 - z / H;
+    if (P->kz_kind == 1) {
+        *K = ku * (z + P->z0) * g;
+        *dK = ku * (g - (z + P->z0) / H);
+    } else {
+        *K = ku * (z + P->z0) * g * g;
+        *dK = ku * (g * g - 2.0 * (z + P->z0) * g / H);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Deposition rates (Sec. 2: dry below the mixing height, wet with rain)     */
+/* ------------------------------------------------------------------------ */
+
+double orc_dry_rate(const orc_problem* P, double z)
+{
+    if (P->v_d == 0.0 || z < 0.0 || z >= P->h_s) return 0.0;
+    return P->v_d * (2.0 / P->h_s) * (1.0 - z / P->h_s);
+}
+
+double orc_wet_rate(const orc_problem* P, double x, double y)
+{
+    if (P->Lambda0 == 0.0) return 0.0;
+    double dx = x - P->rain_cx, dy = y - P->rain_cy;
+    double ca = cos(P->rain_angle), sa = sin(P->rain_angle);
+    double xr = ca * dx + sa * dy;
+    double yr = -sa * dx + ca * dy;
+    double re = sqrt((xr / P->rain_a) * (xr / P->rain_a) + (yr / P->rain_b) * (yr / P->rain_b));
+    double f = (1.0 - re) / P->rain_edge + 0.5;
+    if (f < 0.0) f = 0.0;
+    if (f > 1.0) f = 1.0;
+    return P->Lambda0 * f;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gridding (Sec. 3.2: activities summed on a rectangular grid)              */
+/* ------------------------------------------------------------------------ */
+
+/* Add value a at (x, y, z) to grid g[nz][ny][nx]; mode 0 = cell containing
+ * the point (half-open cells), 1 = trilinear cloud-in-cell about cell centres
+ * with out-of-grid weights dropped.  nz == 1 with dz <= 0 means a 2-D grid. */
+static void bin3(double* g, int nx, int ny, int nz, double x0, double y0,
+                 double z0, double dx, double dy, double dz, int mode,
+                 double x, double y, double z, double a, int two_d)
+{
+    if (mode == 0) {
+        double fx = floor((x - x0) / dx), fy = floor((y - y0) / dy);
+        double fz = two_d ? 0.0 : floor((z - z0) / dz);
+        if (fx < 0 || fy < 0 || fz < 0 || fx >= nx || fy >= ny || fz >= nz) return;
+        g[((size_t)fz * ny + (size_t)fy) * nx + (size_t)fx] += a;
+        return;
+    }
+    double fx = (x - x0) / dx - 0.5, fy = (y - y0) / dy - 0.5;
+    double fz = two_d ? 0.0 : (z - z0) / dz - 0.5;
+    double ix = floor(fx), iy = floor(fy), iz = floor(fz);
+    double wx = fx - ix, wy = fy - iy, wz = fz - iz;
+    int nzc = two_d ? 1 : 2;
+    for (int c = 0; c < nzc; ++c) {
+        double kz = iz + c;
+        double vz = two_d ? 1.0 : (c ? wz : 1.0 - wz);
+        if (kz < 0 || kz >= nz) continue;
+        for (int b = 0; b < 2; ++b) {
+            double ky = iy + b;
+            double vy = b ? wy : 1.0 - wy;
+            if (ky < 0 || ky >= ny) continue;
+            for (int a2 = 0; a2 < 2; ++a2) {
+                double kx = ix + a2;
+                double vx = a2 ? wx : 1.0 - wx;
+                if (kx < 0 || kx >= nx) continue;
+                g[((size_t)kz * ny + (size_t)ky) * nx + (size_t)kx] += a * vx * vy * vz;
+            }
+        }
+    }
+}
+
+static int64_t birth_of(const orc_problem* P, int64_t gid)
+{
+    return (gid * (int64_t)P->s_release) / P->n_total;
+}
+
+static double a0_of(const orc_problem* P)
+{
+    return P->q * (double)P->s_release * P->dt / (double)P->n_total;
+}
+
+/* Concentration after step s (time (s + 1) dt) of the given particles:
+ * A_n = a0 m exp(-lambda_n age), summed per nuclide on the concentration
+ * grid; out[n_nuc][cnz][cny][cnx] is added to. */
+void orc_grid_concentration(const orc_problem* P, int32_t s, const double* x,
+                            const double* y, const double* z, const double* m,
+                            double* out)
+{
+    size_t cells = (size_t)P->cnx * P->cny * P->cnz;
+    double vol = P->cdensity ? P->cdx * P->cdy * P->cdz : 1.0;
+    double a0 = a0_of(P);
+    for (int64_t i = 0; i < P->n_local; ++i) {
+        int64_t gid = P->id_base + i * P->id_stride;
+        int64_t b = birth_of(P, gid);
+        if (b > s || !(m[i] > 0.0)) continue;
+        double age = (double)(s + 1 - b) * P->dt;
+        for (int n = 0; n < P->n_nuc; ++n) {
+            double A = a0 * m[i] * exp(-P->lambda[n] * age);
+            bin3(out + n * cells, P->cnx, P->cny, P->cnz, P->cx0, P->cy0, P->cz0,
+                 P->cdx, P->cdy, P->cdz, P->cmode, x[i], y[i], z[i], A / vol, 0);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One time step of one particle (Sec. 3.2 main loop, Eqs. 1-3)              */
+/* ------------------------------------------------------------------------ */
+
+static double fold(double z, double H)
+{
+    for (int it = 0; it < 64; ++it) {
+        if (z < 0.0) z = -z;
+        else if (H > 0.0 && z > H) z = 2.0 * H - z;
+        else break;
+    }
+    return z;
+}
+
+/* Advance particle i (global id gid, birth b) over step s.  led[n*4 + 1..3]
+ * receive deposited, decayed and exited activity; dep receives the deposited
+ * activity on the deposition grid. */
+static void step_particle(const orc_problem* P, int64_t gid, int64_t b, int32_t s,
+                          double* px, double* py, double* pz, double* pm,
+                          double* led, double* dep)
+{
+    const double dt = P->dt;
+    double x = *px, y = *py, z = *pz, m = *pm;
+    double age = (double)(s - b) * dt;
+    double a0 = a0_of(P);
+
+    /* random numbers for Eq. (2) */
+    double xi[4];
+    orc_normals(P->seed, P->scenario, (uint32_t)gid, (uint32_t)s, 0u, xi);
+
+    /* weather sample at the start-of-step position and time (Eq. 1) */
+    double uvw[3];
+    orc_wind(P, x, y, z, (double)s * dt, uvw);
+    double u = P->wind_scale * uvw[0];
+    double v = P->wind_scale * uvw[1];
+    double w = P->wind_scale * uvw[2];
+
+    /* diffusion coefficients (Eq. 2, Eq. 3) */
+    double Kz, dKz, Kzm, dKzm;
+    orc_kz(P, z, &Kz, &dKz);
+    double zm = z + 0.5 * dKz * dt;
+    if (zm < 0.0) zm = 0.0;
+    if (zm > P->H_mix) zm = P->H_mix;
+    orc_kz(P, zm, &Kzm, &dKzm);
+
+    /* move: advection + turbulent displacement (Eq. 1, Eq. 2) */
+    double xn = x + u * dt + xi[0] * sqrt(2.0 * P->Kh * dt);
+    double yn = y + v * dt + xi[1] * sqrt(2.0 * P->Kh * dt);
+    double zn = z + w * dt + dKz * dt + xi[2] * sqrt(2.0 * Kzm * dt);
+    zn = fold(zn, P->H_lid);
+
+    /* decay and deposition at the new position */
+    double k = orc_dry_rate(P, zn) + orc_wet_rate(P, xn, yn);
+    double mn = m * exp(-k * dt);
+    size_t cells = (size_t)P->dnx * P->dny;
+    double area = P->ddensity ? P->ddx * P->ddy : 1.0;
+    for (int n = 0; n < P->n_nuc; ++n) {
+        double lam = P->lambda[n];
+        double A = a0 * m * exp(-lam * age);
+        double r = lam + k;
+        if (r <= 0.0) continue;
+        double loss = A * (-expm1(-r * dt));
+        double d = loss * (k / r);
+        double c = loss * (lam / r);
+        led[n * 4 + 1] += d;
+        led[n * 4 + 2] += c;
+        if (d != 0.0)
+            bin3(dep + n * cells, P->dnx, P->dny, 1, P->dx0, P->dy0, 0.0, P->ddx,
+                 P->ddy, 1.0, P->dmode, xn, yn, 0.0, d / area, 1);
+    }
+
+    /* leaving the simulated area inactivates the particle (Sec. 3.2) */
+    if (P->bounded) {
+        double X1 = P->fx0 + P->nx * P->fdx, Y1 = P->fy0 + P->ny * P->fdy;
+        if (xn < P->fx0 || xn >= X1 || yn < P->fy0 || yn >= Y1) {
+            for (int n = 0; n < P->n_nuc; ++n)
+                led[n * 4 + 3] += a0 * mn * exp(-P->lambda[n] * (age + dt));
+            mn = 0.0;
+        }
+    }
+    *px = xn; *py = yn; *pz = zn; *pm = mn;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Main loop                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Run steps [s_begin, s_end).  In step s the particles born at s are released
+ * at the source with m = 1, then every released particle with m > 0 is
+ * advanced; after a step listed in snap_steps the concentration is gridded
+ * into snaps[k].  x, y, z, m (length n_local) are updated in place; dep
+ * ([n_nuc][dny][dnx]), ledger ([n_nuc][4] = released, deposited, decayed,
+ * exited) and snaps ([n_snap][n_nuc][cnz][cny][cnx]) are added to.
+ * Returns 0, or -1 for invalid arguments. */
+int orc_simulate(const orc_problem* P, int32_t s_begin, int32_t s_end,
+                 double* x, double* y, double* z, double* m, double* dep,
+                 double* ledger, const int32_t* snap_steps, int32_t n_snap,
+                 double* snaps, int32_t nthreads)
+{
+    if (!P || P->n_nuc < 1 || P->n_nuc > 4 || P->n_total <= 0 || P->s_release <= 0 ||
+        P->n_local < 0 || P->id_stride <= 0 || !x || !y || !z || !m || !dep || !ledger ||
+        (n_snap > 0 && (!snaps || !snap_steps)) || !P->f || P->nx < 1 || P->ny < 1 ||
+        P->nz < 1 || P->nt < 1 || (P->ncomp != 2 && P->ncomp != 3))
+        return -1;
+    int nth = 1;
+#ifdef _OPENMP
+    nth = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    size_t dcells = (size_t)P->n_nuc * P->dnx * P->dny;
+    size_t ccells = (size_t)P->n_nuc * P->cnx * P->cny * P->cnz;
+    double* dep_t = (double*)calloc((size_t)nth * dcells, sizeof(double));
+    double* led_t = (double*)calloc((size_t)nth * 16, sizeof(double));
+    if (!dep_t || !led_t) { free(dep_t); free(led_t); return -1; }
+    const double a0 = a0_of(P);
+
+#pragma omp parallel num_threads(nth)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* my_dep = dep_t + (size_t)tid * dcells;
+        double* my_led = led_t + (size_t)tid * 16;
+        for (int32_t s = s_begin; s < s_end; ++s) {
+#pragma omp for schedule(static, 256)
+            for (int64_t i = 0; i < P->n_local; ++i) {
+                int64_t gid = P->id_base + i * P->id_stride;
+                int64_t b = birth_of(P, gid);
+                if (b == s) {
+                    x[i] = P->xs; y[i] = P->ys; z[i] = P->h; m[i] = 1.0;
+                    for (int n = 0; n < P->n_nuc; ++n) my_led[n * 4 + 0] += a0;
+                }
+                if (b <= s && m[i] > 0.0)
+                    step_particle(P, gid, b, s, &x[i], &y[i], &z[i], &m[i], my_led, my_dep);
+            }
+            for (int32_t k = 0; k < n_snap; ++k) {
+                if (snap_steps[k] != s) continue;
+#pragma omp single
+                orc_grid_concentration(P, s, x, y, z, m, snaps + (size_t)k * ccells);
+            }
+        }
+    }
+    for (int t = 0; t < nth; ++t) {
+        for (size_t c = 0; c < dcells; ++c) dep[c] += dep_t[(size_t)t * dcells + c];
+        for (int c = 0; c < 4 * P->n_nuc; ++c) ledger[c] += led_t[(size_t)t * 16 + c];
+    }
+    free(dep_t);
+    free(led_t);
+    return 0;
+}
+
+/* Activity still airborne after step s: sum of a0 m exp(-lambda age). */
+void orc_airborne(const orc_problem* P, int32_t s, const double* m, double* out)
+{
+    double a0 = a0_of(P);
+    for (int n = 0; n < P->n_nuc; ++n) out[n] = 0.0;
+    for (int64_t i = 0; i < P->n_local; ++i) {
+        int64_t gid = P->id_base + i * P->id_stride;
+        int64_t b = birth_of(P, gid);
+        if (b > s || !(m[i] > 0.0)) continue;
+        for (int n = 0; n < P->n_nuc; ++n)
+            out[n] += a0 * m[i] * exp(-P->lambda[n] * (double)(s + 1 - b) * P->dt);
+    }
+}
