@@ -1,0 +1,157 @@
+"""Benchmark: forward particle-steps/s of the particle-dispersion hot path on
+one MI355X.
+
+Workload (one benchmark step = one full forward run): 1e6 particles released
+continuously from (0, 0, 50 m) over 6 h at dt = 5 s (4320 time steps), steady
+200 x 200 x 30 wind field (250/250/40 m nodes, power-law profile with four
+seeded Fourier modes of direction), parabolic K_z over a 1000 m mixed layer,
+dry deposition (v_d = 0.002 m/s), wet scavenging (1e-5 1/s) in a seeded
+elliptical rain region, two nuclides (lambda = 1e-6, 1e-5 1/s).  Every step of
+a run: release, particle step (advection, turbulent random walk, reflection,
+decay, dry/wet deposition with the deposition scatter), concentration gridding
+on the 200 x 200 x 30 x 2 cloud-in-cell grid every 60 steps, and the final
+deposition grid.  `value` = active particle-steps per second over the timed
+runs (inputs resident in HBM).
+
+    python bench.py [--steps K] [--warmup W] [--spl STEPS_PER_LAUNCH]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU issue peak with packed FP32 disabled: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz lane-operations per second (the 157.3 TFLOP/s FP32 figure counts a
+# packed two-lane FMA as four flops).
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# Lane-cycles of VALU work one particle-step of the method needs (Philox
+# 10 rounds, Box-Muller, trilinear wind, K_z at two heights, move and fold,
+# deposition rates, decay of two nuclides, FP64 ledger sums); derived in the
+# design notes.  Quarter-rate transcendentals and 32-bit multiplies count 4.
+ALG_OPS_PER_PSTEP = 300
+HBM_PEAK = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--spl", type=int, default=60, help="time steps per step-kernel launch")
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=8,
+                    help="oracle sample: every k-th particle id of the same workload")
+    return ap.parse_args()
+
+
+def cpu_baseline(case, stride):
+    import oracle
+    sub = case.with_(schedule=case.schedule.subset(stride))
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    o = oracle.Oracle(sub)
+    t = time.perf_counter()
+    r = o.simulate(nthreads=threads)
+    dt = time.perf_counter() - t
+    return {"value": r["psteps"] / dt, "unit": "particle-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"every {stride}th particle id of the same 1e6-particle 6 h run "
+                      f"({sub.schedule.local_count} particles, {r['psteps']} particle-steps, "
+                      f"{dt:.1f} s, FP64, {threads} OpenMP threads)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_0912_3223_amd as L
+
+    case = synth.c1(n_total=a.n)
+    snaps = case.output_steps()
+    run = L.DeviceRun(case)
+    stream = torch.cuda.current_stream()
+
+    # step-kernel timing: HIP events on the stream the kernels are launched on
+    ev = []
+
+    def one_run(timed):
+        run.reset()
+        for s0, s1 in run.windows(0, case.n_steps, a.spl, snaps):
+            run.release(s0, s1 - s0)
+            if timed:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                run.step(s0, s1 - s0)
+                e1.record(stream)
+                ev.append((e0, e1))
+            else:
+                run.step(s0, s1 - s0)
+            if (s1 - 1) in snaps:
+                run.grid_concentration(s1 - 1)
+        run.grid_deposition()
+
+    for _ in range(a.warmup):
+        one_run(False)
+    torch.cuda.synchronize()
+    psteps = run.particle_steps()
+    run.check()
+    ledger = run.ledger()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        one_run(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert run.particle_steps() == psteps, "runs are not deterministic in their step count"
+
+    ms = (t1 - t0) * 1e3 / a.steps
+    value = psteps * a.steps / (t1 - t0)
+    step_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    launches_per_run = len(step_ms) // a.steps
+    step_total_s = sum(step_ms) / 1e3 / a.steps
+    avg_launch_s = sum(step_ms) / 1e3 / len(step_ms)
+    ops_per_launch = ALG_OPS_PER_PSTEP * psteps / launches_per_run
+    achieved = ops_per_launch / avg_launch_s
+    out = {
+        "metric": "particle-steps/s (forward)",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1e6-particle 6 h continuous point release, 200x200x30 steady "
+                               "gridded wind, dt=5 s, 4320 steps, CIC gridding every 60 steps",
+                   "particles": case.schedule.n_total, "time_steps": case.n_steps,
+                   "steps_per_launch": a.spl, "particle_steps_per_run": psteps},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                     "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
+                     "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "kernel": "step_kernel", "avg_launch_ms": avg_launch_s * 1e3,
+                     "launches_per_run": launches_per_run,
+                     "step_kernel_share": step_total_s / (ms / 1e3)},
+        "ledger_first_nuclide": list(map(float, ledger[0])),
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, a.cpu_stride)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

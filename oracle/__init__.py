@@ -86,7 +86,8 @@ def lib():
         L.orc_wet_rate.restype = C.c_double
         L.orc_grid_concentration.argtypes = [P, C.c_int32, dp, dp, dp, dp, dp]
         L.orc_simulate.argtypes = [P, C.c_int32, C.c_int32, dp, dp, dp, dp, dp, dp,
-                                   C.POINTER(C.c_int32), C.c_int32, dp, C.c_int32]
+                                   C.POINTER(C.c_int32), C.c_int32, dp, C.c_int32,
+                                   C.POINTER(C.c_int64)]
         L.orc_simulate.restype = C.c_int
         L.orc_airborne.argtypes = [P, C.c_int32, dp, dp]
         _lib = L
@@ -174,14 +175,15 @@ class Oracle:
         ledger = np.zeros((nn, 4))
         snaps_idx = np.asarray(list(snap_steps), dtype=np.int32)
         snaps = np.zeros((max(len(snaps_idx), 1), nn, cg.nz, cg.ny, cg.nx))
+        psteps = C.c_int64(0)
         rc = lib().orc_simulate(C.byref(self.p), s_begin, s_end, _dp(st["x"]), _dp(st["y"]),
                                 _dp(st["z"]), _dp(st["m"]), _dp(dep), _dp(ledger),
                                 snaps_idx.ctypes.data_as(C.POINTER(C.c_int32)),
-                                len(snaps_idx), _dp(snaps), nthreads)
+                                len(snaps_idx), _dp(snaps), nthreads, C.byref(psteps))
         if rc != 0:
             raise ValueError("oracle rejected the problem")
         return {"state": st, "dep": dep, "ledger": ledger,
-                "snaps": snaps[:len(snaps_idx)]}
+                "snaps": snaps[:len(snaps_idx)], "psteps": psteps.value}
 
     def grid_concentration(self, s: int, x, y, z, m):
         cg, nn = self.case.conc_grid, self.case.physics.n_nuc

@@ -419,12 +419,13 @@ static void step_particle(const orc_problem* P, int64_t gid, int64_t b, int32_t 
  * advanced; after a step listed in snap_steps the concentration is gridded
  * into snaps[k].  x, y, z, m (length n_local) are updated in place; dep
  * ([n_nuc][dny][dnx]), ledger ([n_nuc][4] = released, deposited, decayed,
- * exited) and snaps ([n_snap][n_nuc][cnz][cny][cnx]) are added to.
+ * exited) and snaps ([n_snap][n_nuc][cnz][cny][cnx]) are added to;
+ * *psteps (if not NULL) receives the number of particle-steps advanced.
  * Returns 0, or -1 for invalid arguments. */
 int orc_simulate(const orc_problem* P, int32_t s_begin, int32_t s_end,
                  double* x, double* y, double* z, double* m, double* dep,
                  double* ledger, const int32_t* snap_steps, int32_t n_snap,
-                 double* snaps, int32_t nthreads)
+                 double* snaps, int32_t nthreads, int64_t* psteps)
 {
     if (!P || P->n_nuc < 1 || P->n_nuc > 4 || P->n_total <= 0 || P->s_release <= 0 ||
         P->n_local < 0 || P->id_stride <= 0 || !x || !y || !z || !m || !dep || !ledger ||
@@ -439,7 +440,8 @@ int orc_simulate(const orc_problem* P, int32_t s_begin, int32_t s_end,
     size_t ccells = (size_t)P->n_nuc * P->cnx * P->cny * P->cnz;
     double* dep_t = (double*)calloc((size_t)nth * dcells, sizeof(double));
     double* led_t = (double*)calloc((size_t)nth * 16, sizeof(double));
-    if (!dep_t || !led_t) { free(dep_t); free(led_t); return -1; }
+    int64_t* cnt_t = (int64_t*)calloc((size_t)nth, sizeof(int64_t));
+    if (!dep_t || !led_t || !cnt_t) { free(dep_t); free(led_t); free(cnt_t); return -1; }
     const double a0 = a0_of(P);
 
 #pragma omp parallel num_threads(nth)
@@ -459,8 +461,10 @@ int orc_simulate(const orc_problem* P, int32_t s_begin, int32_t s_end,
                     x[i] = P->xs; y[i] = P->ys; z[i] = P->h; m[i] = 1.0;
                     for (int n = 0; n < P->n_nuc; ++n) my_led[n * 4 + 0] += a0;
                 }
-                if (b <= s && m[i] > 0.0)
+                if (b <= s && m[i] > 0.0) {
                     step_particle(P, gid, b, s, &x[i], &y[i], &z[i], &m[i], my_led, my_dep);
+                    cnt_t[tid] += 1;
+                }
             }
             for (int32_t k = 0; k < n_snap; ++k) {
                 if (snap_steps[k] != s) continue;
@@ -469,12 +473,16 @@ int orc_simulate(const orc_problem* P, int32_t s_begin, int32_t s_end,
             }
         }
     }
+    int64_t count = 0;
     for (int t = 0; t < nth; ++t) {
         for (size_t c = 0; c < dcells; ++c) dep[c] += dep_t[(size_t)t * dcells + c];
         for (int c = 0; c < 4 * P->n_nuc; ++c) ledger[c] += led_t[(size_t)t * 16 + c];
+        count += cnt_t[t];
     }
+    if (psteps) *psteps = count;
     free(dep_t);
     free(led_t);
+    free(cnt_t);
     return 0;
 }
 

@@ -1,0 +1,175 @@
+"""Python binding of liblpm (MI355X particle-dispersion hot path).
+
+Argument marshalling only: every step of the model runs in the HIP kernels of
+``liblpm.so``; PyTorch provides device memory and streams.  The entry points
+carry the C names without the ``lpm_`` prefix and raise ``LpmError`` on a
+negative return code.  The library must have been built in-tree
+(``python -m paper_0912_3223_amd.build``); importing this package without it
+raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # loaded first so that liblpm binds to torch's HIP runtime
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblpm.so")
+
+LPM_OK, LPM_EINVAL, LPM_ECAPACITY, LPM_EHIP, LPM_ENONFINITE = 0, -1, -2, -3, -4
+LEDGER_SLOTS = 64
+LEDGER_STRIDE = 32
+
+
+class LpmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class State(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("m", C.c_void_p),
+                ("capacity", C.c_int64)]
+
+
+class Source(C.Structure):
+    _fields_ = [("xs", C.c_double), ("ys", C.c_double), ("h", C.c_double), ("q", C.c_double),
+                ("wind_scale", C.c_double), ("v_d", C.c_double), ("scenario", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class Schedule(C.Structure):
+    _fields_ = [("n_total", C.c_int64), ("n_local", C.c_int64), ("id_base", C.c_int64),
+                ("id_stride", C.c_int64), ("s_release", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Field(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("z_levels", C.c_void_p),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nt", C.c_int32),
+                ("ncomp", C.c_int32), ("bounded", C.c_int32),
+                ("x0", C.c_double), ("y0", C.c_double), ("dx", C.c_double), ("dy", C.c_double),
+                ("dz", C.c_double), ("t0", C.c_double), ("dt_field", C.c_double)]
+
+
+class Physics(C.Structure):
+    _fields_ = [("dt", C.c_double), ("Kh", C.c_double), ("Kz_const", C.c_double),
+                ("kappa_ustar", C.c_double), ("z0", C.c_double), ("H_mix", C.c_double),
+                ("H_lid", C.c_double), ("h_s", C.c_double),
+                ("kz_kind", C.c_int32), ("n_nuc", C.c_int32), ("lam", C.c_double * 4),
+                ("Lambda0", C.c_double), ("rain_cx", C.c_double), ("rain_cy", C.c_double),
+                ("rain_a", C.c_double), ("rain_b", C.c_double), ("rain_angle", C.c_double),
+                ("rain_edge", C.c_double), ("seed", C.c_uint64)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("mode", C.c_int32),
+                ("density", C.c_int32), ("reserved", C.c_int32),
+                ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
+
+
+class Accum(C.Structure):
+    _fields_ = [("dep", C.c_void_p), ("ledger", C.c_void_p), ("err", C.c_void_p),
+                ("n_nuc", C.c_int32), ("reserved", C.c_int32), ("dep_grid", Grid)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_0912_3223_amd.build` (no CPU fallback exists)")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    sig = {
+        "lpm_accum_reset": [P(Accum), C.c_void_p],
+        "lpm_release_particles": [P(State), P(Source), P(Schedule), P(Physics), C.c_int32,
+                                  C.c_int32, P(Accum), C.c_void_p],
+        "lpm_step_particles": [P(State), P(Source), P(Schedule), P(Field), P(Physics),
+                               C.c_int32, C.c_int32, P(Accum), C.c_void_p],
+        "lpm_grid_concentration": [P(State), P(Source), P(Schedule), P(Physics), P(Grid),
+                                   C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
+        "lpm_grid_deposition": [P(Accum), C.c_void_p, C.c_void_p],
+        "lpm_read_ledger": [P(Accum), P(C.c_double), C.c_void_p],
+        "lpm_check": [P(Accum), C.c_void_p],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.lpm_last_error.restype = C.c_char_p
+    L.lpm_version.restype = C.c_char_p
+    return L
+
+
+_lib = _load()
+
+#: C entry points exported by include/lpm.h (checked by the test suite).
+EXPORTS = ("lpm_accum_reset", "lpm_release_particles", "lpm_step_particles",
+           "lpm_grid_concentration", "lpm_grid_deposition", "lpm_read_ledger", "lpm_check",
+           "lpm_last_error", "lpm_version")
+
+
+def lib():
+    return _lib
+
+
+def _rc(code):
+    if code != LPM_OK:
+        raise LpmError(code, _lib.lpm_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+# -- entry points (same names as the C ABI) ---------------------------------
+
+def accum_reset(acc: Accum, stream=None):
+    _rc(_lib.lpm_accum_reset(C.byref(acc), _stream(stream)))
+
+
+def release_particles(st: State, src: Source, sch: Schedule, ph: Physics, step0: int,
+                      n_steps: int, acc: Accum, stream=None):
+    _rc(_lib.lpm_release_particles(C.byref(st), C.byref(src), C.byref(sch), C.byref(ph),
+                                   step0, n_steps, C.byref(acc), _stream(stream)))
+
+
+def step_particles(st: State, src: Source, sch: Schedule, fld: Field, ph: Physics, step0: int,
+                   n_steps: int, acc: Accum, stream=None):
+    _rc(_lib.lpm_step_particles(C.byref(st), C.byref(src), C.byref(sch), C.byref(fld),
+                                C.byref(ph), step0, n_steps, C.byref(acc), _stream(stream)))
+
+
+def grid_concentration(st: State, src: Source, sch: Schedule, ph: Physics, grid: Grid,
+                       step: int, acc_scratch: torch.Tensor, out: torch.Tensor, stream=None):
+    assert acc_scratch.dtype == torch.float64 and out.dtype == torch.float32
+    _rc(_lib.lpm_grid_concentration(C.byref(st), C.byref(src), C.byref(sch), C.byref(ph),
+                                    C.byref(grid), step, C.c_void_p(acc_scratch.data_ptr()),
+                                    C.c_void_p(out.data_ptr()), _stream(stream)))
+
+
+def grid_deposition(acc: Accum, out: torch.Tensor, stream=None):
+    assert out.dtype == torch.float32
+    _rc(_lib.lpm_grid_deposition(C.byref(acc), C.c_void_p(out.data_ptr()), _stream(stream)))
+
+
+def read_ledger(acc: Accum, stream=None):
+    """Synchronises; returns ([n_nuc][4] released, deposited, decayed,
+    exited, particle-steps advanced)."""
+    out = (C.c_double * (4 * acc.n_nuc + 1))()
+    _rc(_lib.lpm_read_ledger(C.byref(acc), out, _stream(stream)))
+    return ([[out[n * 4 + e] for e in range(4)] for n in range(acc.n_nuc)],
+            int(out[4 * acc.n_nuc]))
+
+
+def check(acc: Accum, stream=None):
+    _rc(_lib.lpm_check(C.byref(acc), _stream(stream)))
+
+
+def version() -> str:
+    return _lib.lpm_version().decode()
+
+
+from .host import DeviceRun, make_source, make_schedule, make_physics, make_grid  # noqa: E402

@@ -1,0 +1,233 @@
+// Device-side building blocks of the particle step for gfx950 (CDNA4).
+//
+// Everything here runs per particle in registers: counter-based random
+// numbers (no random-number buffer in HBM), the wind gather, the diffusivity
+// profile and the deposition rates.  The formulas follow Sec. 2 and Eqs. 1-3
+// of Molnar Jr. et al. (arXiv:0912.3223) with the readings stated in lpm.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lpm {
+
+// Per-launch constants, precomputed in double precision on the host and
+// rounded once to float.  Passed by value, so they live in SGPRs/the kernel
+// argument segment and cost no vector registers.
+struct StepConst {
+    // particle state
+    float* X;
+    float* Y;
+    float* Z;
+    float* M;
+    // schedule
+    long long n_total, id_base, id_stride, i_hi;
+    int s_release, step0, step_end, pad0;
+    // source
+    float xs, ys, h, a0, wscale;
+    uint32_t key0, key1;
+    // wind field
+    const float* f;
+    const float* lev;
+    int nx, ny, nz, nt;
+    int imax, jmax, kmax, tmaxi;          // largest lower node index
+    float fxmax, fymax, fzmax, ftmax;     // largest fractional node index
+    float fx0, fy0, inv_dx, inv_dy, inv_dz, ft0, inv_dtf;
+    int di, dj, dk, dt_off;               // float offsets of the upper neighbours
+    int sj, sk, st, pad1;                 // float strides of j, k, t
+    int bounded;
+    float X0, X1, Y0, Y1;                 // exit box
+    // physics
+    float dt, sKh, s2dt, half_dt;
+    int kz_kind;
+    float Kz_const, ku, z0, H_mix, inv_Hmix, H_lid;
+    float dry_c1, dry_c2, h_s;            // v_d (2/h_s)(1 - z/h_s) = c1 - c2 z
+    float L0, rcx, rcy, r_ca_a, r_sa_a, r_ca_b, r_sa_b, inv_edge;
+    float lam[4];                         // decay constants
+    float lam_l2e[4];                     // lambda log2(e)
+    float cdec[4];                        // 1 - exp(-lambda dt)
+    float edec[4];                        // exp(-lambda dt)
+    // deposition grid and accumulators
+    double* dep;
+    double* ledger;
+    uint32_t* err;
+    int dnx, dny, dmode, pad2;
+    double dx0, dy0, dinv_dx, dinv_dy;
+    float dscale;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter (c0, c1, 0, 0),
+// key (k0, k1).  The two upper counter words are zero for the turbulence
+// stream, which removes one multiply from the first round.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox_10(uint32_t c0, uint32_t c1, uint32_t k0,
+                                          uint32_t k1, uint32_t r[4])
+{
+    uint32_t c2 = 0u, c3 = 0u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    r[0] = c0;
+    r[1] = c1;
+    r[2] = c2;
+    r[3] = c3;
+}
+
+// Uniform in (0, 1] on the 2^-24 lattice: exact in float.
+__device__ __forceinline__ float lattice_uniform(uint32_t r)
+{
+    return (float)((r >> 8) + 1u) * 5.9604644775390625e-08f;
+}
+
+// Three standard normals (Eq. 2) by the trigonometric Box-Muller form.
+// v_log_f32 is log2 and v_sin/v_cos take the angle in revolutions, so
+// 2 pi u needs no multiply and no range reduction.
+__device__ __forceinline__ void normals3(uint32_t id, uint32_t step, uint32_t k0,
+                                         uint32_t k1, float& xi0, float& xi1,
+                                         float& xi2)
+{
+    uint32_t r[4];
+    philox_10(id, step, k0, k1, r);
+    const float m2ln2 = -1.3862943611198906f;  // -2 ln 2
+    const float u0 = lattice_uniform(r[0]);
+    const float u1 = lattice_uniform(r[1]);
+    const float u2 = lattice_uniform(r[2]);
+    const float u3 = lattice_uniform(r[3]);
+    const float rho0 = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
+    const float rho2 = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
+    xi0 = rho0 * __builtin_amdgcn_cosf(u1);
+    xi1 = rho0 * __builtin_amdgcn_sinf(u1);
+    xi2 = rho2 * __builtin_amdgcn_cosf(u3);
+}
+
+__device__ __forceinline__ float clampf(float v, float lo, float hi)
+{
+    return fminf(fmaxf(v, lo), hi);
+}
+
+__device__ __forceinline__ float lerpf(float a, float b, float w)
+{
+    return fmaf(w, b - a, a);
+}
+
+// Lower node and weight of a coordinate on cell-centred nodes, clamped.
+__device__ __forceinline__ void axis(float pos, float origin, float inv_d, float fmax,
+                                     int imax, int& i0, float& w)
+{
+    const float fi = clampf((pos - origin) * inv_d - 0.5f, 0.0f, fmax);
+    i0 = min((int)fi, imax);
+    w = fi - (float)i0;
+}
+
+// Vertical node and weight for explicitly given node heights (binary search).
+__device__ __forceinline__ void levels(const float* __restrict__ lev, int nz, float z,
+                                       int& k0, float& w)
+{
+    if (nz == 1 || z <= lev[0]) { k0 = 0; w = 0.0f; return; }
+    if (z >= lev[nz - 1]) { k0 = nz - 2; w = 1.0f; return; }
+    int lo = 0, hi = nz - 1;  // lev[lo] <= z < lev[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (lev[mid] <= z) lo = mid; else hi = mid;
+    }
+    k0 = lo;
+    w = (z - lev[lo]) / (lev[lo + 1] - lev[lo]);
+}
+
+// Trilinear sample of one time level: (u, v[, w]) at float offset `base`.
+template <int NCOMP>
+__device__ __forceinline__ void trilinear(const float* __restrict__ f, int base, int di,
+                                          int dj, int dk, float wx, float wy, float wz,
+                                          float out[3])
+{
+    const int o[8] = {base, base + di, base + dj, base + dj + di,
+                      base + dk, base + dk + di, base + dk + dj, base + dk + dj + di};
+    float c[8][NCOMP];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        if constexpr (NCOMP == 2) {
+            const float2 v = *reinterpret_cast<const float2*>(f + o[q]);
+            c[q][0] = v.x;
+            c[q][1] = v.y;
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < NCOMP; ++cc) c[q][cc] = f[o[q] + cc];
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < NCOMP; ++cc) {
+        const float a = lerpf(c[0][cc], c[1][cc], wx);
+        const float b = lerpf(c[2][cc], c[3][cc], wx);
+        const float e = lerpf(c[4][cc], c[5][cc], wx);
+        const float g = lerpf(c[6][cc], c[7][cc], wx);
+        out[cc] = lerpf(lerpf(a, b, wy), lerpf(e, g, wy), wz);
+    }
+    if constexpr (NCOMP == 2) out[2] = 0.0f;
+}
+
+// Wind (u, v, w) at (x, y, z), time t; linear in x, y, z and t (Sec. 3.2).
+template <int NCOMP, bool TIME>
+__device__ __forceinline__ void wind(const StepConst& p, float x, float y, float z,
+                                     float t, float uvw[3])
+{
+    int i0, j0, k0;
+    float wx, wy, wz;
+    axis(x, p.fx0, p.inv_dx, p.fxmax, p.imax, i0, wx);
+    axis(y, p.fy0, p.inv_dy, p.fymax, p.jmax, j0, wy);
+    if (p.lev) levels(p.lev, p.nz, z, k0, wz);
+    else axis(z, 0.0f, p.inv_dz, p.fzmax, p.kmax, k0, wz);
+    const int base = k0 * p.sk + j0 * p.sj + i0 * NCOMP;
+    if constexpr (!TIME) {
+        trilinear<NCOMP>(p.f, base, p.di, p.dj, p.dk, wx, wy, wz, uvw);
+    } else {
+        // time nodes sit at ft0 + k dt_field (not cell-centred)
+        const float ft = clampf((t - p.ft0) * p.inv_dtf, 0.0f, p.ftmax);
+        const int t0 = min((int)ft, p.tmaxi);
+        const float wt = ft - (float)t0;
+        float a[3], b[3];
+        trilinear<NCOMP>(p.f, base + t0 * p.st, p.di, p.dj, p.dk, wx, wy, wz, a);
+        trilinear<NCOMP>(p.f, base + t0 * p.st + p.dt_off, p.di, p.dj, p.dk, wx, wy, wz, b);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) uvw[cc] = lerpf(a[cc], b[cc], wt);
+    }
+}
+
+// Vertical diffusivity and its slope (Eq. 3 with Phi = 1, or constant).
+__device__ __forceinline__ void kz_profile(const StepConst& p, float z, float& K, float& dK)
+{
+    if (p.kz_kind == 0) { K = p.Kz_const; dK = 0.0f; return; }
+    const float zc = fmaxf(z, 0.0f);
+    if (zc >= p.H_mix) { K = 0.0f; dK = 0.0f; return; }
+    const float g = fmaf(-zc, p.inv_Hmix, 1.0f);
+    const float zz = zc + p.z0;
+    if (p.kz_kind == 1) {
+        K = p.ku * zz * g;
+        dK = p.ku * fmaf(-zz, p.inv_Hmix, g);
+    } else {
+        K = p.ku * zz * g * g;
+        dK = p.ku * g * fmaf(-2.0f * zz, p.inv_Hmix, g);
+    }
+}
+
+// Wet-deposition rate in the elliptical rain region with a linear edge.
+__device__ __forceinline__ float wet_rate(const StepConst& p, float x, float y)
+{
+    const float dx = x - p.rcx, dy = y - p.rcy;
+    const float xr = fmaf(p.r_ca_a, dx, p.r_sa_a * dy);
+    const float yr = fmaf(p.r_ca_b, dy, -p.r_sa_b * dx);
+    const float re = __builtin_amdgcn_sqrtf(fmaf(xr, xr, yr * yr));
+    return p.L0 * clampf(fmaf(1.0f - re, p.inv_edge, 0.5f), 0.0f, 1.0f);
+}
+
+}  // namespace lpm

@@ -1,0 +1,148 @@
+"""Host side of a run: device buffers (torch allocations), the C structs that
+describe them, and the paper's host main loop (Sec. 3.2, Fig. 1): release and
+step the particles window by window, and grid the activity every n-th step.
+All arithmetic of the model happens in liblpm's kernels."""
+from __future__ import annotations
+
+import ctypes
+
+from typing import Callable, Iterable, Optional
+
+import numpy as np
+import torch
+
+from . import (Accum, Field, Grid, Physics, Schedule, Source, State, LEDGER_SLOTS, LEDGER_STRIDE,
+               accum_reset, grid_concentration, grid_deposition, read_ledger,
+               release_particles, step_particles, check)
+
+
+def make_source(src) -> Source:
+    return Source(src.xs, src.ys, src.h, src.q, src.wind_scale, src.v_d, src.scenario, 0)
+
+
+def make_schedule(sch) -> Schedule:
+    return Schedule(sch.n_total, sch.local_count, sch.id_base, sch.id_stride, sch.s_release, 0)
+
+
+def make_physics(ph) -> Physics:
+    lam = (ctypes.c_double * 4)(*(list(ph.lambdas) + [0.0] * (4 - ph.n_nuc)))
+    r = ph.rain
+    return Physics(ph.dt, ph.Kh, ph.Kz_const, ph.kappa_ustar, ph.z0, ph.H_mix, ph.H_lid, ph.h_s,
+                   ph.kz_kind, ph.n_nuc, lam, ph.Lambda0, r.cx, r.cy, r.a, r.b, r.angle,
+                   r.edge, ph.seed)
+
+
+def make_grid(g) -> Grid:
+    return Grid(g.nx, g.ny, g.nz, g.mode, int(g.density), 0, g.x0, g.y0, g.z0, g.dx, g.dy, g.dz)
+
+
+class DeviceRun:
+    """Device buffers and structs for one workload (a ``synth.Case``)."""
+
+    def __init__(self, case, device: str = "cuda", capacity: Optional[int] = None):
+        self.case = case
+        self.device = torch.device(device)
+        sch, ph, fld = case.schedule, case.physics, case.field
+        n = sch.local_count
+        cap = n if capacity is None else capacity
+        f32 = dict(dtype=torch.float32, device=self.device)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.x = torch.zeros(max(cap, 1), **f32)
+        self.y = torch.zeros(max(cap, 1), **f32)
+        self.z = torch.zeros(max(cap, 1), **f32)
+        self.m = torch.zeros(max(cap, 1), **f32)
+        self.st = State(self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr(),
+                        self.m.data_ptr(), cap)
+        self.field_data = torch.from_numpy(np.ascontiguousarray(fld.data)).to(self.device)
+        self.levels = None
+        if fld.z_levels is not None:
+            self.levels = torch.from_numpy(np.ascontiguousarray(fld.z_levels)).to(self.device)
+        self.fld = Field(self.field_data.data_ptr(),
+                         self.levels.data_ptr() if self.levels is not None else None,
+                         fld.nx, fld.ny, fld.nz, fld.nt, fld.ncomp, int(fld.bounded),
+                         fld.x0, fld.y0, fld.dx, fld.dy, fld.dz, fld.t0, fld.dt_field)
+        self.src = make_source(case.source)
+        self.sch = make_schedule(sch)
+        self.ph = make_physics(ph)
+        dg, cg = case.dep_grid, case.conc_grid
+        nn = ph.n_nuc
+        self.dep = torch.zeros((nn, dg.ny, dg.nx), **f64)
+        self.ledger_buf = torch.zeros((LEDGER_SLOTS, LEDGER_STRIDE, 4, 4), **f64)
+        self.err = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.acc = Accum(self.dep.data_ptr(), self.ledger_buf.data_ptr(), self.err.data_ptr(),
+                         nn, 0, make_grid(dg))
+        self.cgrid = make_grid(cg)
+        self.conc_scratch = torch.empty((nn, cg.nz, cg.ny, cg.nx), **f64)
+        self.conc = torch.empty((nn, cg.nz, cg.ny, cg.nx), **f32)
+        self.dep_out = torch.empty((nn, dg.ny, dg.nx), **f32)
+        self.reset()
+
+    # -- thin wrappers ------------------------------------------------------
+    def reset(self):
+        self.m.zero_()
+        accum_reset(self.acc)
+
+    def set_state(self, x, y, z, m):
+        for dst, src in ((self.x, x), (self.y, y), (self.z, z), (self.m, m)):
+            dst[: len(src)].copy_(torch.as_tensor(np.asarray(src, dtype=np.float32)))
+
+    def release(self, step0: int, n_steps: int = 1):
+        release_particles(self.st, self.src, self.sch, self.ph, step0, n_steps, self.acc)
+
+    def step(self, step0: int, n_steps: int = 1):
+        step_particles(self.st, self.src, self.sch, self.fld, self.ph, step0, n_steps, self.acc)
+
+    def grid_concentration(self, step: int) -> torch.Tensor:
+        grid_concentration(self.st, self.src, self.sch, self.ph, self.cgrid, step,
+                           self.conc_scratch, self.conc)
+        return self.conc
+
+    def grid_deposition(self) -> torch.Tensor:
+        grid_deposition(self.acc, self.dep_out)
+        return self.dep_out
+
+    def ledger(self) -> np.ndarray:
+        """[n_nuc][4]: released, deposited, decayed, exited (synchronises)."""
+        return np.array(read_ledger(self.acc)[0])
+
+    def particle_steps(self) -> int:
+        """Particle-steps advanced since the last reset (synchronises)."""
+        return read_ledger(self.acc)[1]
+
+    def check(self):
+        check(self.acc)
+
+    def state(self):
+        n = self.sch.n_local
+        return {k: getattr(self, k)[:n].double().cpu().numpy() for k in "xyzm"}
+
+    # -- the host main loop -------------------------------------------------
+    def windows(self, s_begin: int, s_end: int, steps_per_launch: int,
+                snap_steps: Iterable[int] = ()):
+        cuts = {s_end}
+        cuts.update(s + 1 for s in snap_steps if s_begin <= s < s_end)
+        bounds = sorted(cuts)
+        out, a = [], s_begin
+        for b in bounds:
+            while a < b:
+                e = min(b, a + steps_per_launch)
+                out.append((a, e))
+                a = e
+        return out
+
+    def run(self, s_begin: int = 0, s_end: Optional[int] = None, steps_per_launch: int = 60,
+            snap_steps: Iterable[int] = (), on_snapshot: Optional[Callable] = None,
+            release: bool = True):
+        """Release, step and grid over steps [s_begin, s_end).  After every
+        step in ``snap_steps`` the concentration is gridded and passed to
+        ``on_snapshot(step, tensor)`` (the tensor is reused)."""
+        s_end = self.case.n_steps if s_end is None else s_end
+        snaps = sorted(set(snap_steps))
+        for a, b in self.windows(s_begin, s_end, steps_per_launch, snaps):
+            if release:
+                self.release(a, b - a)
+            self.step(a, b - a)
+            if (b - 1) in snaps:
+                g = self.grid_concentration(b - 1)
+                if on_snapshot is not None:
+                    on_snapshot(b - 1, g)

@@ -1,0 +1,162 @@
+"""The C ABI: the library loads, exports every entry point that include/lpm.h
+declares, the binding's structs match the C layout, and invalid arguments are
+rejected on the host before anything reaches a device (no GPU needed)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lpm.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(lpm_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_0912_3223_amd as L
+    names = declared()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(L.lib(), n), n
+    assert set(names) == set(L.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}$", out, re.M), n
+
+
+def test_struct_layout_matches_header(tmp_path):
+    import paper_0912_3223_amd as L
+    structs = {"lpm_state": L.State, "lpm_source": L.Source, "lpm_schedule": L.Schedule,
+               "lpm_field": L.Field, "lpm_physics": L.Physics, "lpm_grid": L.Grid,
+               "lpm_accum": L.Accum}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lpm.h"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            cf = {"lam": "lambda"}.get(f, f)
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {cf}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+@pytest.fixture
+def args():
+    """Structurally valid arguments with fake (never dereferenced) device
+    pointers; each test breaks one thing."""
+    import paper_0912_3223_amd as L
+    import synth
+    case = synth.c1(n_total=1000, n_steps=10)
+    fake = 0x10000
+    st = L.State(fake, fake, fake, fake, 1000)
+    src = L.make_source(case.source)
+    sch = L.make_schedule(case.schedule)
+    ph = L.make_physics(case.physics)
+    fld = L.Field(fake, None, 200, 200, 30, 1, 2, 1, -25e3, -25e3, 250.0, 250.0, 40.0, 0.0, 3600.0)
+    acc = L.Accum(fake, fake, fake, 2, 0, L.make_grid(case.dep_grid))
+    grid = L.make_grid(case.conc_grid)
+    return L, st, src, sch, ph, fld, acc, grid
+
+
+def code(L, fn, *a):
+    return getattr(L.lib(), fn)(*[C.byref(x) if isinstance(x, C.Structure) else x for x in a])
+
+
+def test_rejects_bad_arguments(args):
+    L, st, src, sch, ph, fld, acc, grid = args
+    step = lambda *o: code(L, "lpm_step_particles", *o)
+    ok = (st, src, sch, fld, ph, 0, 1, acc, None)
+    # capacity
+    small = L.State(st.x, st.y, st.z, st.m, 999)
+    assert step(small, *ok[1:]) == L.LPM_ECAPACITY
+    assert b"capacity" in L.lib().lpm_last_error()
+    # null pointers
+    assert L.lib().lpm_step_particles(None, C.byref(src), C.byref(sch), C.byref(fld), C.byref(ph),
+                                      0, 1, C.byref(acc), None) == L.LPM_EINVAL
+    nul = L.State(0, st.y, st.z, st.m, 1000)
+    assert step(nul, *ok[1:]) == L.LPM_EINVAL
+    # misaligned state
+    mis = L.State(st.x + 2, st.y, st.z, st.m, 1000)
+    assert step(mis, *ok[1:]) == L.LPM_EINVAL
+    # bad windows
+    assert step(st, src, sch, fld, ph, -1, 1, acc, None) == L.LPM_EINVAL
+    assert step(st, src, sch, fld, ph, 0, 0, acc, None) == L.LPM_EINVAL
+    # n_nuc
+    ph5 = L.Physics.from_buffer_copy(ph)
+    ph5.n_nuc = 5
+    assert step(st, src, sch, fld, ph5, 0, 1, acc, None) == L.LPM_EINVAL
+    acc1 = L.Accum.from_buffer_copy(acc)
+    acc1.n_nuc = 1
+    assert step(st, src, sch, fld, ph, 0, 1, acc1, None) == L.LPM_EINVAL
+    # field
+    f3 = L.Field.from_buffer_copy(fld)
+    f3.ncomp = 4
+    assert step(st, src, sch, f3, ph, 0, 1, acc, None) == L.LPM_EINVAL
+    f4 = L.Field.from_buffer_copy(fld)
+    f4.dx = 0.0
+    assert step(st, src, sch, f4, ph, 0, 1, acc, None) == L.LPM_EINVAL
+    f5 = L.Field.from_buffer_copy(fld)
+    f5.data = fld.data + 4
+    assert step(st, src, sch, f5, ph, 0, 1, acc, None) == L.LPM_EINVAL  # 2-comp needs 8 B
+    # schedule
+    s2 = L.Schedule.from_buffer_copy(sch)
+    s2.id_stride = 0
+    assert step(st, src, s2, fld, ph, 0, 1, acc, None) == L.LPM_EINVAL
+    s3 = L.Schedule.from_buffer_copy(sch)
+    s3.n_total = 1 << 33
+    assert step(st, src, s3, fld, ph, 0, 1, acc, None) == L.LPM_EINVAL
+    s4 = L.Schedule.from_buffer_copy(sch)
+    s4.id_base = 5
+    assert step(st, src, s4, fld, ph, 0, 1, acc, None) == L.LPM_EINVAL  # ids beyond n_total
+    # physics
+    p2 = L.Physics.from_buffer_copy(ph)
+    p2.dt = 0.0
+    assert step(st, src, sch, fld, p2, 0, 1, acc, None) == L.LPM_EINVAL
+    p3 = L.Physics.from_buffer_copy(ph)
+    p3.kz_kind = 7
+    assert step(st, src, sch, fld, p3, 0, 1, acc, None) == L.LPM_EINVAL
+    p4 = L.Physics.from_buffer_copy(ph)
+    p4.rain_a = 0.0
+    assert step(st, src, sch, fld, p4, 0, 1, acc, None) == L.LPM_EINVAL
+    # gridding
+    g2 = L.Grid.from_buffer_copy(grid)
+    g2.mode = 3
+    assert code(L, "lpm_grid_concentration", st, src, sch, ph, g2, 0, C.c_void_p(0x10000),
+                C.c_void_p(0x10000), None) == L.LPM_EINVAL
+    assert code(L, "lpm_grid_concentration", st, src, sch, ph, grid, 0, None,
+                C.c_void_p(0x10000), None) == L.LPM_EINVAL
+    assert code(L, "lpm_grid_deposition", acc, None, None) == L.LPM_EINVAL
+    assert code(L, "lpm_release_particles", small, src, sch, ph, 0, 1, acc, None) == L.LPM_ECAPACITY
+    assert L.lib().lpm_check(None, None) == L.LPM_EINVAL
+
+
+def test_binding_raises(args):
+    L, st, src, sch, ph, fld, acc, grid = args
+    small = L.State(st.x, st.y, st.z, st.m, 10)
+    with pytest.raises(L.LpmError) as e:
+        L.step_particles(small, src, sch, fld, ph, 0, 1, acc, stream=0)
+    assert e.value.code == L.LPM_ECAPACITY
+
+
+def test_empty_window_launches_nothing(args):
+    """A window in which no local particle has been born returns OK without
+    touching the device."""
+    L, st, src, sch, ph, fld, acc, grid = args
+    empty = L.Schedule.from_buffer_copy(sch)
+    empty.n_local = 0
+    assert code(L, "lpm_step_particles", st, src, empty, fld, ph, 0, 1, acc, None) == L.LPM_OK
+    assert code(L, "lpm_release_particles", st, src, empty, ph, 0, 1, acc, None) == L.LPM_OK
