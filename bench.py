@@ -34,7 +34,7 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # 10 rounds, Box-Muller, trilinear wind, K_z at two heights, move and fold,
 # deposition rates, decay of two nuclides, FP64 ledger sums); derived in the
 # design notes.  Quarter-rate transcendentals and 32-bit multiplies count 4.
-ALG_OPS_PER_PSTEP = 300
+ALG_OPS_PER_PSTEP = 290
 HBM_PEAK = 8.0e12
 
 
@@ -43,11 +43,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--spl", type=int, default=60, help="time steps per step-kernel launch")
+    ap.add_argument("--spl", type=int, default=0,
+                    help="time steps per step-kernel launch; 0 = the whole run in one launch "
+                         "with the output-step states recorded and gridded afterwards")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=8,
                     help="oracle sample: every k-th particle id of the same workload")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run one plain device-to-device copy of this size before timing "
+                         "(reference dispatch for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -77,14 +82,31 @@ def main():
 
     case = synth.c1(n_total=a.n)
     snaps = case.output_steps()
+    assert snaps == list(range(case.out_every - 1, case.n_steps, case.out_every))
     run = L.DeviceRun(case)
     stream = torch.cuda.current_stream()
 
     # step-kernel timing: HIP events on the stream the kernels are launched on
     ev = []
 
+    rec = run.record_buffer(len(snaps)) if a.spl == 0 else None
+
     def one_run(timed):
         run.reset()
+        if a.spl == 0:
+            run.release(0, case.n_steps)
+            if timed:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            run.step_record(0, case.n_steps, snaps[0], case.out_every, len(snaps), rec)
+            if timed:
+                e1.record(stream)
+                ev.append((e0, e1))
+            for k, s in enumerate(snaps):
+                run.grid_recorded(rec, k, s)
+            run.grid_deposition()
+            return
         for s0, s1 in run.windows(0, case.n_steps, a.spl, snaps):
             run.release(s0, s1 - s0)
             if timed:
@@ -103,6 +125,13 @@ def main():
     for _ in range(a.warmup):
         one_run(False)
     torch.cuda.synchronize()
+    if a.copy_calibration_mb:
+        n = a.copy_calibration_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     psteps = run.particle_steps()
     run.check()
     ledger = run.ledger()
@@ -139,7 +168,7 @@ def main():
         "config": {"workload": "1e6-particle 6 h continuous point release, 200x200x30 steady "
                                "gridded wind, dt=5 s, 4320 steps, CIC gridding every 60 steps",
                    "particles": case.schedule.n_total, "time_steps": case.n_steps,
-                   "steps_per_launch": a.spl, "particle_steps_per_run": psteps},
+                   "steps_per_launch": a.spl or case.n_steps, "particle_steps_per_run": psteps},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                      "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK_OPS, "traffic": None,

@@ -193,6 +193,24 @@ int lpm_step_particles(const lpm_state* st, const lpm_source* src,
                        const lpm_physics* ph, int32_t step0, int32_t n_steps,
                        const lpm_accum* acc, lpm_stream stream);
 
+/* lpm_step_particles, and in addition the state of every local particle
+ * after each output step rec_step0 + k * rec_every (k = 0 .. n_rec - 1) is
+ * written to rec: device float planes x, y, z, m of record k at
+ * rec + (4 k + q) * rec_stride, q = 0..3 (m = 0 once a particle has left the
+ * area; particles not yet born at that step are not written, and gridding
+ * skips them by their birth).  With every recorded step inside one window the
+ * whole run can be a single launch in which each thread carries its particle
+ * from birth to the last step, and the concentration at each output step
+ * (Sec. 3.2: activities summed every n-th step) is gridded afterwards from the
+ * records with lpm_grid_concentration.  All recorded steps must lie in
+ * [step0, step0 + n_steps); rec_stride >= n_local.  rec is caller-owned. */
+int lpm_step_particles_record(const lpm_state* st, const lpm_source* src,
+                              const lpm_schedule* sch, const lpm_field* fld,
+                              const lpm_physics* ph, int32_t step0, int32_t n_steps,
+                              const lpm_accum* acc, int32_t rec_step0, int32_t rec_every,
+                              int32_t n_rec, float* rec, int64_t rec_stride,
+                              lpm_stream stream);
+
 /* Concentration after step `step` (time (step + 1) dt; Sec. 3.2: every n-th
  * step the activity a0 m exp(-lambda age) of each particle is summed on a
  * rectangular grid).  acc_scratch: device double [n_nuc][nz][ny][nx],

@@ -4,7 +4,7 @@ Argument marshalling only: every step of the model runs in the HIP kernels of
 ``liblpm.so``; PyTorch provides device memory and streams.  The entry points
 carry the C names without the ``lpm_`` prefix and raise ``LpmError`` on a
 negative return code.  The library must have been built in-tree
-(``python -m paper_0912_3223_amd.build``); importing this package without it
+(``python paper_0912_3223_amd/build.py``); importing this package without it
 raises ImportError -- there is no fallback.
 """
 from __future__ import annotations
@@ -77,7 +77,7 @@ class Accum(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_0912_3223_amd.build` (no CPU fallback exists)")
+                          "`python paper_0912_3223_amd/build.py` (no CPU fallback exists)")
     L = C.CDLL(LIB_PATH)
     P = C.POINTER
     sig = {
@@ -86,6 +86,9 @@ def _load():
                                   C.c_int32, P(Accum), C.c_void_p],
         "lpm_step_particles": [P(State), P(Source), P(Schedule), P(Field), P(Physics),
                                C.c_int32, C.c_int32, P(Accum), C.c_void_p],
+        "lpm_step_particles_record": [P(State), P(Source), P(Schedule), P(Field), P(Physics),
+                                      C.c_int32, C.c_int32, P(Accum), C.c_int32, C.c_int32,
+                                      C.c_int32, C.c_void_p, C.c_int64, C.c_void_p],
         "lpm_grid_concentration": [P(State), P(Source), P(Schedule), P(Physics), P(Grid),
                                    C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
         "lpm_grid_deposition": [P(Accum), C.c_void_p, C.c_void_p],
@@ -105,6 +108,7 @@ _lib = _load()
 
 #: C entry points exported by include/lpm.h (checked by the test suite).
 EXPORTS = ("lpm_accum_reset", "lpm_release_particles", "lpm_step_particles",
+           "lpm_step_particles_record",
            "lpm_grid_concentration", "lpm_grid_deposition", "lpm_read_ledger", "lpm_check",
            "lpm_last_error", "lpm_version")
 
@@ -140,6 +144,17 @@ def step_particles(st: State, src: Source, sch: Schedule, fld: Field, ph: Physic
                    n_steps: int, acc: Accum, stream=None):
     _rc(_lib.lpm_step_particles(C.byref(st), C.byref(src), C.byref(sch), C.byref(fld),
                                 C.byref(ph), step0, n_steps, C.byref(acc), _stream(stream)))
+
+
+def step_particles_record(st: State, src: Source, sch: Schedule, fld: Field, ph: Physics,
+                          step0: int, n_steps: int, acc: Accum, rec_step0: int, rec_every: int,
+                          n_rec: int, rec: torch.Tensor, rec_stride: int, stream=None):
+    assert rec.dtype == torch.float32 and rec.is_contiguous()
+    assert rec.numel() >= 4 * n_rec * rec_stride
+    _rc(_lib.lpm_step_particles_record(C.byref(st), C.byref(src), C.byref(sch), C.byref(fld),
+                                       C.byref(ph), step0, n_steps, C.byref(acc), rec_step0,
+                                       rec_every, n_rec, C.c_void_p(rec.data_ptr()), rec_stride,
+                                       _stream(stream)))
 
 
 def grid_concentration(st: State, src: Source, sch: Schedule, ph: Physics, grid: Grid,

@@ -1,6 +1,8 @@
 """Build liblpm.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_0912_3223_amd.build
+    python paper_0912_3223_amd/build.py
+
+(Run it as a script: importing the package loads the library being built.)
 """
 from __future__ import annotations
 

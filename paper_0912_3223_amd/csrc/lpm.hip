@@ -43,6 +43,16 @@ __device__ __forceinline__ long long birth(long long gid, long long s_release,
     return (gid * s_release) / n_total;
 }
 
+// exp(x) - 1 for x <= 0.  Per-step rates times dt are small (|x| < 1e-3 in
+// practice), where the Taylor series of exp to x^4/24 is exact to float
+// rounding (truncation x^5/120); larger |x| use the library expm1f.
+__device__ __forceinline__ float expm1_neg(float x)
+{
+    if (x > -0.0078125f)
+        return x * fmaf(x, fmaf(x, fmaf(x, 1.0f / 24.0f, 1.0f / 6.0f), 0.5f), 1.0f);
+    return expm1f(x);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
@@ -52,16 +62,16 @@ __device__ __forceinline__ T wave_sum(T v)
 }
 
 // ---------------------------------------------------------------------------
-// Block-private deposition histogram: an open-addressing hash table of grid
-// cells in LDS with FP64 values.  A block's particles were released together
-// and deposit into few cells, so near the source thousands of deposits per
-// step would otherwise serialise on the same global addresses.  Cells that do
-// not find a slot within kProbes probes go straight to the global grid.
+// Block-private histogram: an open-addressing hash table of grid cells in LDS
+// with FP64 values.  A block's particles were released together and land in
+// few cells, so near the source thousands of contributions per step would
+// otherwise serialise on the same global addresses.  Cells that do not find a
+// slot within kProbes probes go straight to the global grid.
 // ---------------------------------------------------------------------------
-template <int NNUC>
-struct DepTable {
-    static constexpr int kSlots = NNUC <= 2 ? 1024 : 512;
-    static constexpr int kShift = NNUC <= 2 ? 22 : 23;  // 32 - log2(kSlots)
+template <int NNUC, int LOG2_SLOTS>
+struct CellTable {
+    static constexpr int kSlots = 1 << LOG2_SLOTS;
+    static constexpr int kShift = 32 - LOG2_SLOTS;
     static constexpr int kProbes = 8;
     int* key;      // [kSlots]: 0 = empty, else cell + 1
     double* val;   // [NNUC][kSlots]
@@ -111,6 +121,9 @@ struct DepTable {
 // cell) or above one cell quad (cloud-in-cell): partial sums of the corner
 // weights times the deposited activity, flushed to the block table when the
 // cell changes and at the end of the window.
+template <int NNUC>
+using DepTable = CellTable<NNUC, NNUC <= 2 ? 10 : 9>;
+
 template <int NNUC>
 struct Dwell {
     int i0 = INT_MIN, j0 = 0;
@@ -173,15 +186,14 @@ struct Dwell {
 // ---------------------------------------------------------------------------
 // The particle step (Sec. 3.2 main loop; Eqs. 1-3).
 // ---------------------------------------------------------------------------
-template <int NCOMP, bool TIME, int NNUC>
+template <int NCOMP, bool TIME, bool LEVELS, int NNUC, int KZ, bool DEP>
 __global__ __launch_bounds__(kBlock) void step_kernel(const StepConst p)
 {
     __shared__ int tab_key[DepTable<NNUC>::kSlots];
     __shared__ double tab_val[NNUC * DepTable<NNUC>::kSlots];
     DepTable<NNUC> tab{tab_key, tab_val};
     const long long plane = (long long)p.dnx * p.dny;
-    const bool depositing = p.dry_c1 > 0.0f || p.L0 > 0.0f;
-    if (depositing) tab.init();
+    if constexpr (DEP) tab.init();
     __syncthreads();
 
     const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -193,63 +205,80 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepConst p)
         const long long gid = p.id_base + i * p.id_stride;
         const long long b = birth(gid, p.s_release, p.n_total);
         float m = p.M[i];
+        const int s0 = b > p.step0 ? (int)b : p.step0;
+        // next recorded step at or after the particle's first step here
+        int krec = s0 <= p.rec_step0 ? 0 : (s0 - p.rec_step0 + p.rec_every - 1) / p.rec_every;
+        int next_rec = krec < p.n_rec ? p.rec_step0 + krec * p.rec_every : INT_MAX;
         if (m > 0.0f && b < p.step_end) {
             float x = p.X[i], y = p.Y[i], z = p.Z[i];
-            const int s0 = b > p.step0 ? (int)b : p.step0;
             bool bad = false;
             int advanced = 0;
             Dwell<NNUC> dw;
             for (int s = s0; s < p.step_end; ++s) {
                 ++advanced;
                 const float age = (float)(s - (int)b) * p.dt;
+                // weather at the start-of-step position and time (Eq. 1): the
+                // loads are issued first; everything up to the interpolation
+                // below is independent of them
+                WindTap<NCOMP, TIME> tap;
+                wind_gather<NCOMP, TIME, LEVELS>(p, x, y, z, (float)s * p.dt, tap);
                 // random numbers of Eq. (2)
                 float xi0, xi1, xi2;
                 normals3((uint32_t)gid, (uint32_t)s, p.key0, p.key1, xi0, xi1, xi2);
-                // weather at the start-of-step position and time (Eq. 1)
-                float uvw[3];
-                wind<NCOMP, TIME>(p, x, y, z, (float)s * p.dt, uvw);
                 // diffusivity (Eq. 3) with the drift and midpoint evaluation
                 float K, dK, Km, dKm;
-                kz_profile(p, z, K, dK);
+                kz_profile<KZ>(p, z, K, dK);
                 const float zm = clampf(fmaf(p.half_dt, dK, z), 0.0f, p.H_mix);
-                kz_profile(p, zm, Km, dKm);
+                kz_profile<KZ>(p, zm, Km, dKm);
+                // decay factors of this step's start
+                float D[NNUC];
+#pragma unroll
+                for (int n = 0; n < NNUC; ++n) D[n] = exp2f(-p.lam_l2e[n] * age);
+                float uvw[3];
+                wind_interp<NCOMP, TIME>(tap, uvw);
                 // move (Eq. 1 with Eq. 2)
                 float xn = fmaf(xi0, p.sKh, fmaf(p.wscale * uvw[0], p.dt, x));
                 float yn = fmaf(xi1, p.sKh, fmaf(p.wscale * uvw[1], p.dt, y));
                 float zn = fmaf(xi2 * __builtin_amdgcn_sqrtf(Km), p.s2dt,
                                 fmaf(fmaf(p.wscale, uvw[2], dK), p.dt, z));
-                // reflection at the ground and the lid (fold until inside)
+                // reflection at the ground and the lid: one fold each, and the
+                // general fold-until-inside for the (never seen) larger steps
+                zn = fabsf(zn);
+                if (zn > p.H_top) zn = 2.0f * p.H_top - zn;
+                if (zn < 0.0f || zn > p.H_top) {
 #pragma unroll 1
-                for (int it = 0; it < 64; ++it) {
-                    if (zn < 0.0f) zn = -zn;
-                    else if (p.H_lid > 0.0f && zn > p.H_lid) zn = 2.0f * p.H_lid - zn;
-                    else break;
+                    for (int it = 0; it < 64; ++it) {
+                        if (zn < 0.0f) zn = -zn;
+                        else if (zn > p.H_top) zn = 2.0f * p.H_top - zn;
+                        else break;
+                    }
                 }
                 // deposition rate at the new position (Sec. 2)
                 float k = 0.0f;
-                if (p.dry_c1 > 0.0f && zn < p.h_s) k = fmaxf(fmaf(-p.dry_c2, zn, p.dry_c1), 0.0f);
-                if (p.L0 > 0.0f) k += wet_rate(p, xn, yn);
-                const float mn = m * exp2f(-1.4426950408889634f * k * p.dt);
+                if constexpr (DEP) {
+                    if (zn < p.h_s) k = fmaxf(fmaf(-p.dry_c2, zn, p.dry_c1), 0.0f);
+                    if (p.L0 > 0.0f) k += wet_rate(p, xn, yn);
+                }
+                const float mn = k > 0.0f ? m * exp2f(-1.4426950408889634f * k * p.dt) : m;
                 // decay and deposition of each nuclide's activity this step
                 float dsum[NNUC];
-                float D[NNUC];
 #pragma unroll
                 for (int n = 0; n < NNUC; ++n) {
-                    D[n] = exp2f(-p.lam_l2e[n] * age);
                     const float A = p.a0 * m * D[n];
-                    if (k > 0.0f) {
+                    if (DEP && k > 0.0f) {
+                        // loss of activity this step, split by the rates
                         const float r = p.lam[n] + k;
-                        const float loss = -A * expm1f(-r * p.dt);
-                        const float dep = loss * (k / r);
+                        const float loss = -A * expm1_neg(-r * p.dt);
+                        const float dep = loss * (k * __builtin_amdgcn_rcpf(r));
                         dsum[n] = dep * p.dscale;
                         led[3 * n + 0] += (double)dep;
-                        led[3 * n + 1] += (double)(loss * (p.lam[n] / r));
+                        led[3 * n + 1] += (double)(loss - dep);
                     } else {
                         dsum[n] = 0.0f;
                         led[3 * n + 1] += (double)(A * p.cdec[n]);
                     }
                 }
-                if (k > 0.0f) dw.add(p, tab, plane, xn, yn, dsum);
+                if (DEP && k > 0.0f) dw.add(p, tab, plane, xn, yn, dsum);
                 x = xn;
                 y = yn;
                 z = zn;
@@ -260,15 +289,26 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepConst p)
                     break;
                 }
                 // leaving the simulated area inactivates the particle
-                if (p.bounded && (x < p.X0 || x >= p.X1 || y < p.Y0 || y >= p.Y1)) {
+                const bool gone = p.bounded && (x < p.X0 || x >= p.X1 || y < p.Y0 || y >= p.Y1);
+                if (gone) {
 #pragma unroll
                     for (int n = 0; n < NNUC; ++n)
                         led[3 * n + 2] += (double)(p.a0 * m * D[n] * p.edec[n]);
                     m = 0.0f;
-                    break;
                 }
+                // state after an output step, for gridding later
+                if (s == next_rec) {
+                    float* r = p.rec + 4ll * krec * p.rec_stride + i;
+                    r[0] = x;
+                    r[p.rec_stride] = y;
+                    r[2 * p.rec_stride] = z;
+                    r[3 * p.rec_stride] = m;
+                    ++krec;
+                    next_rec = krec < p.n_rec ? p.rec_step0 + krec * p.rec_every : INT_MAX;
+                }
+                if (gone) break;
             }
-            dw.flush(p, tab, plane);
+            if constexpr (DEP) dw.flush(p, tab, plane);
             p.X[i] = x;
             p.Y[i] = y;
             p.Z[i] = z;
@@ -276,6 +316,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepConst p)
             led[3 * NNUC] = (double)advanced;
             if (bad) atomicOr(p.err, 1u);
         }
+        // records after the particle stopped (or of a particle already
+        // inactive): no activity
+        for (; krec < p.n_rec; ++krec) p.rec[(4ll * krec + 3) * p.rec_stride + i] = 0.0f;
     }
     // ledger slot: [nuclide][released, deposited, decayed, exited], steps
     double* slot = p.ledger + (long long)(blockIdx.x % LPM_LEDGER_SLOTS) * LPM_LEDGER_STRIDE;
@@ -296,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepConst p)
         const int off = q == 3 * NNUC ? LPM_LEDGER_PSTEPS : (q / 3) * 4 + 1 + q % 3;
         if (s != 0.0) atomicAdd(slot + off, s);
     }
-    if (depositing) tab.flush(p.dep, plane);
+    if constexpr (DEP) tab.flush(p.dep, plane);
 }
 
 // ---------------------------------------------------------------------------
@@ -336,50 +379,55 @@ struct GridConst {
     double* acc;
 };
 
+template <int NNUC>
 __global__ __launch_bounds__(kBlock) void conc_kernel(const GridConst g)
 {
+    using Table = CellTable<NNUC, NNUC <= 2 ? 11 : 10>;
+    __shared__ int tab_key[Table::kSlots];
+    __shared__ double tab_val[NNUC * Table::kSlots];
+    Table tab{tab_key, tab_val};
+    tab.init();
+    __syncthreads();
     const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= g.i_hi) return;
-    const float m = g.M[i];
-    if (!(m > 0.0f)) return;
-    const long long gid = g.id_base + i * g.id_stride;
-    const long long b = birth(gid, g.s_release, g.n_total);
-    if (b > g.step) return;
-    const float age = (float)(g.step + 1 - (int)b) * g.dt;
-    float A[4];
-    for (int n = 0; n < g.nnuc; ++n) A[n] = g.a0 * m * exp2f(-g.lam_l2e[n] * age) * g.scale;
-    // cell index and weights in double precision (see deposit())
-    const double fx = ((double)g.X[i] - g.x0) * g.inv_dx;
-    const double fy = ((double)g.Y[i] - g.y0) * g.inv_dy;
-    const double fz = ((double)g.Z[i] - g.z0) * g.inv_dz;
-    if (g.mode == 0) {
-        const double ix = floor(fx), iy = floor(fy), iz = floor(fz);
-        if (!(ix >= 0.0 && iy >= 0.0 && iz >= 0.0 && ix < (double)g.nx && iy < (double)g.ny &&
-              iz < (double)g.nz))  // also rejects NaN
-            return;
-        const long long c = ((long long)iz * g.ny + (long long)iy) * g.nx + (long long)ix;
-        for (int n = 0; n < g.nnuc; ++n) atomicAdd(g.acc + n * g.cells + c, (double)A[n]);
-        return;
-    }
-    const double ix = floor(fx - 0.5), iy = floor(fy - 0.5), iz = floor(fz - 0.5);
-    const double wx = fx - 0.5 - ix, wy = fy - 0.5 - iy, wz = fz - 0.5 - iz;
-    for (int c3 = 0; c3 < 2; ++c3) {
-        const double kz = iz + (double)c3;
-        if (!(kz >= 0.0 && kz < (double)g.nz)) continue;  // also skips NaN
-        const double vz = c3 ? wz : 1.0 - wz;
-        for (int b2 = 0; b2 < 2; ++b2) {
-            const double ky = iy + (double)b2;
-            if (!(ky >= 0.0 && ky < (double)g.ny)) continue;
-            const double vy = b2 ? wy : 1.0 - wy;
-            for (int a2 = 0; a2 < 2; ++a2) {
-                const double kx = ix + (double)a2;
-                if (!(kx >= 0.0 && kx < (double)g.nx)) continue;
-                const double w = (a2 ? wx : 1.0 - wx) * vy * vz;
-                const long long c = ((long long)kz * g.ny + (long long)ky) * g.nx + (long long)kx;
-                for (int n = 0; n < g.nnuc; ++n) atomicAdd(g.acc + n * g.cells + c, (double)A[n] * w);
+    const float m = i < g.i_hi ? g.M[i] : 0.0f;
+    long long b = 0;
+    if (m > 0.0f) b = birth(g.id_base + i * g.id_stride, g.s_release, g.n_total);
+    if (m > 0.0f && b <= g.step) {
+        const float age = (float)(g.step + 1 - (int)b) * g.dt;
+        float A[NNUC];
+#pragma unroll
+        for (int n = 0; n < NNUC; ++n) A[n] = g.a0 * m * exp2f(-g.lam_l2e[n] * age) * g.scale;
+        // cell index and weights in double precision (see Dwell::add)
+        const double fx = ((double)g.X[i] - g.x0) * g.inv_dx;
+        const double fy = ((double)g.Y[i] - g.y0) * g.inv_dy;
+        const double fz = ((double)g.Z[i] - g.z0) * g.inv_dz;
+        if (g.mode == 0) {
+            const double ix = floor(fx), iy = floor(fy), iz = floor(fz);
+            if (ix >= 0.0 && iy >= 0.0 && iz >= 0.0 && ix < (double)g.nx && iy < (double)g.ny &&
+                iz < (double)g.nz)  // false for NaN
+                tab.add((int)(((long long)iz * g.ny + (long long)iy) * g.nx + (long long)ix), A,
+                        g.acc, g.cells);
+        } else {
+            const double ix = floor(fx - 0.5), iy = floor(fy - 0.5), iz = floor(fz - 0.5);
+            const float wx = (float)(fx - 0.5 - ix), wy = (float)(fy - 0.5 - iy);
+            const float wz = (float)(fz - 0.5 - iz);
+            for (int c = 0; c < 8; ++c) {
+                const double kx = ix + (c & 1), ky = iy + ((c >> 1) & 1), kz = iz + (c >> 2);
+                if (!(kx >= 0.0 && ky >= 0.0 && kz >= 0.0 && kx < (double)g.nx &&
+                      ky < (double)g.ny && kz < (double)g.nz))  // also skips NaN
+                    continue;
+                const float w = ((c & 1) ? wx : 1.0f - wx) * (((c >> 1) & 1) ? wy : 1.0f - wy) *
+                                ((c >> 2) ? wz : 1.0f - wz);
+                float v[NNUC];
+#pragma unroll
+                for (int n = 0; n < NNUC; ++n) v[n] = A[n] * w;
+                tab.add((int)(((long long)kz * g.ny + (long long)ky) * g.nx + (long long)kx), v,
+                        g.acc, g.cells);
             }
         }
     }
+    __syncthreads();
+    tab.flush(g.acc, g.cells);
 }
 
 __global__ __launch_bounds__(kBlock) void fill_f64(double* p, long long n)
@@ -488,7 +536,7 @@ int check_grid(const lpm_grid* g, bool two_d)
         return fail(LPM_EINVAL, "grid spacings must be positive");
     if (g->mode != 0 && g->mode != 1) return fail(LPM_EINVAL, "grid mode must be 0 or 1");
     const double cells = (double)g->nx * g->ny * (two_d ? 1 : g->nz);
-    if (cells * 4 > 9.0e18) return fail(LPM_EINVAL, "grid too large");
+    if (cells >= 2147483647.0) return fail(LPM_EINVAL, "grid must have fewer than 2^31 - 1 cells");
     return LPM_OK;
 }
 
@@ -601,24 +649,52 @@ int fill_field(lpm::StepConst& p, const lpm_field* f)
     return LPM_OK;
 }
 
-template <int NCOMP, bool TIME>
-void launch_step_n(int nnuc, unsigned nb, hipStream_t s, const lpm::StepConst& p)
+// Compile-time variants: wind components, time interpolation, nonuniform
+// levels, nuclide count, K_z kind, deposition on/off.
+template <int NCOMP, bool TIME, bool LEV, int NNUC, int KZ>
+void launch_step_dep(bool dep, unsigned nb, hipStream_t s, const lpm::StepConst& p)
+{
+    if (dep) hipLaunchKernelGGL((lpm::step_kernel<NCOMP, TIME, LEV, NNUC, KZ, true>), dim3(nb), dim3(lpm::kBlock), 0, s, p);
+    else hipLaunchKernelGGL((lpm::step_kernel<NCOMP, TIME, LEV, NNUC, KZ, false>), dim3(nb), dim3(lpm::kBlock), 0, s, p);
+}
+
+template <int NCOMP, bool TIME, bool LEV, int NNUC>
+void launch_step_kz(int kz, bool dep, unsigned nb, hipStream_t s, const lpm::StepConst& p)
+{
+    switch (kz) {
+    case 0: launch_step_dep<NCOMP, TIME, LEV, NNUC, 0>(dep, nb, s, p); break;
+    case 1: launch_step_dep<NCOMP, TIME, LEV, NNUC, 1>(dep, nb, s, p); break;
+    default: launch_step_dep<NCOMP, TIME, LEV, NNUC, 2>(dep, nb, s, p); break;
+    }
+}
+
+template <int NCOMP, bool TIME, bool LEV>
+void launch_step_n(int nnuc, int kz, bool dep, unsigned nb, hipStream_t s, const lpm::StepConst& p)
 {
     switch (nnuc) {
-    case 1: hipLaunchKernelGGL((lpm::step_kernel<NCOMP, TIME, 1>), dim3(nb), dim3(lpm::kBlock), 0, s, p); break;
-    case 2: hipLaunchKernelGGL((lpm::step_kernel<NCOMP, TIME, 2>), dim3(nb), dim3(lpm::kBlock), 0, s, p); break;
-    case 3: hipLaunchKernelGGL((lpm::step_kernel<NCOMP, TIME, 3>), dim3(nb), dim3(lpm::kBlock), 0, s, p); break;
-    default: hipLaunchKernelGGL((lpm::step_kernel<NCOMP, TIME, 4>), dim3(nb), dim3(lpm::kBlock), 0, s, p); break;
+    case 1: launch_step_kz<NCOMP, TIME, LEV, 1>(kz, dep, nb, s, p); break;
+    case 2: launch_step_kz<NCOMP, TIME, LEV, 2>(kz, dep, nb, s, p); break;
+    case 3: launch_step_kz<NCOMP, TIME, LEV, 3>(kz, dep, nb, s, p); break;
+    default: launch_step_kz<NCOMP, TIME, LEV, 4>(kz, dep, nb, s, p); break;
     }
+}
+
+template <int NCOMP, bool TIME>
+void launch_step_lev(bool lev, int nnuc, int kz, bool dep, unsigned nb, hipStream_t s,
+                     const lpm::StepConst& p)
+{
+    if (lev) launch_step_n<NCOMP, TIME, true>(nnuc, kz, dep, nb, s, p);
+    else launch_step_n<NCOMP, TIME, false>(nnuc, kz, dep, nb, s, p);
 }
 
 }  // namespace
 
 extern "C" {
 
-int lpm_step_particles(const lpm_state* st, const lpm_source* src, const lpm_schedule* sch,
-                       const lpm_field* fld, const lpm_physics* ph, int32_t step0,
-                       int32_t n_steps, const lpm_accum* acc, lpm_stream stream)
+static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_schedule* sch,
+                     const lpm_field* fld, const lpm_physics* ph, int32_t step0, int32_t n_steps,
+                     const lpm_accum* acc, int32_t rec_step0, int32_t rec_every, int32_t n_rec,
+                     float* rec, int64_t rec_stride, lpm_stream stream)
 {
     g_msg[0] = 0;
     int rc = check_state(st, sch);
@@ -628,9 +704,23 @@ int lpm_step_particles(const lpm_state* st, const lpm_source* src, const lpm_sch
     if (acc->n_nuc != ph->n_nuc) return fail(LPM_EINVAL, "accumulator and physics n_nuc differ");
     if (step0 < 0 || n_steps < 1 || (long long)step0 + n_steps > 0x7FFFFFFFll)
         return fail(LPM_EINVAL, "bad step window");
+    if (n_rec < 0) return fail(LPM_EINVAL, "n_rec must be >= 0");
+    if (n_rec > 0) {
+        if (!rec || !aligned4(rec)) return fail(LPM_EINVAL, "null or misaligned record buffer");
+        if (rec_every < 1) return fail(LPM_EINVAL, "rec_every must be >= 1");
+        if (rec_stride < sch->n_local) return fail(LPM_EINVAL, "rec_stride below n_local");
+        const long long last = (long long)rec_step0 + (long long)(n_rec - 1) * rec_every;
+        if (rec_step0 < step0 || last >= (long long)step0 + n_steps)
+            return fail(LPM_EINVAL, "recorded steps must lie inside the step window");
+    }
     lpm::StepConst p;
     memset(&p, 0, sizeof p);
     if ((rc = fill_field(p, fld))) return rc;
+    p.rec = n_rec > 0 ? rec : nullptr;
+    p.rec_stride = rec_stride;
+    p.rec_step0 = rec_step0;
+    p.rec_every = rec_every > 0 ? rec_every : 1;
+    p.n_rec = n_rec;
 
     p.X = st->x; p.Y = st->y; p.Z = st->z; p.M = st->m;
     p.n_total = sch->n_total; p.id_base = sch->id_base; p.id_stride = sch->id_stride;
@@ -656,7 +746,7 @@ int lpm_step_particles(const lpm_state* st, const lpm_source* src, const lpm_sch
     p.z0 = (float)ph->z0;
     p.H_mix = (float)ph->H_mix;
     p.inv_Hmix = ph->H_mix > 0 ? (float)(1.0 / ph->H_mix) : 0.0f;
-    p.H_lid = (float)ph->H_lid;
+    p.H_top = ph->H_lid > 0.0 ? (float)ph->H_lid : INFINITY;
     if (src->v_d > 0.0 && ph->h_s > 0.0) {
         p.dry_c1 = (float)(2.0 * src->v_d / ph->h_s);
         p.dry_c2 = (float)(2.0 * src->v_d / (ph->h_s * ph->h_s));
@@ -688,14 +778,34 @@ int lpm_step_particles(const lpm_state* st, const lpm_source* src, const lpm_sch
     const unsigned nb = blocks_for(p.i_hi);
     hipStream_t s = (hipStream_t)stream;
     const bool time = fld->nt > 1;
+    const bool dep = p.dry_c1 > 0.0f || p.L0 > 0.0f;
+    const int kz = ph->kz_kind;
+    const bool lev = fld->z_levels != nullptr;
     if (fld->ncomp == 2) {
-        if (time) launch_step_n<2, true>(ph->n_nuc, nb, s, p);
-        else launch_step_n<2, false>(ph->n_nuc, nb, s, p);
+        if (time) launch_step_lev<2, true>(lev, ph->n_nuc, kz, dep, nb, s, p);
+        else launch_step_lev<2, false>(lev, ph->n_nuc, kz, dep, nb, s, p);
     } else {
-        if (time) launch_step_n<3, true>(ph->n_nuc, nb, s, p);
-        else launch_step_n<3, false>(ph->n_nuc, nb, s, p);
+        if (time) launch_step_lev<3, true>(lev, ph->n_nuc, kz, dep, nb, s, p);
+        else launch_step_lev<3, false>(lev, ph->n_nuc, kz, dep, nb, s, p);
     }
     return hip_status("lpm_step_particles");
+}
+
+int lpm_step_particles(const lpm_state* st, const lpm_source* src, const lpm_schedule* sch,
+                       const lpm_field* fld, const lpm_physics* ph, int32_t step0,
+                       int32_t n_steps, const lpm_accum* acc, lpm_stream stream)
+{
+    return step_impl(st, src, sch, fld, ph, step0, n_steps, acc, 0, 1, 0, nullptr, 0, stream);
+}
+
+int lpm_step_particles_record(const lpm_state* st, const lpm_source* src,
+                              const lpm_schedule* sch, const lpm_field* fld,
+                              const lpm_physics* ph, int32_t step0, int32_t n_steps,
+                              const lpm_accum* acc, int32_t rec_step0, int32_t rec_every,
+                              int32_t n_rec, float* rec, int64_t rec_stride, lpm_stream stream)
+{
+    return step_impl(st, src, sch, fld, ph, step0, n_steps, acc, rec_step0, rec_every, n_rec, rec,
+                     rec_stride, stream);
 }
 
 int lpm_grid_concentration(const lpm_state* st, const lpm_source* src, const lpm_schedule* sch,
@@ -733,8 +843,15 @@ int lpm_grid_concentration(const lpm_state* st, const lpm_source* src, const lpm
     hipStream_t s = (hipStream_t)stream;
     const unsigned fb = blocks_for(total) < 8192 ? blocks_for(total) : 8192;
     hipLaunchKernelGGL(lpm::fill_f64, dim3(fb), dim3(lpm::kBlock), 0, s, acc_scratch, total);
-    if (g.i_hi > 0)
-        hipLaunchKernelGGL(lpm::conc_kernel, dim3(blocks_for(g.i_hi)), dim3(lpm::kBlock), 0, s, g);
+    if (g.i_hi > 0) {
+        const dim3 nb(blocks_for(g.i_hi)), bs(lpm::kBlock);
+        switch (ph->n_nuc) {
+        case 1: hipLaunchKernelGGL(lpm::conc_kernel<1>, nb, bs, 0, s, g); break;
+        case 2: hipLaunchKernelGGL(lpm::conc_kernel<2>, nb, bs, 0, s, g); break;
+        case 3: hipLaunchKernelGGL(lpm::conc_kernel<3>, nb, bs, 0, s, g); break;
+        default: hipLaunchKernelGGL(lpm::conc_kernel<4>, nb, bs, 0, s, g); break;
+        }
+    }
     hipLaunchKernelGGL(lpm::to_f32, dim3(fb), dim3(lpm::kBlock), 0, s, acc_scratch, out, total,
                        1.0 / vol);
     return hip_status("lpm_grid_concentration");

@@ -40,13 +40,17 @@ struct StepConst {
     // physics
     float dt, sKh, s2dt, half_dt;
     int kz_kind;
-    float Kz_const, ku, z0, H_mix, inv_Hmix, H_lid;
+    float Kz_const, ku, z0, H_mix, inv_Hmix, H_top;  // H_top: lid, or +inf
     float dry_c1, dry_c2, h_s;            // v_d (2/h_s)(1 - z/h_s) = c1 - c2 z
     float L0, rcx, rcy, r_ca_a, r_sa_a, r_ca_b, r_sa_b, inv_edge;
     float lam[4];                         // decay constants
     float lam_l2e[4];                     // lambda log2(e)
     float cdec[4];                        // 1 - exp(-lambda dt)
     float edec[4];                        // exp(-lambda dt)
+    // recorded states: plane q (x, y, z, m) of record k at rec + (4 k + q) rec_stride
+    float* rec;
+    long long rec_stride;
+    int rec_step0, rec_every, n_rec, pad3;
     // deposition grid and accumulators
     double* dep;
     double* ledger;
@@ -77,6 +81,10 @@ __device__ __forceinline__ void philox_10(uint32_t c0, uint32_t c1, uint32_t k0,
         c2 = n2;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
+        // Keep the key schedule as two scalar registers updated per round:
+        // hoisting all twenty round keys out of the particle loop would
+        // exhaust the SGPRs and spill them to VGPR lanes.
+        asm volatile("" : "+s"(k0), "+s"(k1));
     }
     r[0] = c0;
     r[1] = c1;
@@ -145,15 +153,23 @@ __device__ __forceinline__ void levels(const float* __restrict__ lev, int nz, fl
     w = (z - lev[lo]) / (lev[lo + 1] - lev[lo]);
 }
 
-// Trilinear sample of one time level: (u, v[, w]) at float offset `base`.
+// Wind stencil of one particle: the corner values of the trilinear cell at
+// one or two field times, and the interpolation weights.  Gathering (issuing
+// the loads) and interpolating are separate so that the random numbers and
+// the diffusivity, which do not depend on the wind, are computed while the
+// loads are in flight.
+template <int NCOMP, bool TIME>
+struct WindTap {
+    float c[TIME ? 2 : 1][8][NCOMP];
+    float wx, wy, wz, wt;
+};
+
 template <int NCOMP>
-__device__ __forceinline__ void trilinear(const float* __restrict__ f, int base, int di,
-                                          int dj, int dk, float wx, float wy, float wz,
-                                          float out[3])
+__device__ __forceinline__ void gather8(const float* __restrict__ f, int base, int di, int dj,
+                                        int dk, float (&c)[8][NCOMP])
 {
     const int o[8] = {base, base + di, base + dj, base + dj + di,
                       base + dk, base + dk + di, base + dk + dj, base + dk + dj + di};
-    float c[8][NCOMP];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         if constexpr (NCOMP == 2) {
@@ -165,6 +181,12 @@ __device__ __forceinline__ void trilinear(const float* __restrict__ f, int base,
             for (int cc = 0; cc < NCOMP; ++cc) c[q][cc] = f[o[q] + cc];
         }
     }
+}
+
+template <int NCOMP>
+__device__ __forceinline__ void trilinear(const float (&c)[8][NCOMP], float wx, float wy,
+                                          float wz, float out[3])
+{
 #pragma unroll
     for (int cc = 0; cc < NCOMP; ++cc) {
         const float a = lerpf(c[0][cc], c[1][cc], wx);
@@ -176,47 +198,64 @@ __device__ __forceinline__ void trilinear(const float* __restrict__ f, int base,
     if constexpr (NCOMP == 2) out[2] = 0.0f;
 }
 
-// Wind (u, v, w) at (x, y, z), time t; linear in x, y, z and t (Sec. 3.2).
-template <int NCOMP, bool TIME>
-__device__ __forceinline__ void wind(const StepConst& p, float x, float y, float z,
-                                     float t, float uvw[3])
+// Issue the loads of the wind stencil at (x, y, z), time t (Sec. 3.2: linear
+// in x, y, z and t).
+template <int NCOMP, bool TIME, bool LEVELS>
+__device__ __forceinline__ void wind_gather(const StepConst& p, float x, float y, float z,
+                                            float t, WindTap<NCOMP, TIME>& w)
 {
     int i0, j0, k0;
-    float wx, wy, wz;
-    axis(x, p.fx0, p.inv_dx, p.fxmax, p.imax, i0, wx);
-    axis(y, p.fy0, p.inv_dy, p.fymax, p.jmax, j0, wy);
-    if (p.lev) levels(p.lev, p.nz, z, k0, wz);
-    else axis(z, 0.0f, p.inv_dz, p.fzmax, p.kmax, k0, wz);
-    const int base = k0 * p.sk + j0 * p.sj + i0 * NCOMP;
-    if constexpr (!TIME) {
-        trilinear<NCOMP>(p.f, base, p.di, p.dj, p.dk, wx, wy, wz, uvw);
-    } else {
+    axis(x, p.fx0, p.inv_dx, p.fxmax, p.imax, i0, w.wx);
+    axis(y, p.fy0, p.inv_dy, p.fymax, p.jmax, j0, w.wy);
+    if constexpr (LEVELS) levels(p.lev, p.nz, z, k0, w.wz);
+    else axis(z, 0.0f, p.inv_dz, p.fzmax, p.kmax, k0, w.wz);
+    int base = k0 * p.sk + j0 * p.sj + i0 * NCOMP;
+    if constexpr (TIME) {
         // time nodes sit at ft0 + k dt_field (not cell-centred)
         const float ft = clampf((t - p.ft0) * p.inv_dtf, 0.0f, p.ftmax);
         const int t0 = min((int)ft, p.tmaxi);
-        const float wt = ft - (float)t0;
-        float a[3], b[3];
-        trilinear<NCOMP>(p.f, base + t0 * p.st, p.di, p.dj, p.dk, wx, wy, wz, a);
-        trilinear<NCOMP>(p.f, base + t0 * p.st + p.dt_off, p.di, p.dj, p.dk, wx, wy, wz, b);
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) uvw[cc] = lerpf(a[cc], b[cc], wt);
+        w.wt = ft - (float)t0;
+        base += t0 * p.st;
+        gather8<NCOMP>(p.f, base, p.di, p.dj, p.dk, w.c[0]);
+        gather8<NCOMP>(p.f, base + p.dt_off, p.di, p.dj, p.dk, w.c[1]);
+    } else {
+        w.wt = 0.0f;
+        gather8<NCOMP>(p.f, base, p.di, p.dj, p.dk, w.c[0]);
     }
 }
 
-// Vertical diffusivity and its slope (Eq. 3 with Phi = 1, or constant).
+template <int NCOMP, bool TIME>
+__device__ __forceinline__ void wind_interp(const WindTap<NCOMP, TIME>& w, float uvw[3])
+{
+    trilinear<NCOMP>(w.c[0], w.wx, w.wy, w.wz, uvw);
+    if constexpr (TIME) {
+        float b[3];
+        trilinear<NCOMP>(w.c[1], w.wx, w.wy, w.wz, b);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) uvw[cc] = lerpf(uvw[cc], b[cc], w.wt);
+    }
+}
+
+// Vertical diffusivity and its slope (Eq. 3 with Phi = 1, or constant);
+// KZ is the profile kind (0 constant, 1 parabolic, 2 Eq. 3 exponent).
+template <int KZ>
 __device__ __forceinline__ void kz_profile(const StepConst& p, float z, float& K, float& dK)
 {
-    if (p.kz_kind == 0) { K = p.Kz_const; dK = 0.0f; return; }
-    const float zc = fmaxf(z, 0.0f);
-    if (zc >= p.H_mix) { K = 0.0f; dK = 0.0f; return; }
-    const float g = fmaf(-zc, p.inv_Hmix, 1.0f);
-    const float zz = zc + p.z0;
-    if (p.kz_kind == 1) {
-        K = p.ku * zz * g;
-        dK = p.ku * fmaf(-zz, p.inv_Hmix, g);
+    if constexpr (KZ == 0) {
+        K = p.Kz_const;
+        dK = 0.0f;
     } else {
-        K = p.ku * zz * g * g;
-        dK = p.ku * g * fmaf(-2.0f * zz, p.inv_Hmix, g);
+        const float zc = fmaxf(z, 0.0f);
+        const float g = fmaf(-zc, p.inv_Hmix, 1.0f);
+        const float zz = zc + p.z0;
+        const bool inside = zc < p.H_mix;
+        if constexpr (KZ == 1) {
+            K = inside ? p.ku * zz * g : 0.0f;
+            dK = inside ? p.ku * fmaf(-zz, p.inv_Hmix, g) : 0.0f;
+        } else {
+            K = inside ? p.ku * zz * g * g : 0.0f;
+            dK = inside ? p.ku * g * fmaf(-2.0f * zz, p.inv_Hmix, g) : 0.0f;
+        }
     }
 }
 

@@ -13,7 +13,7 @@ import torch
 
 from . import (Accum, Field, Grid, Physics, Schedule, Source, State, LEDGER_SLOTS, LEDGER_STRIDE,
                accum_reset, grid_concentration, grid_deposition, read_ledger,
-               release_particles, step_particles, check)
+               release_particles, step_particles, step_particles_record, check)
 
 
 def make_source(src) -> Source:
@@ -116,6 +116,29 @@ class DeviceRun:
         n = self.sch.n_local
         return {k: getattr(self, k)[:n].double().cpu().numpy() for k in "xyzm"}
 
+    def step_record(self, step0: int, n_steps: int, rec_step0: int, rec_every: int,
+                    n_rec: int, rec: torch.Tensor):
+        step_particles_record(self.st, self.src, self.sch, self.fld, self.ph, step0, n_steps,
+                              self.acc, rec_step0, rec_every, n_rec, rec, self.rec_stride)
+
+    @property
+    def rec_stride(self) -> int:
+        return max(self.sch.n_local, 1)
+
+    def record_buffer(self, n_rec: int) -> torch.Tensor:
+        return torch.empty(4 * n_rec * self.rec_stride, dtype=torch.float32,
+                           device=self.device)
+
+    def recorded_state(self, rec: torch.Tensor, k: int) -> State:
+        base = rec.data_ptr() + 4 * k * 4 * self.rec_stride
+        plane = 4 * self.rec_stride
+        return State(base, base + plane, base + 2 * plane, base + 3 * plane, self.rec_stride)
+
+    def grid_recorded(self, rec: torch.Tensor, k: int, step: int) -> torch.Tensor:
+        grid_concentration(self.recorded_state(rec, k), self.src, self.sch, self.ph, self.cgrid,
+                           step, self.conc_scratch, self.conc)
+        return self.conc
+
     # -- the host main loop -------------------------------------------------
     def windows(self, s_begin: int, s_end: int, steps_per_launch: int,
                 snap_steps: Iterable[int] = ()):
@@ -129,6 +152,35 @@ class DeviceRun:
                 out.append((a, e))
                 a = e
         return out
+
+    def run_whole(self, s_begin: int = 0, s_end: Optional[int] = None, every: int = 60,
+                  on_snapshot: Optional[Callable] = None, rec: Optional[torch.Tensor] = None):
+        """Whole window [s_begin, s_end) in one step launch: each thread carries
+        its particle through every step; the states after the output steps
+        s_begin + every - 1, s_begin + 2 every - 1, ... (and s_end - 1) are
+        recorded and gridded afterwards (results equal the windowed run)."""
+        s_end = self.case.n_steps if s_end is None else s_end
+        steps = list(range(s_begin + every - 1, s_end, every))
+        if not steps or steps[-1] != s_end - 1:
+            steps.append(s_end - 1)
+        regular = [s for s in steps if (s - s_begin + 1) % every == 0]
+        n_rec = len(regular)
+        if rec is None or rec.numel() < 4 * n_rec * self.rec_stride:
+            rec = self.record_buffer(max(n_rec, 1))
+        self.release(s_begin, s_end - s_begin)
+        if n_rec:
+            self.step_record(s_begin, s_end - s_begin, regular[0], every, n_rec, rec)
+        else:
+            self.step(s_begin, s_end - s_begin)
+        for k, s in enumerate(regular):
+            g = self.grid_recorded(rec, k, s)
+            if on_snapshot is not None:
+                on_snapshot(s, g)
+        if steps[-1] not in regular:
+            g = self.grid_concentration(steps[-1])
+            if on_snapshot is not None:
+                on_snapshot(steps[-1], g)
+        return rec
 
     def run(self, s_begin: int = 0, s_end: Optional[int] = None, steps_per_launch: int = 60,
             snap_steps: Iterable[int] = (), on_snapshot: Optional[Callable] = None,

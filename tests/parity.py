@@ -49,6 +49,13 @@ def run_oracle(case, snaps=(), state=None, s_begin=0, s_end=None, nthreads=0):
     return r
 
 
+def ledger_ok(gl, ol, released, tol=1e-6):
+    """Every ledger entry within ``tol`` of the released activity."""
+    for n in range(len(ol)):
+        for e in range(4):
+            assert abs(gl[n][e] - ol[n][e]) <= tol * released, (n, e, gl[n][e], ol[n][e])
+
+
 def distances(a, b, active):
     d = np.sqrt((a["x"] - b["x"]) ** 2 + (a["y"] - b["y"]) ** 2 + (a["z"] - b["z"]) ** 2)
     return d[active]

@@ -17,8 +17,8 @@ import numpy as np
 import pytest
 
 import synth
-from parity import (activities, distances, log, ngp_unexplained, rel_l2_masked, run_gpu,
-                    run_oracle)
+from parity import (activities, distances, ledger_ok, log, ngp_unexplained, rel_l2_masked,
+                    run_gpu, run_oracle)
 
 pytestmark = pytest.mark.gpu
 
@@ -29,12 +29,6 @@ def _gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_0912_3223_amd  # noqa: F401  (fails loudly if liblpm.so is missing)
-
-
-def ledger_ok(gl, ol, released, tol=1e-6):
-    for n in range(len(ol)):
-        for e in range(4):
-            assert abs(gl[n][e] - ol[n][e]) <= tol * released, (n, e, gl[n][e], ol[n][e])
 
 
 def with_ngp(case):
@@ -154,3 +148,27 @@ def test_subset_ids_reproduce_full_run():
     sub = run_gpu(c.with_(schedule=c.schedule.subset(7, 3)))
     for k in "xyzm":
         np.testing.assert_array_equal(sub["state"][k], full["state"][k][3::7])
+
+
+def test_whole_run_recorded_equals_windowed_and_oracle():
+    """One launch for the whole run with the output-step states recorded
+    gives the windowed run's states bitwise and the oracle's snapshots."""
+    import paper_0912_3223_amd as L
+    c = synth.c1(n_total=50_000, n_steps=720, s_release=720)
+    snaps = c.output_steps()
+    w = run_gpu(c, snaps=snaps)
+    r = L.DeviceRun(c)
+    got = {}
+    r.run_whole(every=c.out_every, on_snapshot=lambda s, g: got.__setitem__(s, g.double().cpu().numpy()))
+    st = r.state()
+    for k in "xyzm":
+        np.testing.assert_array_equal(st[k], w["state"][k])
+    o = run_oracle(c, snaps=snaps)
+    for s in snaps:
+        np.testing.assert_allclose(got[s], w["snaps"][s], rtol=1e-9, atol=1e-12 * np.abs(w["snaps"][s]).max())
+        rel, ncell = rel_l2_masked(got[s], o["snap_map"][s])
+        log("whole-run CIC step", s, "rel_l2 %.3e over %d cells" % (rel, ncell))
+        assert rel <= 1e-4
+    ledger_ok(r.ledger(), o["ledger"], o["ledger"][0][0])
+    np.testing.assert_allclose(r.grid_deposition().double().cpu().numpy(), w["dep"], rtol=1e-5,
+                               atol=1e-9 * np.abs(w["dep"]).max())
