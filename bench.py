@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=8,
                     help="oracle sample: every k-th particle id of the same workload")
+    ap.add_argument("--ensemble-steps", type=int, default=2)
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the 64-scenario batched-vs-sequential comparison")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this size before timing "
                          "(reference dispatch for hardware byte counters)")
@@ -71,6 +74,60 @@ def cpu_baseline(case, stride):
                       f"{dt:.1f} s, FP64, {threads} OpenMP threads)"}
 
 
+def ensemble_vs_plain(a):
+    """64 release scenarios of uneven size on the gridded 6 h workload:
+    one persistent ensemble launch per run against 64 sequential plain runs
+    (release + whole-window step each), same particle-steps."""
+    import torch
+    import synth
+    import paper_0912_3223_amd as L
+    base, sources, counts = synth.c3()
+    e = L.EnsembleRun(base, sources, counts)
+    e.prepare()
+    tune = e.autotune(trial_steps=240)
+    e.run()
+    torch.cuda.synchronize()
+    ps = e.particle_steps()
+    t0 = time.perf_counter()
+    for _ in range(a.ensemble_steps):
+        e.run()
+    torch.cuda.synchronize()
+    batched = (time.perf_counter() - t0) / a.ensemble_steps
+    tuned = (tune.refill_every, tune.blocks_per_cu)
+    L.set_launch(1, 0)
+    runs = []
+    for src, n in zip(sources, counts):
+        case = base.with_(source=src, schedule=synth.Schedule(n_total=n, s_release=base.n_steps))
+        runs.append(L.DeviceRun(case))
+    L.set_launch(*tuned)
+
+    def sequential():
+        for r in runs:
+            r.reset()
+            r.release(0, base.n_steps)
+            r.step(0, base.n_steps)
+
+    sequential()
+    torch.cuda.synchronize()
+    ps_plain = sum(r.particle_steps() for r in runs)
+    t0 = time.perf_counter()
+    for _ in range(a.ensemble_steps):
+        sequential()
+    torch.cuda.synchronize()
+    seq = (time.perf_counter() - t0) / a.ensemble_steps
+    L.set_launch(1, 0)
+    return {"workload": "64 scenarios, counts log-uniform in [1e4, 1e6] (seed 3), heights "
+                        "U(10,200) m, rates U(0.5,2), wind scale U(0.8,1.2), shared 200x200x30 "
+                        "field, 4320 steps",
+            "particles": int(sum(counts)), "particle_steps": ps, "plain_particle_steps": ps_plain,
+            "batched_ms": batched * 1e3, "sequential_ms": seq * 1e3,
+            "batched_particle_steps_per_s": ps / batched,
+            "sequential_particle_steps_per_s": ps_plain / seq,
+            "speedup_batched_vs_sequential": seq / batched,
+            "autotuned": {"refill_every": tune.refill_every, "blocks_per_cu": tune.blocks_per_cu,
+                          "best_trial_ms": tune.best_ms, "worst_trial_ms": tune.worst_ms}}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -90,6 +147,7 @@ def main():
     ev = []
 
     rec = run.record_buffer(len(snaps)) if a.spl == 0 else None
+    gbufs = run.grid_buffers(len(snaps)) if a.spl == 0 else None
 
     def one_run(timed):
         run.reset()
@@ -103,8 +161,7 @@ def main():
             if timed:
                 e1.record(stream)
                 ev.append((e0, e1))
-            for k, s in enumerate(snaps):
-                run.grid_recorded(rec, k, s)
+            run.grid_records(rec, snaps[0], case.out_every, len(snaps), gbufs)
             run.grid_deposition()
             return
         for s0, s1 in run.windows(0, case.n_steps, a.spl, snaps):
@@ -177,6 +234,8 @@ def main():
                      "step_kernel_share": step_total_s / (ms / 1e3)},
         "ledger_first_nuclide": list(map(float, ledger[0])),
     }
+    if not a.no_ensemble:
+        out["ensemble"] = ensemble_vs_plain(a)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, a.cpu_stride)
     print(json.dumps(out), flush=True)

@@ -59,6 +59,10 @@ extern "C" {
 #define LPM_LEDGER_SLOTS 64
 #define LPM_LEDGER_STRIDE 32 /* doubles per slot (two 128-byte lines) */
 #define LPM_LEDGER_PSTEPS 16 /* slot entry counting advanced particle-steps */
+/* Control words (see lpm_accum.ctrl). */
+#define LPM_CTRL_WORDS 64
+#define LPM_CTRL_ERR 0   /* error flags: bit 0 = a particle became non-finite */
+#define LPM_CTRL_QUEUE 2 /* 64-bit work counter of the step kernel (words 2-3) */
 /* Ledger entries per nuclide. */
 #define LPM_LEDGER_RELEASED 0
 #define LPM_LEDGER_DEPOSITED 1
@@ -151,17 +155,20 @@ typedef struct {
  *          (2) and exited (3) activity, entry LPM_LEDGER_PSTEPS the number of
  *          particle-steps advanced; per-slot partial sums that
  *          lpm_read_ledger adds up;
- *  err:    uint32, bit 0 set when a particle became non-finite. */
+ *  ctrl:   uint32 [LPM_CTRL_WORDS], 8-byte aligned: word LPM_CTRL_ERR holds
+ *          the error flags (bit 0: a particle became non-finite), the other
+ *          words are working counters of the kernels (calls on one accum
+ *          must therefore be ordered on one stream). */
 typedef struct {
     double* dep;
     double* ledger;
-    uint32_t* err;
+    uint32_t* ctrl;
     int32_t n_nuc;
     int32_t reserved;
     lpm_grid dep_grid;
 } lpm_accum;
 
-/* Zero dep, ledger and err.  Stream-ordered. */
+/* Zero dep, ledger and ctrl.  Stream-ordered. */
 int lpm_accum_reset(const lpm_accum* acc, lpm_stream stream);
 
 /* Release (Sec. 2: particles released from a point source in each time step;
@@ -194,16 +201,18 @@ int lpm_step_particles(const lpm_state* st, const lpm_source* src,
                        const lpm_accum* acc, lpm_stream stream);
 
 /* lpm_step_particles, and in addition the state of every local particle
- * after each output step rec_step0 + k * rec_every (k = 0 .. n_rec - 1) is
- * written to rec: device float planes x, y, z, m of record k at
- * rec + (4 k + q) * rec_stride, q = 0..3 (m = 0 once a particle has left the
- * area; particles not yet born at that step are not written, and gridding
- * skips them by their birth).  With every recorded step inside one window the
- * whole run can be a single launch in which each thread carries its particle
- * from birth to the last step, and the concentration at each output step
- * (Sec. 3.2: activities summed every n-th step) is gridded afterwards from the
- * records with lpm_grid_concentration.  All recorded steps must lie in
- * [step0, step0 + n_steps); rec_stride >= n_local.  rec is caller-owned. */
+ * after each output step s_k = rec_step0 + k * rec_every (k = 0 .. n_rec - 1)
+ * is recorded for gridding later (Sec. 3.2: activities summed every n-th
+ * step).  rec: caller-owned device buffer, 16-byte aligned, of
+ * 16 * n_rec * rec_stride + 4 * rec_stride bytes: record k of local particle i
+ * is the float4 (x, y, z, m) at index k * rec_stride + i, followed by an int32
+ * array last[rec_stride]: the step after which particle i stopped being
+ * active in this window (INT_MAX if it is still active at the end, INT_MIN if
+ * it was inactive on entry).  Records at or after `last` and of particles not
+ * yet born are not meaningful; lpm_grid_records skips them.  All recorded
+ * steps must lie in [step0, step0 + n_steps); rec_stride >= n_local.
+ * With every output step inside one window the whole run is one launch in
+ * which all particles of the run are in flight at once. */
 int lpm_step_particles_record(const lpm_state* st, const lpm_source* src,
                               const lpm_schedule* sch, const lpm_field* fld,
                               const lpm_physics* ph, int32_t step0, int32_t n_steps,
@@ -220,6 +229,17 @@ int lpm_grid_concentration(const lpm_state* st, const lpm_source* src,
                            const lpm_schedule* sch, const lpm_physics* ph,
                            const lpm_grid* grid, int32_t step,
                            double* acc_scratch, float* out, lpm_stream stream);
+
+/* Concentration at every recorded step of rec (lpm_step_particles_record
+ * with the same schedule, source, physics, rec_step0, rec_every, n_rec and
+ * rec_stride): out[k] = the grid of lpm_grid_concentration after step s_k.
+ * acc_scratch: device double [n_rec][n_nuc][nz][ny][nx], overwritten;
+ * out: device float [n_rec][n_nuc][nz][ny][nx], overwritten. */
+int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0,
+                     int32_t rec_every, int32_t n_rec, const lpm_source* src,
+                     const lpm_schedule* sch, const lpm_physics* ph,
+                     const lpm_grid* grid, double* acc_scratch, float* out,
+                     lpm_stream stream);
 
 /* Deposited activity so far on the deposition grid, converted to float and
  * divided by the cell area when dep_grid.density != 0.
@@ -238,6 +258,93 @@ int lpm_check(const lpm_accum* acc, lpm_stream stream);
 
 /* Message of the calling thread's last failed call ("" if none). */
 const char* lpm_last_error(void);
+
+/* Launch tuning of the step kernels (process-wide): a wave refills idle
+ * lanes from the work queue every `refill_every` steps (default 1), and at
+ * most `blocks_per_cu` blocks per compute unit are launched (0 = as many as
+ * fit).  Results do not depend on either. */
+int lpm_set_launch(int32_t refill_every, int32_t blocks_per_cu);
+
+/* lpm_set_launch, and a wave refills only once at least `refill_min` of its
+ * 64 lanes are idle (or all of them; default 1). */
+int lpm_set_launch_ex(int32_t refill_every, int32_t blocks_per_cu, int32_t refill_min);
+
+/* ---------------------------------------------------------------------------
+ * Ensembles: many release scenarios advanced in one persistent launch.
+ * Every scenario is a full run of its own (local ids 0 .. n_total - 1, births
+ * floor(l * s_release / n_total), Philox key (seed, src.scenario)) whose
+ * particles sit at [offset, offset + n_total) of one combined state; the
+ * work queue of the step kernel runs over the particles of all scenarios, so
+ * scenarios of very different sizes share the device without per-scenario
+ * launches.  Each scenario's trajectories equal those of its plain run.
+ * ------------------------------------------------------------------------- */
+#define LPM_MAX_SCENARIOS 256
+#define LPM_SCENARIO_BYTES 96 /* device table bytes per scenario */
+
+typedef struct {
+    lpm_source src;  /* release point, rate, wind scale, v_d, Philox scenario key */
+    int64_t n_total; /* particles of the scenario */
+    int32_t s_release;
+    int32_t reserved;
+    int64_t offset;  /* first element of the scenario in the combined state */
+} lpm_scenario;
+
+/* A prepared ensemble window (filled by lpm_ensemble_prepare). */
+typedef struct {
+    void* table;        /* device scenario table (caller-owned workspace) */
+    int32_t n_scen;
+    int32_t n_nuc;
+    int32_t step0;
+    int32_t n_steps;
+    int64_t queue_len;   /* particles of all scenarios born before step0 + n_steps */
+    int64_t max_release; /* most particles one scenario releases in the window */
+} lpm_ensemble;
+
+/* Check the scenarios (n_scen <= LPM_MAX_SCENARIOS, disjoint state ranges
+ * within st->capacity) and upload the table of the window [step0, step0 +
+ * n_steps) into `table` (device, >= n_scen * LPM_SCENARIO_BYTES bytes,
+ * 16-byte aligned); `out` describes it.  Not stream-captured work: call it
+ * before capturing release and step into a graph. */
+int lpm_ensemble_prepare(const lpm_scenario* scen, int32_t n_scen, const lpm_state* st,
+                         const lpm_physics* ph, int32_t step0, int32_t n_steps,
+                         void* table, int64_t table_bytes, lpm_ensemble* out,
+                         lpm_stream stream);
+
+/* lpm_release_particles for every scenario of a prepared window.  ledgers:
+ * device double [n_scen][LPM_LEDGER_SLOTS][LPM_LEDGER_STRIDE]. */
+int lpm_release_ensemble(const lpm_state* st, const lpm_ensemble* ens, double* ledgers,
+                         lpm_stream stream);
+
+/* lpm_step_particles for every scenario of a prepared window, in one
+ * persistent launch.  dep: device double [n_scen][n_nuc][ny][nx] on
+ * dep_grid; ledgers as for lpm_release_ensemble; ctrl: device uint32
+ * [LPM_CTRL_WORDS].  Wind field and physics (K, decay, rain) are shared; the
+ * source (rate, wind scale, v_d, key) is per scenario.  n_nuc <= 2. */
+int lpm_step_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_field* fld,
+                      const lpm_physics* ph, const lpm_grid* dep_grid, double* dep,
+                      double* ledgers, uint32_t* ctrl, lpm_stream stream);
+
+/* Launch settings picked by lpm_autotune_ensemble. */
+typedef struct {
+    int32_t refill_every;
+    int32_t blocks_per_cu;
+    double best_ms;   /* trial time of the chosen setting */
+    double worst_ms;  /* trial time of the slowest setting */
+    int32_t n_tried;
+    int32_t reserved;
+} lpm_tuning;
+
+/* Autotuner: time the ensemble step over the first `trial_steps` steps of
+ * the prepared window for each candidate (refill interval x blocks per
+ * compute unit), keep the fastest (installed with lpm_set_launch) and report
+ * it.  It runs release and step on the given buffers, so state, dep, ledgers
+ * and ctrl must be reset and the particles released again afterwards.
+ * Synchronises `stream`. */
+int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens,
+                          const lpm_scenario* scen, const lpm_field* fld,
+                          const lpm_physics* ph, const lpm_grid* dep_grid, double* dep,
+                          double* ledgers, uint32_t* ctrl, int32_t trial_steps,
+                          lpm_tuning* out, lpm_stream stream);
 
 /* Library version string. */
 const char* lpm_version(void);

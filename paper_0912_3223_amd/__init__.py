@@ -19,7 +19,10 @@ LIB_PATH = os.path.join(_PKG, "liblpm.so")
 
 LPM_OK, LPM_EINVAL, LPM_ECAPACITY, LPM_EHIP, LPM_ENONFINITE = 0, -1, -2, -3, -4
 LEDGER_SLOTS = 64
+MAX_SCENARIOS = 256
+SCENARIO_BYTES = 96
 LEDGER_STRIDE = 32
+CTRL_WORDS = 64
 
 
 class LpmError(RuntimeError):
@@ -69,8 +72,25 @@ class Grid(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
 
 
+class Scenario(C.Structure):
+    _fields_ = [("src", Source), ("n_total", C.c_int64), ("s_release", C.c_int32),
+                ("reserved", C.c_int32), ("offset", C.c_int64)]
+
+
+class Ensemble(C.Structure):
+    _fields_ = [("table", C.c_void_p), ("n_scen", C.c_int32), ("n_nuc", C.c_int32),
+                ("step0", C.c_int32), ("n_steps", C.c_int32), ("queue_len", C.c_int64),
+                ("max_release", C.c_int64)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("refill_every", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("best_ms", C.c_double), ("worst_ms", C.c_double), ("n_tried", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class Accum(C.Structure):
-    _fields_ = [("dep", C.c_void_p), ("ledger", C.c_void_p), ("err", C.c_void_p),
+    _fields_ = [("dep", C.c_void_p), ("ledger", C.c_void_p), ("ctrl", C.c_void_p),
                 ("n_nuc", C.c_int32), ("reserved", C.c_int32), ("dep_grid", Grid)]
 
 
@@ -91,9 +111,22 @@ def _load():
                                       C.c_int32, C.c_void_p, C.c_int64, C.c_void_p],
         "lpm_grid_concentration": [P(State), P(Source), P(Schedule), P(Physics), P(Grid),
                                    C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
+        "lpm_grid_records": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, P(Source),
+                             P(Schedule), P(Physics), P(Grid), C.c_void_p, C.c_void_p,
+                             C.c_void_p],
         "lpm_grid_deposition": [P(Accum), C.c_void_p, C.c_void_p],
         "lpm_read_ledger": [P(Accum), P(C.c_double), C.c_void_p],
         "lpm_check": [P(Accum), C.c_void_p],
+        "lpm_set_launch": [C.c_int32, C.c_int32],
+        "lpm_set_launch_ex": [C.c_int32, C.c_int32, C.c_int32],
+        "lpm_ensemble_prepare": [P(Scenario), C.c_int32, P(State), P(Physics), C.c_int32,
+                                 C.c_int32, C.c_void_p, C.c_int64, P(Ensemble), C.c_void_p],
+        "lpm_release_ensemble": [P(State), P(Ensemble), C.c_void_p, C.c_void_p],
+        "lpm_step_ensemble": [P(State), P(Ensemble), P(Field), P(Physics), P(Grid), C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p],
+        "lpm_autotune_ensemble": [P(State), P(Ensemble), P(Scenario), P(Field), P(Physics),
+                                  P(Grid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                  P(Tuning), C.c_void_p],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -109,7 +142,9 @@ _lib = _load()
 #: C entry points exported by include/lpm.h (checked by the test suite).
 EXPORTS = ("lpm_accum_reset", "lpm_release_particles", "lpm_step_particles",
            "lpm_step_particles_record",
-           "lpm_grid_concentration", "lpm_grid_deposition", "lpm_read_ledger", "lpm_check",
+           "lpm_grid_concentration", "lpm_grid_records", "lpm_grid_deposition",
+           "lpm_read_ledger", "lpm_check", "lpm_set_launch", "lpm_set_launch_ex", "lpm_ensemble_prepare",
+           "lpm_release_ensemble", "lpm_step_ensemble", "lpm_autotune_ensemble",
            "lpm_last_error", "lpm_version")
 
 
@@ -150,7 +185,7 @@ def step_particles_record(st: State, src: Source, sch: Schedule, fld: Field, ph:
                           step0: int, n_steps: int, acc: Accum, rec_step0: int, rec_every: int,
                           n_rec: int, rec: torch.Tensor, rec_stride: int, stream=None):
     assert rec.dtype == torch.float32 and rec.is_contiguous()
-    assert rec.numel() >= 4 * n_rec * rec_stride
+    assert rec.numel() >= (4 * n_rec + 1) * rec_stride
     _rc(_lib.lpm_step_particles_record(C.byref(st), C.byref(src), C.byref(sch), C.byref(fld),
                                        C.byref(ph), step0, n_steps, C.byref(acc), rec_step0,
                                        rec_every, n_rec, C.c_void_p(rec.data_ptr()), rec_stride,
@@ -163,6 +198,17 @@ def grid_concentration(st: State, src: Source, sch: Schedule, ph: Physics, grid:
     _rc(_lib.lpm_grid_concentration(C.byref(st), C.byref(src), C.byref(sch), C.byref(ph),
                                     C.byref(grid), step, C.c_void_p(acc_scratch.data_ptr()),
                                     C.c_void_p(out.data_ptr()), _stream(stream)))
+
+
+def grid_records(rec: torch.Tensor, rec_stride: int, rec_step0: int, rec_every: int, n_rec: int,
+                 src: Source, sch: Schedule, ph: Physics, grid: Grid, acc_scratch: torch.Tensor,
+                 out: torch.Tensor, stream=None):
+    assert rec.dtype == torch.float32 and acc_scratch.dtype == torch.float64
+    assert out.dtype == torch.float32
+    _rc(_lib.lpm_grid_records(C.c_void_p(rec.data_ptr()), rec_stride, rec_step0, rec_every, n_rec,
+                              C.byref(src), C.byref(sch), C.byref(ph), C.byref(grid),
+                              C.c_void_p(acc_scratch.data_ptr()), C.c_void_p(out.data_ptr()),
+                              _stream(stream)))
 
 
 def grid_deposition(acc: Accum, out: torch.Tensor, stream=None):
@@ -183,8 +229,47 @@ def check(acc: Accum, stream=None):
     _rc(_lib.lpm_check(C.byref(acc), _stream(stream)))
 
 
+def ensemble_prepare(scen, n_scen: int, st: State, ph: Physics, step0: int, n_steps: int,
+                     table: torch.Tensor, stream=None) -> Ensemble:
+    ens = Ensemble()
+    _rc(_lib.lpm_ensemble_prepare(scen, n_scen, C.byref(st), C.byref(ph), step0, n_steps,
+                                  C.c_void_p(table.data_ptr()),
+                                  table.numel() * table.element_size(), C.byref(ens),
+                                  _stream(stream)))
+    return ens
+
+
+def release_ensemble(st: State, ens: Ensemble, ledgers: torch.Tensor, stream=None):
+    _rc(_lib.lpm_release_ensemble(C.byref(st), C.byref(ens), C.c_void_p(ledgers.data_ptr()),
+                                  _stream(stream)))
+
+
+def step_ensemble(st: State, ens: Ensemble, fld: Field, ph: Physics, dep_grid: Grid,
+                  dep: torch.Tensor, ledgers: torch.Tensor, ctrl: torch.Tensor, stream=None):
+    _rc(_lib.lpm_step_ensemble(C.byref(st), C.byref(ens), C.byref(fld), C.byref(ph),
+                               C.byref(dep_grid), C.c_void_p(dep.data_ptr()),
+                               C.c_void_p(ledgers.data_ptr()), C.c_void_p(ctrl.data_ptr()),
+                               _stream(stream)))
+
+
+def autotune_ensemble(st: State, ens: Ensemble, scen, fld: Field, ph: Physics, dep_grid: Grid,
+                      dep: torch.Tensor, ledgers: torch.Tensor, ctrl: torch.Tensor,
+                      trial_steps: int, stream=None) -> Tuning:
+    t = Tuning()
+    _rc(_lib.lpm_autotune_ensemble(C.byref(st), C.byref(ens), scen, C.byref(fld), C.byref(ph),
+                                   C.byref(dep_grid), C.c_void_p(dep.data_ptr()),
+                                   C.c_void_p(ledgers.data_ptr()), C.c_void_p(ctrl.data_ptr()),
+                                   trial_steps, C.byref(t), _stream(stream)))
+    return t
+
+
+def set_launch(refill_every: int = 1, blocks_per_cu: int = 0, refill_min: int = 1):
+    _rc(_lib.lpm_set_launch_ex(refill_every, blocks_per_cu, refill_min))
+
+
 def version() -> str:
     return _lib.lpm_version().decode()
 
 
-from .host import DeviceRun, make_source, make_schedule, make_physics, make_grid  # noqa: E402
+from .host import (DeviceRun, EnsembleRun, make_source, make_schedule, make_physics,  # noqa: E402
+                   make_grid)

@@ -29,6 +29,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <utility>
+#include <vector>
+
 #include "lpm.h"
 #include "lpm_device.h"
 
@@ -117,17 +121,94 @@ struct CellTable {
     }
 };
 
+// Wave-private histogram for the persistent step kernel.  The lanes of a wave
+// run independent particles and never meet at a block barrier, so each wave
+// owns a table; when half of its slots are taken, the wave (which executes in
+// lockstep) moves the table to the global grid and empties it.
+template <int NNUC, int LOG2_SLOTS>
+struct WaveTable {
+    static constexpr int kSlots = 1 << LOG2_SLOTS;
+    static constexpr int kShift = 32 - LOG2_SLOTS;
+    static constexpr int kProbes = 8;
+    int* key;      // [kSlots]: 0 = empty, else cell + 1
+    double* val;   // [NNUC][kSlots]
+    int* used;     // slots taken
+    // A key is scen * plane + cell; scenario scen's grid starts at
+    // scen * NNUC * plane (a plain launch has scen = 0).
+    __device__ static double* at(double* grid, long long plane, int key, int n)
+    {
+        const unsigned sc = (unsigned)key / (unsigned)plane;
+        return grid + (long long)sc * (NNUC - 1) * plane + (long long)n * plane + key;
+    }
+
+    __device__ void init(int lane)
+    {
+        for (int t = lane; t < kSlots; t += 64) {
+            key[t] = 0;
+#pragma unroll
+            for (int n = 0; n < NNUC; ++n) val[n * kSlots + t] = 0.0;
+        }
+        if (lane == 0) *used = 0;
+    }
+
+    __device__ void add(int cell, const float (&v)[NNUC], double* grid, long long plane)
+    {
+        unsigned h = ((unsigned)cell * 2654435761u) >> kShift;
+        for (int probe = 0; probe < kProbes; ++probe) {
+            const int old = atomicCAS(&key[h], 0, cell + 1);
+            if (old == 0 || old == cell + 1) {
+                if (old == 0) atomicAdd(used, 1);
+#pragma unroll
+                for (int n = 0; n < NNUC; ++n)
+                    if (v[n] != 0.0f) atomicAdd(&val[n * kSlots + h], (double)v[n]);
+                return;
+            }
+            h = (h + 1) & (kSlots - 1);
+        }
+#pragma unroll
+        for (int n = 0; n < NNUC; ++n)
+            if (v[n] != 0.0f) atomicAdd(at(grid, plane, cell, n), (double)v[n]);
+    }
+
+    // Called by all lanes of the wave at the same point.
+    __device__ void flush(int lane, double* grid, long long plane)
+    {
+        __builtin_amdgcn_wave_barrier();
+        for (int t = lane; t < kSlots; t += 64) {
+            const int k = atomicExch(&key[t], 0);
+            if (k == 0) continue;
+#pragma unroll
+            for (int n = 0; n < NNUC; ++n) {
+                const double v = atomicExch(&val[n * kSlots + t], 0.0);
+                if (v != 0.0) atomicAdd(at(grid, plane, k - 1, n), v);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) atomicExch(used, 0);
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    __device__ void flush_if_half_full(int lane, double* grid, long long plane)
+    {
+        // one broadcast LDS read (not 64 same-address atomics)
+        const int u = __hip_atomic_load(used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (__builtin_amdgcn_readfirstlane(u) > kSlots / 2) flush(lane, grid, plane);
+    }
+};
+
+template <int NNUC>
+using DepTable = WaveTable<NNUC, 8>;
+
 // Per-thread deposition while the particle stays in one grid cell (nearest
 // cell) or above one cell quad (cloud-in-cell): partial sums of the corner
-// weights times the deposited activity, flushed to the block table when the
-// cell changes and at the end of the window.
-template <int NNUC>
-using DepTable = CellTable<NNUC, NNUC <= 2 ? 10 : 9>;
-
+// weights times the deposited activity, flushed to the wave's table when the
+// cell changes and when the particle stops.
 template <int NNUC>
 struct Dwell {
     int i0 = INT_MIN, j0 = 0;
     float acc[NNUC][4];
+
+    int key_base = 0;  // scenario * plane in an ensemble launch
 
     __device__ void flush(const StepConst& p, DepTable<NNUC>& tab, long long plane)
     {
@@ -139,7 +220,7 @@ struct Dwell {
             float v[NNUC];
 #pragma unroll
             for (int n = 0; n < NNUC; ++n) v[n] = acc[n][c];
-            tab.add(jj * p.dnx + ii, v, p.dep, plane);
+            tab.add(key_base + jj * p.dnx + ii, v, p.dep, plane);
         }
         i0 = INT_MIN;
     }
@@ -184,162 +265,281 @@ struct Dwell {
 };
 
 // ---------------------------------------------------------------------------
-// The particle step (Sec. 3.2 main loop; Eqs. 1-3).
+// One time step of one particle (Sec. 3.2 main loop; Eqs. 1-3).  Returns 1
+// when the particle left the area, 2 when it became non-finite, else 0.
 // ---------------------------------------------------------------------------
-template <int NCOMP, bool TIME, bool LEVELS, int NNUC, int KZ, bool DEP>
-__global__ __launch_bounds__(kBlock) void step_kernel(const StepConst p)
+template <int NCOMP, bool TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS>
+__device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
+                                       DepTable<NNUC>& tab, long long plane, uint32_t gid,
+                                       int b, int s, float& x, float& y, float& z, float& m,
+                                       double (&led)[3 * NNUC + 1], Dwell<NNUC>& dw)
 {
-    __shared__ int tab_key[DepTable<NNUC>::kSlots];
-    __shared__ double tab_val[NNUC * DepTable<NNUC>::kSlots];
-    DepTable<NNUC> tab{tab_key, tab_val};
-    const long long plane = (long long)p.dnx * p.dny;
-    if constexpr (DEP) tab.init();
-    __syncthreads();
+    const float age = (float)(s - b) * p.dt;
+    // weather at the start-of-step position and time (Eq. 1): the loads are
+    // issued first; everything up to the interpolation is independent of them
+    WindTap<NCOMP, TIME> tap;
+    wind_gather<NCOMP, TIME, LEVELS>(p, x, y, z, (float)s * p.dt, tap);
+    // random numbers of Eq. (2)
+    float xi0, xi1, xi2;
+    normals3<!ENS>(gid, (uint32_t)s, p.key0, sv.key1, xi0, xi1, xi2);
+    // diffusivity (Eq. 3) with the drift and midpoint evaluation
+    float K, dK, Km, dKm;
+    kz_profile<KZ>(p, z, K, dK);
+    const float zm = clampf(fmaf(p.half_dt, dK, z), 0.0f, p.H_mix);
+    kz_profile<KZ>(p, zm, Km, dKm);
+    // decay factors at the start of the step
+    float D[NNUC];
+#pragma unroll
+    for (int n = 0; n < NNUC; ++n) D[n] = exp2f(-p.lam_l2e[n] * age);
+    float uvw[3];
+    wind_interp<NCOMP, TIME>(tap, uvw);
+    // move (Eq. 1 with Eq. 2)
+    const float xn = fmaf(xi0, p.sKh, fmaf(sv.wscale * uvw[0], p.dt, x));
+    const float yn = fmaf(xi1, p.sKh, fmaf(sv.wscale * uvw[1], p.dt, y));
+    float zn = fmaf(xi2 * __builtin_amdgcn_sqrtf(Km), p.s2dt,
+                    fmaf(fmaf(sv.wscale, uvw[2], dK), p.dt, z));
+    // reflection at the ground and the lid: one fold each, and the general
+    // fold-until-inside for the (never seen) larger steps
+    zn = fabsf(zn);
+    if (zn > p.H_top) zn = 2.0f * p.H_top - zn;
+    if (zn < 0.0f || zn > p.H_top) {
+#pragma unroll 1
+        for (int it = 0; it < 64; ++it) {
+            if (zn < 0.0f) zn = -zn;
+            else if (zn > p.H_top) zn = 2.0f * p.H_top - zn;
+            else break;
+        }
+    }
+    // deposition rate at the new position (Sec. 2)
+    float k = 0.0f;
+    if constexpr (DEP) {
+        if (zn < p.h_s) k = fmaxf(fmaf(-sv.dry_c2, zn, sv.dry_c1), 0.0f);
+        if (p.L0 > 0.0f) k += wet_rate(p, xn, yn);
+    }
+    const float mn = k > 0.0f ? m * exp2f(-1.4426950408889634f * k * p.dt) : m;
+    // decay and deposition of each nuclide's activity this step
+    float dsum[NNUC];
+#pragma unroll
+    for (int n = 0; n < NNUC; ++n) {
+        const float A = sv.a0 * m * D[n];
+        if (DEP && k > 0.0f) {
+            // loss of activity this step, split by the rates
+            const float r = p.lam[n] + k;
+            const float loss = -A * expm1_neg(-r * p.dt);
+            const float dep = loss * (k * __builtin_amdgcn_rcpf(r));
+            dsum[n] = dep * p.dscale;
+            led[3 * n + 0] += (double)dep;
+            led[3 * n + 1] += (double)(loss - dep);
+        } else {
+            dsum[n] = 0.0f;
+            led[3 * n + 1] += (double)(A * p.cdec[n]);
+        }
+    }
+    if (DEP && k > 0.0f) dw.add(p, tab, plane, xn, yn, dsum);
+    x = xn;
+    y = yn;
+    z = zn;
+    m = mn;
+    led[3 * NNUC] += 1.0;
+    if (!(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z) &&
+          __builtin_isfinite(m)))
+        return 2;
+    // leaving the simulated area inactivates the particle
+    if (p.bounded && (x < p.X0 || x >= p.X1 || y < p.Y0 || y >= p.Y1)) {
+#pragma unroll
+        for (int n = 0; n < NNUC; ++n) led[3 * n + 2] += (double)(sv.a0 * m * D[n] * p.edec[n]);
+        m = 0.0f;
+        return 1;
+    }
+    return 0;
+}
 
-    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+// Adds one lane's ledger partials into a ledger slot (ensemble launches,
+// where lanes may hold different scenarios).
+template <int NNUC>
+__device__ __forceinline__ void lane_ledger(double (&led)[3 * NNUC + 1], double* slot)
+{
+#pragma unroll
+    for (int q = 0; q <= 3 * NNUC; ++q) {
+        const int off = q == 3 * NNUC ? LPM_LEDGER_PSTEPS : (q / 3) * 4 + 1 + q % 3;
+        if (led[q] != 0.0) atomicAdd(slot + off, led[q]);
+        led[q] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent step kernel.  The grid is sized to the resident capacity; every
+// lane takes particles from a queue of work indices (one atomic per wave and
+// refill) and carries each through the window, so a lane whose particle
+// leaves the area or stops picks up the next one.  Lanes of a wave therefore
+// hold particles at different steps; what they do per step is exactly one
+// call of advance().  In an ensemble launch (ENS) the queue runs over the
+// particles of all scenarios, each lane looks up its particle's scenario, and
+// deposition and ledger go to that scenario's accumulators.
+// ---------------------------------------------------------------------------
+template <int NCOMP, bool TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS>
+__global__ __launch_bounds__(kBlock) void step_kernel(const StepConst pk)
+{
+    constexpr int kWaves = kBlock / 64;
+    // The launch constants live in LDS: kept in SGPRs across the persistent
+    // loop they outnumber the scalar registers and spill to VGPR lanes.
+    __shared__ StepConst pc;
+    __shared__ long long scen_qbase[ENS ? LPM_MAX_SCENARIOS + 1 : 1];
+    if (threadIdx.x < sizeof(StepConst) / 4)
+        reinterpret_cast<uint32_t*>(&pc)[threadIdx.x] = reinterpret_cast<const uint32_t*>(&pk)[threadIdx.x];
+    if constexpr (ENS) {
+        for (int c = threadIdx.x; c <= pk.n_scen; c += kBlock)
+            scen_qbase[c] = c < pk.n_scen ? pk.scen[c].qbase : pk.i_hi;
+    }
+    __syncthreads();
+    const StepConst& p = pc;
+    __shared__ int tab_key[kWaves][DepTable<NNUC>::kSlots];
+    __shared__ double tab_val[kWaves][NNUC * DepTable<NNUC>::kSlots];
+    __shared__ int tab_used[kWaves];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    DepTable<NNUC> tab{tab_key[wv], tab_val[wv], &tab_used[wv]};
+    const long long plane = (long long)p.dnx * p.dny;
+    if constexpr (DEP) tab.init(lane);
+    __builtin_amdgcn_wave_barrier();
+
+    unsigned long long* queue = reinterpret_cast<unsigned long long*>(p.ctrl + LPM_CTRL_QUEUE);
+    float4* rec4 = reinterpret_cast<float4*>(p.rec);
+    int* rec_exit = reinterpret_cast<int*>(p.rec + 4ll * p.n_rec * p.rec_stride);
+    const int slot_index = blockIdx.x % LPM_LEDGER_SLOTS;
+
     double led[3 * NNUC + 1];  // deposited, decayed, exited per nuclide; steps
 #pragma unroll
     for (int q = 0; q <= 3 * NNUC; ++q) led[q] = 0.0;
 
-    if (i < p.i_hi) {
-        const long long gid = p.id_base + i * p.id_stride;
-        const long long b = birth(gid, p.s_release, p.n_total);
-        float m = p.M[i];
-        const int s0 = b > p.step0 ? (int)b : p.step0;
-        // next recorded step at or after the particle's first step here
-        int krec = s0 <= p.rec_step0 ? 0 : (s0 - p.rec_step0 + p.rec_every - 1) / p.rec_every;
-        int next_rec = krec < p.n_rec ? p.rec_step0 + krec * p.rec_every : INT_MAX;
-        if (m > 0.0f && b < p.step_end) {
-            float x = p.X[i], y = p.Y[i], z = p.Z[i];
-            bool bad = false;
-            int advanced = 0;
-            Dwell<NNUC> dw;
-            for (int s = s0; s < p.step_end; ++s) {
-                ++advanced;
-                const float age = (float)(s - (int)b) * p.dt;
-                // weather at the start-of-step position and time (Eq. 1): the
-                // loads are issued first; everything up to the interpolation
-                // below is independent of them
-                WindTap<NCOMP, TIME> tap;
-                wind_gather<NCOMP, TIME, LEVELS>(p, x, y, z, (float)s * p.dt, tap);
-                // random numbers of Eq. (2)
-                float xi0, xi1, xi2;
-                normals3((uint32_t)gid, (uint32_t)s, p.key0, p.key1, xi0, xi1, xi2);
-                // diffusivity (Eq. 3) with the drift and midpoint evaluation
-                float K, dK, Km, dKm;
-                kz_profile<KZ>(p, z, K, dK);
-                const float zm = clampf(fmaf(p.half_dt, dK, z), 0.0f, p.H_mix);
-                kz_profile<KZ>(p, zm, Km, dKm);
-                // decay factors of this step's start
-                float D[NNUC];
-#pragma unroll
-                for (int n = 0; n < NNUC; ++n) D[n] = exp2f(-p.lam_l2e[n] * age);
-                float uvw[3];
-                wind_interp<NCOMP, TIME>(tap, uvw);
-                // move (Eq. 1 with Eq. 2)
-                float xn = fmaf(xi0, p.sKh, fmaf(p.wscale * uvw[0], p.dt, x));
-                float yn = fmaf(xi1, p.sKh, fmaf(p.wscale * uvw[1], p.dt, y));
-                float zn = fmaf(xi2 * __builtin_amdgcn_sqrtf(Km), p.s2dt,
-                                fmaf(fmaf(p.wscale, uvw[2], dK), p.dt, z));
-                // reflection at the ground and the lid: one fold each, and the
-                // general fold-until-inside for the (never seen) larger steps
-                zn = fabsf(zn);
-                if (zn > p.H_top) zn = 2.0f * p.H_top - zn;
-                if (zn < 0.0f || zn > p.H_top) {
-#pragma unroll 1
-                    for (int it = 0; it < 64; ++it) {
-                        if (zn < 0.0f) zn = -zn;
-                        else if (zn > p.H_top) zn = 2.0f * p.H_top - zn;
-                        else break;
-                    }
-                }
-                // deposition rate at the new position (Sec. 2)
-                float k = 0.0f;
-                if constexpr (DEP) {
-                    if (zn < p.h_s) k = fmaxf(fmaf(-p.dry_c2, zn, p.dry_c1), 0.0f);
-                    if (p.L0 > 0.0f) k += wet_rate(p, xn, yn);
-                }
-                const float mn = k > 0.0f ? m * exp2f(-1.4426950408889634f * k * p.dt) : m;
-                // decay and deposition of each nuclide's activity this step
-                float dsum[NNUC];
-#pragma unroll
-                for (int n = 0; n < NNUC; ++n) {
-                    const float A = p.a0 * m * D[n];
-                    if (DEP && k > 0.0f) {
-                        // loss of activity this step, split by the rates
-                        const float r = p.lam[n] + k;
-                        const float loss = -A * expm1_neg(-r * p.dt);
-                        const float dep = loss * (k * __builtin_amdgcn_rcpf(r));
-                        dsum[n] = dep * p.dscale;
-                        led[3 * n + 0] += (double)dep;
-                        led[3 * n + 1] += (double)(loss - dep);
+    SrcVals sv{p.a0, p.wscale, p.dry_c1, p.dry_c2, p.key1, 0};
+    int led_scen = 0;  // scenario the ledger partials belong to
+    bool have = false, drained = false;
+    long long i = 0;
+    uint32_t gid = 0;
+    int b = 0, s = 0, krec = 0, next_rec = INT_MAX;
+    float x = 0.0f, y = 0.0f, z = 0.0f, m = 0.0f;
+    Dwell<NNUC> dw;
+
+    while (true) {
+        // hand the next queue entries to the lanes without a particle
+        while (!drained) {
+            const unsigned long long need = __ballot(!have);
+            // refill once enough lanes idle (keeps the lanes of a wave on
+            // particles released together, whose wind stencils overlap), or
+            // when the whole wave is idle
+            const int idle = __popcll(need);
+            if (need == 0ull || (idle < p.refill_min && need != __ballot(true))) break;
+            const int leader = __ffsll((long long)need) - 1;
+            const int cnt = __popcll(need);
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(queue, (unsigned long long)cnt);
+            base = __shfl(base, leader, 64);
+            if (base + (unsigned long long)cnt >= (unsigned long long)p.i_hi) drained = true;
+            if (!have) {
+                const int rank = __popcll(need & ((1ull << lane) - 1ull));
+                const long long q = (long long)(base + (unsigned long long)rank);
+                if (q < p.i_hi) {
+                    long long g;
+                    if constexpr (ENS) {
+                        // scenario of work index q: last c with qbase[c] <= q
+                        int lo = 0, hi = p.n_scen;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (scen_qbase[mid] <= q) lo = mid; else hi = mid;
+                        }
+                        const DevScen& ds = p.scen[lo];
+                        if (lo != led_scen) {
+                            lane_ledger<NNUC>(led, p.ledger + ((long long)led_scen * LPM_LEDGER_SLOTS + slot_index) * LPM_LEDGER_STRIDE);
+                            led_scen = lo;
+                        }
+                        sv = SrcVals{ds.a0, ds.wscale, ds.dry_c1, ds.dry_c2, ds.key1, lo};
+                        dw.key_base = (int)(lo * plane);
+                        g = q - ds.qbase;                  // local id of the scenario
+                        b = (int)birth(g, ds.s_release, ds.n_total);
+                        i = ds.offset + g;                 // element in the state arrays
                     } else {
-                        dsum[n] = 0.0f;
-                        led[3 * n + 1] += (double)(A * p.cdec[n]);
+                        i = q;
+                        g = p.id_base + q * p.id_stride;
+                        b = (int)birth(g, p.s_release, p.n_total);
+                    }
+                    gid = (uint32_t)g;
+                    m = p.M[i];
+                    if (m > 0.0f) {
+                        x = p.X[i];
+                        y = p.Y[i];
+                        z = p.Z[i];
+                        s = b > p.step0 ? b : p.step0;
+                        krec = s <= p.rec_step0 ? 0
+                                                : (s - p.rec_step0 + p.rec_every - 1) / p.rec_every;
+                        next_rec = krec < p.n_rec ? p.rec_step0 + krec * p.rec_every : INT_MAX;
+                        have = true;
+                    } else if (p.n_rec > 0) {
+                        rec_exit[i] = INT_MIN;  // inactive before this window
                     }
                 }
-                if (DEP && k > 0.0f) dw.add(p, tab, plane, xn, yn, dsum);
-                x = xn;
-                y = yn;
-                z = zn;
-                m = mn;
-                if (!(__builtin_isfinite(x) && __builtin_isfinite(y) &&
-                      __builtin_isfinite(z) && __builtin_isfinite(m))) {
-                    bad = true;
-                    break;
-                }
-                // leaving the simulated area inactivates the particle
-                const bool gone = p.bounded && (x < p.X0 || x >= p.X1 || y < p.Y0 || y >= p.Y1);
-                if (gone) {
-#pragma unroll
-                    for (int n = 0; n < NNUC; ++n)
-                        led[3 * n + 2] += (double)(p.a0 * m * D[n] * p.edec[n]);
-                    m = 0.0f;
-                }
-                // state after an output step, for gridding later
-                if (s == next_rec) {
-                    float* r = p.rec + 4ll * krec * p.rec_stride + i;
-                    r[0] = x;
-                    r[p.rec_stride] = y;
-                    r[2 * p.rec_stride] = z;
-                    r[3 * p.rec_stride] = m;
+            }
+        }
+        if (!__any(have)) break;
+        for (int j = 0; j < p.refill_every; ++j) {
+            if (have) {
+                const int st = advance<NCOMP, TIME, LEVELS, NNUC, KZ, DEP, ENS>(
+                    p, sv, tab, plane, gid, b, s, x, y, z, m, led, dw);
+                if (s == next_rec) {  // state after an output step, for gridding later
+                    rec4[(long long)krec * p.rec_stride + i] = make_float4(x, y, z, m);
                     ++krec;
                     next_rec = krec < p.n_rec ? p.rec_step0 + krec * p.rec_every : INT_MAX;
                 }
-                if (gone) break;
+                ++s;
+                if (st != 0 || s >= p.step_end) {
+                    if constexpr (DEP) dw.flush(p, tab, plane);
+                    p.X[i] = x;
+                    p.Y[i] = y;
+                    p.Z[i] = z;
+                    p.M[i] = m;
+                    if (p.n_rec > 0) rec_exit[i] = st != 0 ? s - 1 : INT_MAX;
+                    if (st == 2) atomicOr(p.ctrl + LPM_CTRL_ERR, 1u);
+                    have = false;
+                }
             }
-            if constexpr (DEP) dw.flush(p, tab, plane);
-            p.X[i] = x;
-            p.Y[i] = y;
-            p.Z[i] = z;
-            p.M[i] = m;
-            led[3 * NNUC] = (double)advanced;
-            if (bad) atomicOr(p.err, 1u);
         }
-        // records after the particle stopped (or of a particle already
-        // inactive): no activity
-        for (; krec < p.n_rec; ++krec) p.rec[(4ll * krec + 3) * p.rec_stride + i] = 0.0f;
+        if constexpr (DEP) tab.flush_if_half_full(lane, p.dep, plane);
     }
+    if constexpr (DEP) tab.flush(lane, p.dep, plane);
+
     // ledger slot: [nuclide][released, deposited, decayed, exited], steps
-    double* slot = p.ledger + (long long)(blockIdx.x % LPM_LEDGER_SLOTS) * LPM_LEDGER_STRIDE;
     constexpr int NV = 3 * NNUC + 1;
-    __shared__ double part[kBlock / 64][NV];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if constexpr (ENS) {
+        // lanes of a wave usually finish in one scenario: one atomic per entry
+        const int s0 = __shfl(led_scen, 0, 64);
+        double* slot = p.ledger + ((long long)led_scen * LPM_LEDGER_SLOTS + slot_index) * LPM_LEDGER_STRIDE;
+        if (__all(led_scen == s0)) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const double v = wave_sum(led[q]);
+                const int off = q == 3 * NNUC ? LPM_LEDGER_PSTEPS : (q / 3) * 4 + 1 + q % 3;
+                if (lane == 0 && v != 0.0) atomicAdd(slot + off, v);
+            }
+        } else {
+            lane_ledger<NNUC>(led, slot);
+        }
+        return;
+    }
+    double* slot = p.ledger + (long long)slot_index * LPM_LEDGER_STRIDE;
+    __shared__ double part[kWaves][NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-        const double s = wave_sum(led[q]);
-        if (lane == 0) part[wv][q] = s;
+        const double v = wave_sum(led[q]);
+        if (lane == 0) part[wv][q] = v;
     }
     __syncthreads();
     if (threadIdx.x < NV) {
-        double s = 0.0;
+        double v = 0.0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) s += part[w][threadIdx.x];
+        for (int w = 0; w < kWaves; ++w) v += part[w][threadIdx.x];
         const int q = threadIdx.x;
         const int off = q == 3 * NNUC ? LPM_LEDGER_PSTEPS : (q / 3) * 4 + 1 + q % 3;
-        if (s != 0.0) atomicAdd(slot + off, s);
+        if (v != 0.0) atomicAdd(slot + off, v);
     }
-    if constexpr (DEP) tab.flush(p.dep, plane);
 }
 
 // ---------------------------------------------------------------------------
@@ -359,6 +559,26 @@ __global__ __launch_bounds__(kBlock) void release_kernel(float* X, float* Y, flo
         M[i] = 1.0f;
     }
     if (blockIdx.x == 0 && threadIdx.x < n_nuc) atomicAdd(ledger + threadIdx.x * 4, released);
+}
+
+// Release of every scenario of an ensemble window: blockIdx.y = scenario.
+__global__ __launch_bounds__(kBlock) void release_ensemble_kernel(float* X, float* Y, float* Z,
+                                                                  float* M, const DevScen* scen,
+                                                                  double* ledgers, int n_nuc)
+{
+    const DevScen& d = scen[blockIdx.y];
+    const long long l = d.lo + (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (l < d.hi) {
+        const long long i = d.offset + l;
+        X[i] = d.xs;
+        Y[i] = d.ys;
+        Z[i] = d.h;
+        M[i] = 1.0f;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < n_nuc && d.hi > d.lo)
+        atomicAdd(ledgers + (long long)blockIdx.y * LPM_LEDGER_SLOTS * LPM_LEDGER_STRIDE +
+                      threadIdx.x * 4,
+                  d.released);
 }
 
 // ---------------------------------------------------------------------------
@@ -430,6 +650,71 @@ __global__ __launch_bounds__(kBlock) void conc_kernel(const GridConst g)
     tab.flush(g.acc, g.cells);
 }
 
+// Concentration of recorded states: blockIdx.y selects the record (output
+// step s_k); a record counts if the particle was born by s_k and still
+// active after it.
+template <int NNUC>
+__global__ __launch_bounds__(kBlock) void rec_conc_kernel(const GridConst g, const float4* rec,
+                                                          const int* last, long long rec_stride,
+                                                          int rec_step0, int rec_every)
+{
+    using Table = CellTable<NNUC, NNUC <= 2 ? 11 : 10>;
+    __shared__ int tab_key[Table::kSlots];
+    __shared__ double tab_val[NNUC * Table::kSlots];
+    Table tab{tab_key, tab_val};
+    tab.init();
+    __syncthreads();
+    const int k = blockIdx.y;
+    const int step = rec_step0 + k * rec_every;
+    double* acc = g.acc + (long long)k * NNUC * g.cells;
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    bool live = false;
+    long long b = 0;
+    float4 r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (i < g.i_hi) {
+        b = birth(g.id_base + i * g.id_stride, g.s_release, g.n_total);
+        if (b <= step && step < last[i]) {
+            r = rec[(long long)k * rec_stride + i];
+            live = r.w > 0.0f;
+        }
+    }
+    if (live) {
+        const float age = (float)(step + 1 - (int)b) * g.dt;
+        float A[NNUC];
+#pragma unroll
+        for (int n = 0; n < NNUC; ++n) A[n] = g.a0 * r.w * exp2f(-g.lam_l2e[n] * age) * g.scale;
+        const double fx = ((double)r.x - g.x0) * g.inv_dx;
+        const double fy = ((double)r.y - g.y0) * g.inv_dy;
+        const double fz = ((double)r.z - g.z0) * g.inv_dz;
+        if (g.mode == 0) {
+            const double ix = floor(fx), iy = floor(fy), iz = floor(fz);
+            if (ix >= 0.0 && iy >= 0.0 && iz >= 0.0 && ix < (double)g.nx && iy < (double)g.ny &&
+                iz < (double)g.nz)  // false for NaN
+                tab.add((int)(((long long)iz * g.ny + (long long)iy) * g.nx + (long long)ix), A,
+                        acc, g.cells);
+        } else {
+            const double ix = floor(fx - 0.5), iy = floor(fy - 0.5), iz = floor(fz - 0.5);
+            const float wx = (float)(fx - 0.5 - ix), wy = (float)(fy - 0.5 - iy);
+            const float wz = (float)(fz - 0.5 - iz);
+            for (int c = 0; c < 8; ++c) {
+                const double kx = ix + (c & 1), ky = iy + ((c >> 1) & 1), kz = iz + (c >> 2);
+                if (!(kx >= 0.0 && ky >= 0.0 && kz >= 0.0 && kx < (double)g.nx &&
+                      ky < (double)g.ny && kz < (double)g.nz))  // also skips NaN
+                    continue;
+                const float w = ((c & 1) ? wx : 1.0f - wx) * (((c >> 1) & 1) ? wy : 1.0f - wy) *
+                                ((c >> 2) ? wz : 1.0f - wz);
+                float v[NNUC];
+#pragma unroll
+                for (int n = 0; n < NNUC; ++n) v[n] = A[n] * w;
+                tab.add((int)(((long long)kz * g.ny + (long long)ky) * g.nx + (long long)kx), v,
+                        acc, g.cells);
+            }
+        }
+    }
+    __syncthreads();
+    tab.flush(acc, g.cells);
+}
+
 __global__ __launch_bounds__(kBlock) void fill_f64(double* p, long long n)
 {
     const long long stride = (long long)gridDim.x * kBlock;
@@ -458,6 +743,12 @@ __global__ __launch_bounds__(kBlock) void to_f32(const double* __restrict__ src,
 namespace {
 
 thread_local char g_msg[512] = "";
+
+// Launch tuning of the persistent step kernel (process-wide; set by the
+// autotuner or lpm_set_launch).
+int g_refill_every = 1;
+int g_refill_min = 1;
+int g_blocks_per_cu = 0;  // 0: as many as the device holds
 
 int fail(int code, const char* fmt, ...)
 {
@@ -542,9 +833,9 @@ int check_grid(const lpm_grid* g, bool two_d)
 
 int check_accum(const lpm_accum* acc)
 {
-    if (!acc || !acc->dep || !acc->ledger || !acc->err) return fail(LPM_EINVAL, "null accumulator");
+    if (!acc || !acc->dep || !acc->ledger || !acc->ctrl) return fail(LPM_EINVAL, "null accumulator");
     if (acc->n_nuc < 1 || acc->n_nuc > 4) return fail(LPM_EINVAL, "accumulator n_nuc must be 1..4");
-    if (((uintptr_t)acc->dep & 7u) || ((uintptr_t)acc->ledger & 7u) || !aligned4(acc->err))
+    if (((uintptr_t)acc->dep & 7u) || ((uintptr_t)acc->ledger & 7u) || ((uintptr_t)acc->ctrl & 7u))
         return fail(LPM_EINVAL, "misaligned accumulator");
     if ((double)acc->dep_grid.nx * acc->dep_grid.ny >= 2147483647.0)
         return fail(LPM_EINVAL, "deposition grid must have fewer than 2^31 - 1 cells");
@@ -569,6 +860,23 @@ const char* lpm_last_error(void) { return g_msg; }
 
 const char* lpm_version(void) { return "lpm 0.1 gfx950"; }
 
+int lpm_set_launch(int32_t refill_every, int32_t blocks_per_cu)
+{
+    return lpm_set_launch_ex(refill_every, blocks_per_cu, g_refill_min);
+}
+
+int lpm_set_launch_ex(int32_t refill_every, int32_t blocks_per_cu, int32_t refill_min)
+{
+    g_msg[0] = 0;
+    if (refill_every < 1 || refill_every > 4096 || blocks_per_cu < 0 || refill_min < 1 ||
+        refill_min > 64)
+        return fail(LPM_EINVAL, "refill_every in [1, 4096], blocks_per_cu >= 0, refill_min in [1, 64]");
+    g_refill_every = refill_every;
+    g_blocks_per_cu = blocks_per_cu;
+    g_refill_min = refill_min;
+    return LPM_OK;
+}
+
 int lpm_accum_reset(const lpm_accum* acc, lpm_stream stream)
 {
     g_msg[0] = 0;
@@ -581,7 +889,8 @@ int lpm_accum_reset(const lpm_accum* acc, lpm_stream stream)
     hipLaunchKernelGGL(lpm::fill_f64, dim3(blocks_for(LPM_LEDGER_SLOTS * LPM_LEDGER_STRIDE)),
                        dim3(lpm::kBlock), 0, s, acc->ledger,
                        (long long)LPM_LEDGER_SLOTS * LPM_LEDGER_STRIDE);
-    hipLaunchKernelGGL(lpm::fill_u32, dim3(1), dim3(lpm::kBlock), 0, s, acc->err, 1ll);
+    hipLaunchKernelGGL(lpm::fill_u32, dim3(1), dim3(lpm::kBlock), 0, s, acc->ctrl,
+                       (long long)LPM_CTRL_WORDS);
     return hip_status("lpm_accum_reset");
 }
 
@@ -651,11 +960,115 @@ int fill_field(lpm::StepConst& p, const lpm_field* f)
 
 // Compile-time variants: wind components, time interpolation, nonuniform
 // levels, nuclide count, K_z kind, deposition on/off.
-template <int NCOMP, bool TIME, bool LEV, int NNUC, int KZ>
+// Per-launch constants of the source (plain launches; ensemble launches take
+// them per lane from the scenario table).
+void fill_source(lpm::StepConst& p, const lpm_source* src, const lpm_schedule* sch,
+                 const lpm_physics* ph)
+{
+    p.xs = (float)src->xs; p.ys = (float)src->ys; p.h = (float)src->h;
+    p.a0 = (float)a0_of(src, sch, ph);
+    p.wscale = (float)src->wind_scale;
+    p.key1 = src->scenario;
+    if (src->v_d > 0.0 && ph->h_s > 0.0) {
+        p.dry_c1 = (float)(2.0 * src->v_d / ph->h_s);
+        p.dry_c2 = (float)(2.0 * src->v_d / (ph->h_s * ph->h_s));
+    }
+}
+
+void fill_physics(lpm::StepConst& p, const lpm_physics* ph)
+{
+    const double dt = ph->dt;
+    p.key0 = (uint32_t)(ph->seed & 0xFFFFFFFFull);
+    p.dt = (float)dt;
+    p.sKh = (float)sqrt(2.0 * ph->Kh * dt);
+    p.s2dt = (float)sqrt(2.0 * dt);
+    p.half_dt = (float)(0.5 * dt);
+    p.kz_kind = ph->kz_kind;
+    p.Kz_const = (float)ph->Kz_const;
+    p.ku = (float)ph->kappa_ustar;
+    p.z0 = (float)ph->z0;
+    p.H_mix = (float)ph->H_mix;
+    p.inv_Hmix = ph->H_mix > 0 ? (float)(1.0 / ph->H_mix) : 0.0f;
+    p.H_top = ph->H_lid > 0.0 ? (float)ph->H_lid : INFINITY;
+    p.h_s = ph->h_s > 0.0 ? (float)ph->h_s : 0.0f;
+    if (ph->Lambda0 > 0.0) {
+        p.L0 = (float)ph->Lambda0;
+        p.rcx = (float)ph->rain_cx; p.rcy = (float)ph->rain_cy;
+        const double ca = cos(ph->rain_angle), sa = sin(ph->rain_angle);
+        p.r_ca_a = (float)(ca / ph->rain_a); p.r_sa_a = (float)(sa / ph->rain_a);
+        p.r_ca_b = (float)(ca / ph->rain_b); p.r_sa_b = (float)(sa / ph->rain_b);
+        p.inv_edge = (float)(1.0 / ph->rain_edge);
+    }
+    for (int n = 0; n < ph->n_nuc; ++n) {
+        const double lam = ph->lambda[n];
+        p.lam[n] = (float)lam;
+        p.lam_l2e[n] = (float)(lam * 1.4426950408889634);
+        p.cdec[n] = (float)(-expm1(-lam * dt));
+        p.edec[n] = (float)exp(-lam * dt);
+    }
+}
+
+void fill_depgrid(lpm::StepConst& p, const lpm_grid& dg)
+{
+    p.dnx = dg.nx; p.dny = dg.ny; p.dmode = dg.mode;
+    p.dx0 = dg.x0; p.dy0 = dg.y0;
+    p.dinv_dx = 1.0 / dg.dx; p.dinv_dy = 1.0 / dg.dy;
+    p.dscale = dg.density ? (float)(1.0 / (dg.dx * dg.dy)) : 1.0f;
+}
+
+// Blocks of one persistent launch: at most what the device holds at once.
+template <typename K>
+unsigned resident_blocks(K kernel, unsigned wanted)
+{
+    static int per_cu = -1;  // one cache per kernel instance
+    int dev = 0;
+    hipGetDevice(&dev);
+    static int cus_dev = -1, cus = 0;
+    if (cus_dev != dev) {
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        cus_dev = dev;
+    }
+    if (per_cu < 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, lpm::kBlock, 0) != hipSuccess || n < 1)
+            n = 1;
+        per_cu = n;
+    }
+    const int use = g_blocks_per_cu > 0 && g_blocks_per_cu < per_cu ? g_blocks_per_cu : per_cu;
+    const unsigned cap = (unsigned)(use * (cus > 0 ? cus : 1));
+    return wanted < cap ? wanted : cap;
+}
+
+template <int NCOMP, bool TIME, bool LEV, int NNUC, int KZ, bool ENS = false>
 void launch_step_dep(bool dep, unsigned nb, hipStream_t s, const lpm::StepConst& p)
 {
-    if (dep) hipLaunchKernelGGL((lpm::step_kernel<NCOMP, TIME, LEV, NNUC, KZ, true>), dim3(nb), dim3(lpm::kBlock), 0, s, p);
-    else hipLaunchKernelGGL((lpm::step_kernel<NCOMP, TIME, LEV, NNUC, KZ, false>), dim3(nb), dim3(lpm::kBlock), 0, s, p);
+    if (dep) {
+        auto k = lpm::step_kernel<NCOMP, TIME, LEV, NNUC, KZ, true, ENS>;
+        hipLaunchKernelGGL(k, dim3(resident_blocks(k, nb)), dim3(lpm::kBlock), 0, s, p);
+    } else {
+        auto k = lpm::step_kernel<NCOMP, TIME, LEV, NNUC, KZ, false, ENS>;
+        hipLaunchKernelGGL(k, dim3(resident_blocks(k, nb)), dim3(lpm::kBlock), 0, s, p);
+    }
+}
+
+// Ensemble variants: two or three wind components, steady or hourly fields,
+// uniform levels, one or two nuclides.
+template <int NCOMP, bool TIME>
+void launch_ensemble(int nnuc, int kz, bool dep, unsigned nb, hipStream_t s, const lpm::StepConst& p)
+{
+    if (nnuc == 1) {
+        switch (kz) {
+        case 0: launch_step_dep<NCOMP, TIME, false, 1, 0, true>(dep, nb, s, p); break;
+        case 1: launch_step_dep<NCOMP, TIME, false, 1, 1, true>(dep, nb, s, p); break;
+        default: launch_step_dep<NCOMP, TIME, false, 1, 2, true>(dep, nb, s, p); break;
+        }
+    } else {
+        switch (kz) {
+        case 0: launch_step_dep<NCOMP, TIME, false, 2, 0, true>(dep, nb, s, p); break;
+        case 1: launch_step_dep<NCOMP, TIME, false, 2, 1, true>(dep, nb, s, p); break;
+        default: launch_step_dep<NCOMP, TIME, false, 2, 2, true>(dep, nb, s, p); break;
+        }
+    }
 }
 
 template <int NCOMP, bool TIME, bool LEV, int NNUC>
@@ -706,7 +1119,7 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
         return fail(LPM_EINVAL, "bad step window");
     if (n_rec < 0) return fail(LPM_EINVAL, "n_rec must be >= 0");
     if (n_rec > 0) {
-        if (!rec || !aligned4(rec)) return fail(LPM_EINVAL, "null or misaligned record buffer");
+        if (!rec || ((uintptr_t)rec & 15u)) return fail(LPM_EINVAL, "null or misaligned record buffer");
         if (rec_every < 1) return fail(LPM_EINVAL, "rec_every must be >= 1");
         if (rec_stride < sch->n_local) return fail(LPM_EINVAL, "rec_stride below n_local");
         const long long last = (long long)rec_step0 + (long long)(n_rec - 1) * rec_every;
@@ -716,6 +1129,8 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
     lpm::StepConst p;
     memset(&p, 0, sizeof p);
     if ((rc = fill_field(p, fld))) return rc;
+    p.refill_every = g_refill_every;
+    p.refill_min = g_refill_min;
     p.rec = n_rec > 0 ? rec : nullptr;
     p.rec_stride = rec_stride;
     p.rec_step0 = rec_step0;
@@ -729,54 +1144,16 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
     p.step_end = step0 + n_steps;
     p.i_hi = first_local_born_at_or_after(sch, (long long)p.step_end);
 
-    const double dt = ph->dt;
-    p.xs = (float)src->xs; p.ys = (float)src->ys; p.h = (float)src->h;
-    p.a0 = (float)a0_of(src, sch, ph);
-    p.wscale = (float)src->wind_scale;
-    p.key0 = (uint32_t)(ph->seed & 0xFFFFFFFFull);
-    p.key1 = src->scenario;
-
-    p.dt = (float)dt;
-    p.sKh = (float)sqrt(2.0 * ph->Kh * dt);
-    p.s2dt = (float)sqrt(2.0 * dt);
-    p.half_dt = (float)(0.5 * dt);
-    p.kz_kind = ph->kz_kind;
-    p.Kz_const = (float)ph->Kz_const;
-    p.ku = (float)ph->kappa_ustar;
-    p.z0 = (float)ph->z0;
-    p.H_mix = (float)ph->H_mix;
-    p.inv_Hmix = ph->H_mix > 0 ? (float)(1.0 / ph->H_mix) : 0.0f;
-    p.H_top = ph->H_lid > 0.0 ? (float)ph->H_lid : INFINITY;
-    if (src->v_d > 0.0 && ph->h_s > 0.0) {
-        p.dry_c1 = (float)(2.0 * src->v_d / ph->h_s);
-        p.dry_c2 = (float)(2.0 * src->v_d / (ph->h_s * ph->h_s));
-        p.h_s = (float)ph->h_s;
-    }
-    if (ph->Lambda0 > 0.0) {
-        p.L0 = (float)ph->Lambda0;
-        p.rcx = (float)ph->rain_cx; p.rcy = (float)ph->rain_cy;
-        const double ca = cos(ph->rain_angle), sa = sin(ph->rain_angle);
-        p.r_ca_a = (float)(ca / ph->rain_a); p.r_sa_a = (float)(sa / ph->rain_a);
-        p.r_ca_b = (float)(ca / ph->rain_b); p.r_sa_b = (float)(sa / ph->rain_b);
-        p.inv_edge = (float)(1.0 / ph->rain_edge);
-    }
-    for (int n = 0; n < ph->n_nuc; ++n) {
-        const double lam = ph->lambda[n];
-        p.lam[n] = (float)lam;
-        p.lam_l2e[n] = (float)(lam * 1.4426950408889634);
-        p.cdec[n] = (float)(-expm1(-lam * dt));
-        p.edec[n] = (float)exp(-lam * dt);
-    }
-    const lpm_grid& dg = acc->dep_grid;
-    p.dep = acc->dep; p.ledger = acc->ledger; p.err = acc->err;
-    p.dnx = dg.nx; p.dny = dg.ny; p.dmode = dg.mode;
-    p.dx0 = dg.x0; p.dy0 = dg.y0;
-    p.dinv_dx = 1.0 / dg.dx; p.dinv_dy = 1.0 / dg.dy;
-    p.dscale = dg.density ? (float)(1.0 / (dg.dx * dg.dy)) : 1.0f;
+    fill_source(p, src, sch, ph);
+    fill_physics(p, ph);
+    fill_depgrid(p, acc->dep_grid);
+    p.dep = acc->dep; p.ledger = acc->ledger; p.ctrl = acc->ctrl;
 
     if (p.i_hi <= 0) return LPM_OK;
     const unsigned nb = blocks_for(p.i_hi);
     hipStream_t s = (hipStream_t)stream;
+    // the work queue starts empty
+    hipLaunchKernelGGL(lpm::fill_u32, dim3(1), dim3(lpm::kBlock), 0, s, acc->ctrl + LPM_CTRL_QUEUE, 2ll);
     const bool time = fld->nt > 1;
     const bool dep = p.dry_c1 > 0.0f || p.L0 > 0.0f;
     const int kz = ph->kz_kind;
@@ -806,6 +1183,197 @@ int lpm_step_particles_record(const lpm_state* st, const lpm_source* src,
 {
     return step_impl(st, src, sch, fld, ph, step0, n_steps, acc, rec_step0, rec_every, n_rec, rec,
                      rec_stride, stream);
+}
+
+static_assert(sizeof(lpm::DevScen) <= LPM_SCENARIO_BYTES, "scenario table entry too large");
+
+int lpm_ensemble_prepare(const lpm_scenario* scen, int32_t n_scen, const lpm_state* st,
+                         const lpm_physics* ph, int32_t step0, int32_t n_steps, void* table,
+                         int64_t table_bytes, lpm_ensemble* out, lpm_stream stream)
+{
+    g_msg[0] = 0;
+    int rc;
+    if (!scen || !st || !out) return fail(LPM_EINVAL, "null argument");
+    if ((rc = check_physics(ph))) return rc;
+    if (n_scen < 1 || n_scen > LPM_MAX_SCENARIOS)
+        return fail(LPM_EINVAL, "n_scen must be in [1, %d]", LPM_MAX_SCENARIOS);
+    if (!table || ((uintptr_t)table & 15u) || table_bytes < (int64_t)n_scen * LPM_SCENARIO_BYTES)
+        return fail(LPM_EINVAL, "null, misaligned or small scenario table");
+    if (step0 < 0 || n_steps < 1 || (long long)step0 + n_steps > 0x7FFFFFFFll)
+        return fail(LPM_EINVAL, "bad step window");
+    if (!st->x || !st->y || !st->z || !st->m) return fail(LPM_EINVAL, "null state array");
+    std::vector<lpm::DevScen> t(n_scen);
+    std::vector<std::pair<long long, long long>> ranges;
+    long long q = 0, max_rel = 0;
+    for (int c = 0; c < n_scen; ++c) {
+        const lpm_scenario& e = scen[c];
+        if (e.n_total <= 0 || e.n_total > 0xFFFFFFFFll || e.s_release <= 0 || e.offset < 0 ||
+            e.offset + e.n_total > st->capacity)
+            return fail(LPM_EINVAL, "scenario %d: bad size, release steps or state range", c);
+        ranges.push_back({e.offset, e.offset + e.n_total});
+        lpm_schedule sch{e.n_total, e.n_total, 0, 1, e.s_release, 0};
+        lpm::DevScen& d = t[c];
+        memset(&d, 0, sizeof d);
+        d.qbase = q;
+        d.offset = e.offset;
+        d.n_total = e.n_total;
+        d.s_release = e.s_release;
+        d.i_hi = first_local_born_at_or_after(&sch, (long long)step0 + n_steps);
+        d.lo = first_local_born_at_or_after(&sch, step0);
+        d.hi = d.i_hi;
+        const double a0 = a0_of(&e.src, &sch, ph);
+        d.released = a0 * (double)(d.hi - d.lo);
+        d.a0 = (float)a0;
+        d.wscale = (float)e.src.wind_scale;
+        if (e.src.v_d > 0.0 && ph->h_s > 0.0) {
+            d.dry_c1 = (float)(2.0 * e.src.v_d / ph->h_s);
+            d.dry_c2 = (float)(2.0 * e.src.v_d / (ph->h_s * ph->h_s));
+        }
+        d.xs = (float)e.src.xs; d.ys = (float)e.src.ys; d.h = (float)e.src.h;
+        d.key1 = e.src.scenario;
+        q += d.i_hi;
+        if (d.hi - d.lo > max_rel) max_rel = d.hi - d.lo;
+    }
+    std::sort(ranges.begin(), ranges.end());
+    for (size_t k = 1; k < ranges.size(); ++k)
+        if (ranges[k].first < ranges[k - 1].second)
+            return fail(LPM_EINVAL, "scenario state ranges overlap");
+    if (hipMemcpyAsync(table, t.data(), sizeof(lpm::DevScen) * n_scen, hipMemcpyHostToDevice,
+                       (hipStream_t)stream) != hipSuccess ||
+        hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return hip_status("lpm_ensemble_prepare");
+    out->table = table;
+    out->n_scen = n_scen;
+    out->n_nuc = ph->n_nuc;
+    out->step0 = step0;
+    out->n_steps = n_steps;
+    out->queue_len = q;
+    out->max_release = max_rel;
+    return LPM_OK;
+}
+
+int lpm_release_ensemble(const lpm_state* st, const lpm_ensemble* ens, double* ledgers,
+                         lpm_stream stream)
+{
+    g_msg[0] = 0;
+    if (!st || !ens || !ens->table || !ledgers) return fail(LPM_EINVAL, "null argument");
+    if (ens->n_scen < 1 || ens->n_scen > LPM_MAX_SCENARIOS || ens->n_nuc < 1 || ens->n_nuc > 4)
+        return fail(LPM_EINVAL, "ensemble not prepared");
+    if (ens->max_release <= 0) return LPM_OK;
+    hipLaunchKernelGGL(lpm::release_ensemble_kernel,
+                       dim3(blocks_for(ens->max_release), (unsigned)ens->n_scen), dim3(lpm::kBlock),
+                       0, (hipStream_t)stream, st->x, st->y, st->z, st->m,
+                       (const lpm::DevScen*)ens->table, ledgers, ens->n_nuc);
+    return hip_status("lpm_release_ensemble");
+}
+
+int lpm_step_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_field* fld,
+                      const lpm_physics* ph, const lpm_grid* dep_grid, double* dep,
+                      double* ledgers, uint32_t* ctrl, lpm_stream stream)
+{
+    g_msg[0] = 0;
+    int rc;
+    if (!st || !ens || !ens->table || !dep || !ledgers || !ctrl) return fail(LPM_EINVAL, "null argument");
+    if (((uintptr_t)dep & 7u) || ((uintptr_t)ledgers & 7u) || ((uintptr_t)ctrl & 7u))
+        return fail(LPM_EINVAL, "misaligned accumulator");
+    if ((rc = check_physics(ph)) || (rc = check_grid(dep_grid, true))) return rc;
+    if (ph->n_nuc != ens->n_nuc) return fail(LPM_EINVAL, "physics and ensemble n_nuc differ");
+    if (ph->n_nuc > 2) return fail(LPM_EINVAL, "ensemble launches support one or two nuclides");
+    if ((double)dep_grid->nx * dep_grid->ny * ens->n_scen >= 2147483647.0)
+        return fail(LPM_EINVAL, "scenarios x deposition cells must stay below 2^31 - 1");
+    if (fld && fld->z_levels) return fail(LPM_EINVAL, "ensemble launches need uniform levels");
+    lpm::StepConst p;
+    memset(&p, 0, sizeof p);
+    if ((rc = fill_field(p, fld))) return rc;
+    fill_physics(p, ph);
+    fill_depgrid(p, *dep_grid);
+    p.refill_every = g_refill_every;
+    p.refill_min = g_refill_min;
+    p.rec_every = 1;
+    p.X = st->x; p.Y = st->y; p.Z = st->z; p.M = st->m;
+    p.step0 = ens->step0;
+    p.step_end = ens->step0 + ens->n_steps;
+    p.i_hi = ens->queue_len;
+    p.scen = (const lpm::DevScen*)ens->table;
+    p.n_scen = ens->n_scen;
+    p.dep = dep; p.ledger = ledgers; p.ctrl = ctrl;
+    if (p.i_hi <= 0) return LPM_OK;
+    // wet deposition, or dry deposition of any scenario (v_d is per scenario
+    // and only known to the device table here), selects the depositing variant
+    const bool dep_any = p.L0 > 0.0f || ph->h_s > 0.0;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(lpm::fill_u32, dim3(1), dim3(lpm::kBlock), 0, s, ctrl + LPM_CTRL_QUEUE, 2ll);
+    const unsigned nb = blocks_for(p.i_hi);
+    const int kz = ph->kz_kind;
+    if (fld->ncomp == 2) {
+        if (fld->nt > 1) launch_ensemble<2, true>(ph->n_nuc, kz, dep_any, nb, s, p);
+        else launch_ensemble<2, false>(ph->n_nuc, kz, dep_any, nb, s, p);
+    } else {
+        if (fld->nt > 1) launch_ensemble<3, true>(ph->n_nuc, kz, dep_any, nb, s, p);
+        else launch_ensemble<3, false>(ph->n_nuc, kz, dep_any, nb, s, p);
+    }
+    return hip_status("lpm_step_ensemble");
+}
+
+int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_scenario* scen,
+                          const lpm_field* fld, const lpm_physics* ph, const lpm_grid* dep_grid,
+                          double* dep, double* ledgers, uint32_t* ctrl, int32_t trial_steps,
+                          lpm_tuning* out, lpm_stream stream)
+{
+    g_msg[0] = 0;
+    if (!st || !ens || !scen || !out) return fail(LPM_EINVAL, "null argument");
+    if (trial_steps < 1 || trial_steps > ens->n_steps) return fail(LPM_EINVAL, "bad trial_steps");
+    hipStream_t s = (hipStream_t)stream;
+    const int refills[] = {1, 2, 4, 8};
+    const int occupancy[] = {0, 3, 2};
+    lpm_ensemble trial;
+    int rc = lpm_ensemble_prepare(scen, ens->n_scen, st, ph, ens->step0, trial_steps, ens->table,
+                                  (int64_t)ens->n_scen * LPM_SCENARIO_BYTES, &trial, stream);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return hip_status("lpm_autotune_ensemble");
+    const int keep_refill = g_refill_every, keep_bpc = g_blocks_per_cu;
+    double best = 1e300, worst = 0.0;
+    int best_r = keep_refill, best_o = keep_bpc, tried = 0;
+    for (int r : refills) {
+        for (int o : occupancy) {
+            g_refill_every = r;
+            g_blocks_per_cu = o;
+            for (int rep = 0; rep < 2; ++rep) {  // first repetition warms up
+                if ((rc = lpm_release_ensemble(st, &trial, ledgers, stream))) break;
+                hipEventRecord(e0, s);
+                if ((rc = lpm_step_ensemble(st, &trial, fld, ph, dep_grid, dep, ledgers, ctrl, stream))) break;
+                hipEventRecord(e1, s);
+            }
+            if (rc) break;
+            float ms = 0.0f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = hip_status("lpm_autotune_ensemble");
+                break;
+            }
+            ++tried;
+            if (ms < best) { best = ms; best_r = r; best_o = o; }
+            if (ms > worst) worst = ms;
+        }
+        if (rc) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    g_refill_every = rc ? keep_refill : best_r;
+    g_blocks_per_cu = rc ? keep_bpc : best_o;
+    if (rc) return rc;
+    // restore the caller's window in the table
+    lpm_ensemble again;
+    if ((rc = lpm_ensemble_prepare(scen, ens->n_scen, st, ph, ens->step0, ens->n_steps, ens->table,
+                                   (int64_t)ens->n_scen * LPM_SCENARIO_BYTES, &again, stream)))
+        return rc;
+    out->refill_every = best_r;
+    out->blocks_per_cu = best_o;
+    out->best_ms = best;
+    out->worst_ms = worst;
+    out->n_tried = tried;
+    return LPM_OK;
 }
 
 int lpm_grid_concentration(const lpm_state* st, const lpm_source* src, const lpm_schedule* sch,
@@ -857,6 +1425,64 @@ int lpm_grid_concentration(const lpm_state* st, const lpm_source* src, const lpm
     return hip_status("lpm_grid_concentration");
 }
 
+int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, int32_t rec_every,
+                     int32_t n_rec, const lpm_source* src, const lpm_schedule* sch,
+                     const lpm_physics* ph, const lpm_grid* grid, double* acc_scratch, float* out,
+                     lpm_stream stream)
+{
+    g_msg[0] = 0;
+    if (!src || !sch) return fail(LPM_EINVAL, "null source or schedule");
+    int rc;
+    if ((rc = check_physics(ph)) || (rc = check_grid(grid, false))) return rc;
+    if (sch->n_total <= 0 || sch->s_release <= 0 || sch->n_local < 0 || sch->id_stride <= 0)
+        return fail(LPM_EINVAL, "bad schedule");
+    if (n_rec < 0 || rec_every < 1 || rec_step0 < 0) return fail(LPM_EINVAL, "bad record steps");
+    if (n_rec == 0) return LPM_OK;
+    if (!rec || ((uintptr_t)rec & 15u)) return fail(LPM_EINVAL, "null or misaligned record buffer");
+    if (rec_stride < sch->n_local) return fail(LPM_EINVAL, "rec_stride below n_local");
+    if (!acc_scratch || !out || ((uintptr_t)acc_scratch & 7u) || !aligned4(out))
+        return fail(LPM_EINVAL, "null or misaligned grid buffers");
+    if ((long long)rec_step0 + (long long)(n_rec - 1) * rec_every > 0x7FFFFFFFll)
+        return fail(LPM_EINVAL, "record steps overflow");
+    if (n_rec > 65535) return fail(LPM_EINVAL, "at most 65535 records per call");
+    lpm::GridConst g;
+    memset(&g, 0, sizeof g);
+    g.n_total = sch->n_total; g.id_base = sch->id_base; g.id_stride = sch->id_stride;
+    g.s_release = sch->s_release;
+    g.nnuc = ph->n_nuc;
+    g.mode = grid->mode;
+    g.a0 = (float)a0_of(src, sch, ph);
+    g.dt = (float)ph->dt;
+    g.scale = 1.0f;
+    for (int n = 0; n < ph->n_nuc; ++n) g.lam_l2e[n] = (float)(ph->lambda[n] * 1.4426950408889634);
+    g.nx = grid->nx; g.ny = grid->ny; g.nz = grid->nz;
+    g.x0 = grid->x0; g.y0 = grid->y0; g.z0 = grid->z0;
+    g.inv_dx = 1.0 / grid->dx; g.inv_dy = 1.0 / grid->dy; g.inv_dz = 1.0 / grid->dz;
+    g.cells = (long long)grid->nx * grid->ny * grid->nz;
+    g.acc = acc_scratch;
+    // every particle that can be born by the last recorded step
+    g.i_hi = first_local_born_at_or_after(sch, (long long)rec_step0 + (long long)(n_rec - 1) * rec_every + 1);
+    const long long total = g.cells * ph->n_nuc * n_rec;
+    const double vol = grid->density ? grid->dx * grid->dy * grid->dz : 1.0;
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned fb = blocks_for(total) < 16384 ? blocks_for(total) : 16384;
+    hipLaunchKernelGGL(lpm::fill_f64, dim3(fb), dim3(lpm::kBlock), 0, s, acc_scratch, total);
+    if (g.i_hi > 0) {
+        const float4* r4 = reinterpret_cast<const float4*>(rec);
+        const int* last = reinterpret_cast<const int*>(rec + 4ll * n_rec * rec_stride);
+        const dim3 nb(blocks_for(g.i_hi), (unsigned)n_rec), bs(lpm::kBlock);
+        switch (ph->n_nuc) {
+        case 1: hipLaunchKernelGGL(lpm::rec_conc_kernel<1>, nb, bs, 0, s, g, r4, last, rec_stride, rec_step0, rec_every); break;
+        case 2: hipLaunchKernelGGL(lpm::rec_conc_kernel<2>, nb, bs, 0, s, g, r4, last, rec_stride, rec_step0, rec_every); break;
+        case 3: hipLaunchKernelGGL(lpm::rec_conc_kernel<3>, nb, bs, 0, s, g, r4, last, rec_stride, rec_step0, rec_every); break;
+        default: hipLaunchKernelGGL(lpm::rec_conc_kernel<4>, nb, bs, 0, s, g, r4, last, rec_stride, rec_step0, rec_every); break;
+        }
+    }
+    hipLaunchKernelGGL(lpm::to_f32, dim3(fb), dim3(lpm::kBlock), 0, s, acc_scratch, out, total,
+                       1.0 / vol);
+    return hip_status("lpm_grid_records");
+}
+
 int lpm_grid_deposition(const lpm_accum* acc, float* out, lpm_stream stream)
 {
     g_msg[0] = 0;
@@ -896,10 +1522,10 @@ int lpm_read_ledger(const lpm_accum* acc, double* host_out, lpm_stream stream)
 int lpm_check(const lpm_accum* acc, lpm_stream stream)
 {
     g_msg[0] = 0;
-    if (!acc || !acc->err) return fail(LPM_EINVAL, "null accumulator");
+    if (!acc || !acc->ctrl) return fail(LPM_EINVAL, "null accumulator");
     uint32_t e = 0;
     hipStream_t s = (hipStream_t)stream;
-    if (hipMemcpyAsync(&e, acc->err, sizeof e, hipMemcpyDeviceToHost, s) != hipSuccess ||
+    if (hipMemcpyAsync(&e, acc->ctrl + LPM_CTRL_ERR, sizeof e, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return hip_status("lpm_check");
     if (e & 1u) return fail(LPM_ENONFINITE, "a particle coordinate or mass became non-finite");

@@ -11,6 +11,19 @@
 
 namespace lpm {
 
+// One scenario of an ensemble launch, as uploaded to device memory.
+struct DevScen {
+    long long qbase;    // first work-queue index of the scenario
+    long long offset;   // first element in the combined state arrays
+    long long n_total;  // particles of the scenario
+    long long lo, hi;   // local ids released in the window
+    long long i_hi;     // local ids born before the window ends
+    double released;    // activity released per nuclide in the window
+    float a0, wscale, dry_c1, dry_c2, xs, ys, h;
+    uint32_t key1;
+    int s_release, pad;
+};
+
 // Per-launch constants, precomputed in double precision on the host and
 // rounded once to float.  Passed by value, so they live in SGPRs/the kernel
 // argument segment and cost no vector registers.
@@ -50,11 +63,16 @@ struct StepConst {
     // recorded states: plane q (x, y, z, m) of record k at rec + (4 k + q) rec_stride
     float* rec;
     long long rec_stride;
-    int rec_step0, rec_every, n_rec, pad3;
+    int rec_step0, rec_every, n_rec;
+    int refill_every;  // steps between work-queue refills of a wave
+    int refill_min;    // idle lanes a wave waits for before it refills
+    // ensemble launches: scenario table (device) and its length
+    const DevScen* scen;
+    int n_scen;
     // deposition grid and accumulators
     double* dep;
     double* ledger;
-    uint32_t* err;
+    uint32_t* ctrl;
     int dnx, dny, dmode, pad2;
     double dx0, dy0, dinv_dx, dinv_dy;
     float dscale;
@@ -65,10 +83,15 @@ struct StepConst {
 // key (k0, k1).  The two upper counter words are zero for the turbulence
 // stream, which removes one multiply from the first round.
 // ---------------------------------------------------------------------------
+template <bool UNIFORM_KEY>
 __device__ __forceinline__ void philox_10(uint32_t c0, uint32_t c1, uint32_t k0,
                                           uint32_t k1, uint32_t r[4])
 {
     uint32_t c2 = 0u, c3 = 0u;
+    if constexpr (UNIFORM_KEY) {  // one key for the whole launch: keep it scalar
+        k0 = __builtin_amdgcn_readfirstlane(k0);
+        k1 = __builtin_amdgcn_readfirstlane(k1);
+    }
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
@@ -81,16 +104,25 @@ __device__ __forceinline__ void philox_10(uint32_t c0, uint32_t c1, uint32_t k0,
         c2 = n2;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
-        // Keep the key schedule as two scalar registers updated per round:
-        // hoisting all twenty round keys out of the particle loop would
-        // exhaust the SGPRs and spill them to VGPR lanes.
-        asm volatile("" : "+s"(k0), "+s"(k1));
+        // Keep the key schedule as two registers updated per round: hoisting
+        // all twenty round keys out of the particle loop would exhaust the
+        // registers and spill.
+        if constexpr (UNIFORM_KEY) asm volatile("" : "+s"(k0), "+s"(k1));
+        else asm volatile("" : "+v"(k0), "+v"(k1));
     }
     r[0] = c0;
     r[1] = c1;
     r[2] = c2;
     r[3] = c3;
 }
+
+// Per-particle source values: uniform over a plain launch, per lane in an
+// ensemble launch (each lane may hold a particle of another scenario).
+struct SrcVals {
+    float a0, wscale, dry_c1, dry_c2;
+    uint32_t key1;
+    int scen;
+};
 
 // Uniform in (0, 1] on the 2^-24 lattice: exact in float.
 __device__ __forceinline__ float lattice_uniform(uint32_t r)
@@ -101,12 +133,13 @@ __device__ __forceinline__ float lattice_uniform(uint32_t r)
 // Three standard normals (Eq. 2) by the trigonometric Box-Muller form.
 // v_log_f32 is log2 and v_sin/v_cos take the angle in revolutions, so
 // 2 pi u needs no multiply and no range reduction.
+template <bool UNIFORM_KEY>
 __device__ __forceinline__ void normals3(uint32_t id, uint32_t step, uint32_t k0,
                                          uint32_t k1, float& xi0, float& xi1,
                                          float& xi2)
 {
     uint32_t r[4];
-    philox_10(id, step, k0, k1, r);
+    philox_10<UNIFORM_KEY>(id, step, k0, k1, r);
     const float m2ln2 = -1.3862943611198906f;  // -2 ln 2
     const float u0 = lattice_uniform(r[0]);
     const float u1 = lattice_uniform(r[1]);

@@ -11,9 +11,11 @@ from typing import Callable, Iterable, Optional
 import numpy as np
 import torch
 
-from . import (Accum, Field, Grid, Physics, Schedule, Source, State, LEDGER_SLOTS, LEDGER_STRIDE,
-               accum_reset, grid_concentration, grid_deposition, read_ledger,
-               release_particles, step_particles, step_particles_record, check)
+from . import (Accum, Field, Grid, Physics, Schedule, Scenario, Source, State, CTRL_WORDS,
+               LEDGER_SLOTS, LEDGER_STRIDE, SCENARIO_BYTES, accum_reset, autotune_ensemble,
+               ensemble_prepare, grid_concentration, grid_deposition, grid_records, read_ledger,
+               release_ensemble, release_particles, step_ensemble, step_particles,
+               step_particles_record, check)
 
 
 def make_source(src) -> Source:
@@ -68,8 +70,8 @@ class DeviceRun:
         nn = ph.n_nuc
         self.dep = torch.zeros((nn, dg.ny, dg.nx), **f64)
         self.ledger_buf = torch.zeros((LEDGER_SLOTS, LEDGER_STRIDE, 4, 4), **f64)
-        self.err = torch.zeros(1, dtype=torch.int32, device=self.device)
-        self.acc = Accum(self.dep.data_ptr(), self.ledger_buf.data_ptr(), self.err.data_ptr(),
+        self.ctrl = torch.zeros(CTRL_WORDS, dtype=torch.int32, device=self.device)
+        self.acc = Accum(self.dep.data_ptr(), self.ledger_buf.data_ptr(), self.ctrl.data_ptr(),
                          nn, 0, make_grid(dg))
         self.cgrid = make_grid(cg)
         self.conc_scratch = torch.empty((nn, cg.nz, cg.ny, cg.nx), **f64)
@@ -126,18 +128,23 @@ class DeviceRun:
         return max(self.sch.n_local, 1)
 
     def record_buffer(self, n_rec: int) -> torch.Tensor:
-        return torch.empty(4 * n_rec * self.rec_stride, dtype=torch.float32,
+        """Records of n_rec output steps: float4 per particle and step, then
+        one int32 per particle (see lpm_step_particles_record)."""
+        return torch.empty((4 * n_rec + 1) * self.rec_stride, dtype=torch.float32,
                            device=self.device)
 
-    def recorded_state(self, rec: torch.Tensor, k: int) -> State:
-        base = rec.data_ptr() + 4 * k * 4 * self.rec_stride
-        plane = 4 * self.rec_stride
-        return State(base, base + plane, base + 2 * plane, base + 3 * plane, self.rec_stride)
+    def grid_buffers(self, n_rec: int):
+        cg, nn = self.case.conc_grid, self.case.physics.n_nuc
+        shape = (n_rec, nn, cg.nz, cg.ny, cg.nx)
+        return (torch.empty(shape, dtype=torch.float64, device=self.device),
+                torch.empty(shape, dtype=torch.float32, device=self.device))
 
-    def grid_recorded(self, rec: torch.Tensor, k: int, step: int) -> torch.Tensor:
-        grid_concentration(self.recorded_state(rec, k), self.src, self.sch, self.ph, self.cgrid,
-                           step, self.conc_scratch, self.conc)
-        return self.conc
+    def grid_records(self, rec: torch.Tensor, rec_step0: int, every: int, n_rec: int,
+                     bufs=None):
+        scratch, out = bufs if bufs is not None else self.grid_buffers(n_rec)
+        grid_records(rec, self.rec_stride, rec_step0, every, n_rec, self.src, self.sch, self.ph,
+                     self.cgrid, scratch, out)
+        return out
 
     # -- the host main loop -------------------------------------------------
     def windows(self, s_begin: int, s_end: int, steps_per_launch: int,
@@ -154,33 +161,29 @@ class DeviceRun:
         return out
 
     def run_whole(self, s_begin: int = 0, s_end: Optional[int] = None, every: int = 60,
-                  on_snapshot: Optional[Callable] = None, rec: Optional[torch.Tensor] = None):
-        """Whole window [s_begin, s_end) in one step launch: each thread carries
-        its particle through every step; the states after the output steps
-        s_begin + every - 1, s_begin + 2 every - 1, ... (and s_end - 1) are
-        recorded and gridded afterwards (results equal the windowed run)."""
+                  on_snapshot: Optional[Callable] = None):
+        """Whole window [s_begin, s_end) in one step launch: each particle is
+        carried through every step; the states after the output steps
+        s_begin + every - 1, s_begin + 2 every - 1, ... are recorded and
+        gridded afterwards, and the final step is gridded from the state
+        (results equal the windowed run)."""
         s_end = self.case.n_steps if s_end is None else s_end
-        steps = list(range(s_begin + every - 1, s_end, every))
-        if not steps or steps[-1] != s_end - 1:
-            steps.append(s_end - 1)
-        regular = [s for s in steps if (s - s_begin + 1) % every == 0]
+        regular = list(range(s_begin + every - 1, s_end, every))
         n_rec = len(regular)
-        if rec is None or rec.numel() < 4 * n_rec * self.rec_stride:
-            rec = self.record_buffer(max(n_rec, 1))
         self.release(s_begin, s_end - s_begin)
         if n_rec:
+            rec = self.record_buffer(n_rec)
             self.step_record(s_begin, s_end - s_begin, regular[0], every, n_rec, rec)
+            grids = self.grid_records(rec, regular[0], every, n_rec)
+            if on_snapshot is not None:
+                for k, s in enumerate(regular):
+                    on_snapshot(s, grids[k])
         else:
             self.step(s_begin, s_end - s_begin)
-        for k, s in enumerate(regular):
-            g = self.grid_recorded(rec, k, s)
+        if not regular or regular[-1] != s_end - 1:
+            g = self.grid_concentration(s_end - 1)
             if on_snapshot is not None:
-                on_snapshot(s, g)
-        if steps[-1] not in regular:
-            g = self.grid_concentration(steps[-1])
-            if on_snapshot is not None:
-                on_snapshot(steps[-1], g)
-        return rec
+                on_snapshot(s_end - 1, g)
 
     def run(self, s_begin: int = 0, s_end: Optional[int] = None, steps_per_launch: int = 60,
             snap_steps: Iterable[int] = (), on_snapshot: Optional[Callable] = None,
@@ -198,3 +201,97 @@ class DeviceRun:
                 g = self.grid_concentration(b - 1)
                 if on_snapshot is not None:
                     on_snapshot(b - 1, g)
+
+
+def _field_struct(fld, device):
+    data = torch.from_numpy(np.ascontiguousarray(fld.data)).to(device)
+    lev = None
+    if fld.z_levels is not None:
+        lev = torch.from_numpy(np.ascontiguousarray(fld.z_levels)).to(device)
+    st = Field(data.data_ptr(), lev.data_ptr() if lev is not None else None, fld.nx, fld.ny,
+               fld.nz, fld.nt, fld.ncomp, int(fld.bounded), fld.x0, fld.y0, fld.dx, fld.dy,
+               fld.dz, fld.t0, fld.dt_field)
+    return st, data, lev
+
+
+class EnsembleRun:
+    """Device buffers for an ensemble of release scenarios sharing one wind
+    field and physics (``base``, a ``synth.Case``): ``sources`` and
+    ``counts`` give each scenario's source and particle count; every scenario
+    releases over ``base.schedule.s_release`` steps."""
+
+    def __init__(self, base, sources, counts, device: str = "cuda"):
+        self.base = base
+        self.device = torch.device(device)
+        n_scen = len(sources)
+        assert n_scen == len(counts) and n_scen >= 1
+        self.counts = [int(c) for c in counts]
+        self.offsets = np.concatenate([[0], np.cumsum(self.counts)[:-1]]).astype(np.int64)
+        total = int(sum(self.counts))
+        self.total = total
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.x = torch.zeros(total, **f32)
+        self.y = torch.zeros(total, **f32)
+        self.z = torch.zeros(total, **f32)
+        self.m = torch.zeros(total, **f32)
+        self.st = State(self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr(),
+                        self.m.data_ptr(), total)
+        self.fld, self._fdata, self._flev = _field_struct(base.field, self.device)
+        self.ph = make_physics(base.physics)
+        self.scen = (Scenario * n_scen)()
+        for c, (src, n) in enumerate(zip(sources, self.counts)):
+            self.scen[c] = Scenario(make_source(src), n, base.schedule.s_release, 0,
+                                    int(self.offsets[c]))
+        self.n_scen = n_scen
+        dg = base.dep_grid
+        nn = base.physics.n_nuc
+        self.dgrid = make_grid(dg)
+        self.dep = torch.zeros((n_scen, nn, dg.ny, dg.nx), dtype=torch.float64, device=self.device)
+        self.ledgers = torch.zeros((n_scen, LEDGER_SLOTS, LEDGER_STRIDE), dtype=torch.float64,
+                                   device=self.device)
+        self.ctrl = torch.zeros(CTRL_WORDS, dtype=torch.int32, device=self.device)
+        self.table = torch.zeros(n_scen * SCENARIO_BYTES // 8, dtype=torch.float64,
+                                 device=self.device)
+        self.ens = None
+
+    def prepare(self, step0: int = 0, n_steps: Optional[int] = None):
+        n_steps = self.base.n_steps - step0 if n_steps is None else n_steps
+        self.ens = ensemble_prepare(self.scen, self.n_scen, self.st, self.ph, step0, n_steps,
+                                    self.table)
+        return self.ens
+
+    def reset(self):
+        self.m.zero_()
+        self.dep.zero_()
+        self.ledgers.zero_()
+        self.ctrl.zero_()
+
+    def release(self):
+        release_ensemble(self.st, self.ens, self.ledgers)
+
+    def step(self):
+        step_ensemble(self.st, self.ens, self.fld, self.ph, self.dgrid, self.dep, self.ledgers,
+                      self.ctrl)
+
+    def autotune(self, trial_steps: int):
+        t = autotune_ensemble(self.st, self.ens, self.scen, self.fld, self.ph, self.dgrid,
+                              self.dep, self.ledgers, self.ctrl, trial_steps)
+        self.reset()
+        return t
+
+    def run(self):
+        self.reset()
+        self.release()
+        self.step()
+
+    def ledger(self, c: int) -> np.ndarray:
+        L = self.ledgers[c].sum(dim=0).cpu().numpy()
+        nn = self.base.physics.n_nuc
+        return np.array([[L[n * 4 + e] for e in range(4)] for n in range(nn)])
+
+    def particle_steps(self) -> int:
+        return int(self.ledgers[:, :, 16].sum().item())
+
+    def state(self, c: int):
+        a, n = int(self.offsets[c]), self.counts[c]
+        return {k: getattr(self, k)[a:a + n].double().cpu().numpy() for k in "xyzm"}

@@ -32,7 +32,7 @@ import numpy as np
 
 __all__ = [
     "Source", "Schedule", "Physics", "Rain", "Field", "Grid", "Case",
-    "c0", "c1", "c2", "wind_field", "rain_region", "uniform_field",
+    "c0", "c1", "c2", "c3", "wind_field", "rain_region", "uniform_field",
     "uniform_state", "replace",
 ]
 
@@ -331,6 +331,25 @@ def c2(n_total: int = 16_000_000, n_steps: int = 17280, s_release: int = 4320,
               density=True)
     return Case("c2", src, sch, _gridded_physics(rain), fld, g3, g2, n_steps,
                 out_every=60)
+
+
+def c3(seed: int = 3, n_scen: int = 64, n_steps: int = 4320, scale: float = 1.0):
+    """Ensemble of release scenarios on the gridded 6 h workload: per
+    scenario a particle count log-uniform in [1e4, 1e6] (times ``scale``),
+    source height U(10, 200) m, release rate U(0.5, 2) and wind scale
+    U(0.8, 1.2), drawn as whole vectors in that order from ``seed``; the
+    scenario index is the Philox scenario key.  Returns (base case, sources,
+    counts)."""
+    rng = np.random.default_rng(seed)
+    counts = np.round(10.0 ** rng.uniform(4.0, 6.0, n_scen) * scale).astype(np.int64)
+    counts = np.maximum(counts, 1)
+    h = rng.uniform(10.0, 200.0, n_scen)
+    q = rng.uniform(0.5, 2.0, n_scen)
+    sw = rng.uniform(0.8, 1.2, n_scen)
+    base = c1(n_total=int(counts.max()), n_steps=n_steps)
+    sources = [replace(base.source, h=float(h[c]), q=float(q[c]), wind_scale=float(sw[c]),
+                       scenario=c) for c in range(n_scen)]
+    return base, sources, [int(n) for n in counts]
 
 
 def uniform_state(n: int, box, seed: int):

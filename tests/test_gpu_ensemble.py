@@ -1,0 +1,115 @@
+"""Ensembles of release scenarios in one persistent launch: every scenario's
+trajectories equal its plain run, accumulators equal up to FP64 summation
+order, the autotuner changes no result, and a captured graph replays the
+eager run."""
+import numpy as np
+import pytest
+
+import synth
+from parity import distances, ledger_ok, log, rel_l2_masked, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0912_3223_amd  # noqa: F401
+
+
+def small_ensemble(n_scen=8, steps=600):
+    base, sources, counts = synth.c3(n_scen=n_scen, n_steps=steps, scale=0.01)
+    base = base.with_(schedule=synth.replace(base.schedule, s_release=steps))
+    return base, sources, counts
+
+
+def plain_case(base, src, n):
+    return base.with_(source=src, schedule=synth.Schedule(n_total=n, s_release=base.schedule.s_release))
+
+
+def plain_run(case):
+    import paper_0912_3223_amd as L
+    r = L.DeviceRun(case)
+    r.release(0, case.n_steps)
+    r.step(0, case.n_steps)
+    return r
+
+
+def test_ensemble_equals_plain_runs():
+    import paper_0912_3223_amd as L
+    base, sources, counts = small_ensemble()
+    e = L.EnsembleRun(base, sources, counts)
+    e.prepare()
+    e.run()
+    for c, (src, n) in enumerate(zip(sources, counts)):
+        r = plain_run(plain_case(base, src, n))
+        a, b = e.state(c), r.state()
+        for k in "xyzm":
+            np.testing.assert_array_equal(a[k], b[k], err_msg=f"scenario {c} {k}")
+        np.testing.assert_allclose(e.ledger(c), r.ledger(), rtol=1e-9, atol=1e-12)
+        dep = e.dep[c].cpu().numpy()
+        np.testing.assert_allclose(dep, r.dep.cpu().numpy(), rtol=1e-6, atol=1e-12 * max(np.abs(dep).max(), 1e-300))
+    log("ensemble of %d scenarios (%d particles) equals its plain runs" % (len(counts), sum(counts)))
+
+
+def test_ensemble_scenario_matches_oracle():
+    import paper_0912_3223_amd as L
+    base, sources, counts = small_ensemble(n_scen=4)
+    e = L.EnsembleRun(base, sources, counts)
+    e.prepare()
+    e.run()
+    c = int(np.argmax(counts))
+    case = plain_case(base, sources[c], counts[c])
+    o = run_oracle(case)
+    st = e.state(c)
+    act = (o["state"]["m"] > 0) | (st["m"] > 0)
+    d = distances(st, o["state"], act)
+    reld, _ = rel_l2_masked(e.dep[c].cpu().numpy(), o["dep"])
+    log("ensemble scenario %d vs oracle: P1 mean %.3e max %.3e, dep rel %.3e" % (c, d.mean(), d.max(), reld))
+    assert d.mean() <= 0.05 and np.quantile(d, 0.999) <= 1.0
+    assert reld <= 1e-4
+    ledger_ok(e.ledger(c), o["ledger"], o["ledger"][0][0])
+
+
+def test_autotuner_changes_no_result():
+    import paper_0912_3223_amd as L
+    base, sources, counts = small_ensemble(n_scen=6)
+    e = L.EnsembleRun(base, sources, counts)
+    e.prepare()
+    e.run()
+    ref = [e.state(c) for c in range(6)]
+    t = e.autotune(trial_steps=60)
+    log("autotune: refill %d blocks/cu %d best %.3f ms worst %.3f ms (%d tried)"
+        % (t.refill_every, t.blocks_per_cu, t.best_ms, t.worst_ms, t.n_tried))
+    assert t.n_tried == 12 and t.best_ms <= t.worst_ms
+    e.run()
+    for c in range(6):
+        for k in "xyzm":
+            np.testing.assert_array_equal(e.state(c)[k], ref[c][k])
+    L.set_launch(1, 0)
+
+
+def test_graph_capture_replays():
+    import torch
+    import paper_0912_3223_amd as L
+    base, sources, counts = small_ensemble(n_scen=5, steps=300)
+    e = L.EnsembleRun(base, sources, counts)
+    e.prepare()
+    e.run()
+    torch.cuda.synchronize()
+    want = [e.state(c) for c in range(5)]
+    want_led = [e.ledger(c) for c in range(5)]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        e.run()
+    for rep in range(3):
+        e.reset()                      # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for c in range(5):
+            for k in "xyzm":
+                np.testing.assert_array_equal(e.state(c)[k], want[c][k])
+            np.testing.assert_allclose(e.ledger(c), want_led[c], rtol=1e-9, atol=1e-12)
