@@ -93,8 +93,8 @@ def ensemble_vs_plain(a):
         e.run()
     torch.cuda.synchronize()
     batched = (time.perf_counter() - t0) / a.ensemble_steps
-    tuned = (tune.refill_every, tune.blocks_per_cu)
-    L.set_launch(1, 0)
+    tuned = (tune.refill_every, tune.blocks_per_cu, tune.refill_min)
+    L.set_launch()
     runs = []
     for src, n in zip(sources, counts):
         case = base.with_(source=src, schedule=synth.Schedule(n_total=n, s_release=base.n_steps))
@@ -115,7 +115,7 @@ def ensemble_vs_plain(a):
         sequential()
     torch.cuda.synchronize()
     seq = (time.perf_counter() - t0) / a.ensemble_steps
-    L.set_launch(1, 0)
+    L.set_launch()
     return {"workload": "64 scenarios, counts log-uniform in [1e4, 1e6] (seed 3), heights "
                         "U(10,200) m, rates U(0.5,2), wind scale U(0.8,1.2), shared 200x200x30 "
                         "field, 4320 steps",
@@ -124,7 +124,8 @@ def ensemble_vs_plain(a):
             "batched_particle_steps_per_s": ps / batched,
             "sequential_particle_steps_per_s": ps_plain / seq,
             "speedup_batched_vs_sequential": seq / batched,
-            "autotuned": {"refill_every": tune.refill_every, "blocks_per_cu": tune.blocks_per_cu,
+            "autotuned": {"refill_every": tune.refill_every, "refill_min": tune.refill_min,
+                          "blocks_per_cu": tune.blocks_per_cu,
                           "best_trial_ms": tune.best_ms, "worst_trial_ms": tune.worst_ms}}
 
 

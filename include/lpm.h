@@ -260,13 +260,15 @@ int lpm_check(const lpm_accum* acc, lpm_stream stream);
 const char* lpm_last_error(void);
 
 /* Launch tuning of the step kernels (process-wide): a wave refills idle
- * lanes from the work queue every `refill_every` steps (default 1), and at
+ * lanes from the work queue every `refill_every` steps (default 16), and at
  * most `blocks_per_cu` blocks per compute unit are launched (0 = as many as
  * fit).  Results do not depend on either. */
 int lpm_set_launch(int32_t refill_every, int32_t blocks_per_cu);
 
 /* lpm_set_launch, and a wave refills only once at least `refill_min` of its
- * 64 lanes are idle (or all of them; default 1). */
+ * 64 lanes are idle (or all of them; default 64: a wave takes new particles
+ * only once all its lanes are idle, which keeps particles released together
+ * in one wave). */
 int lpm_set_launch_ex(int32_t refill_every, int32_t blocks_per_cu, int32_t refill_min);
 
 /* ---------------------------------------------------------------------------
@@ -331,12 +333,13 @@ typedef struct {
     double best_ms;   /* trial time of the chosen setting */
     double worst_ms;  /* trial time of the slowest setting */
     int32_t n_tried;
-    int32_t reserved;
+    int32_t refill_min;
 } lpm_tuning;
 
 /* Autotuner: time the ensemble step over the first `trial_steps` steps of
- * the prepared window for each candidate (refill interval x blocks per
- * compute unit), keep the fastest (installed with lpm_set_launch) and report
+ * the prepared window for each candidate (queue schedule, i.e. refill
+ * interval and idle lanes before a refill, x blocks per compute unit), keep
+ * the fastest (installed with lpm_set_launch_ex) and report
  * it.  It runs release and step on the given buffers, so state, dep, ledgers
  * and ctrl must be reset and the particles released again afterwards.
  * Synchronises `stream`. */

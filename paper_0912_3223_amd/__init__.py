@@ -86,7 +86,7 @@ class Ensemble(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("refill_every", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("best_ms", C.c_double), ("worst_ms", C.c_double), ("n_tried", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("refill_min", C.c_int32)]
 
 
 class Accum(C.Structure):
@@ -263,7 +263,7 @@ def autotune_ensemble(st: State, ens: Ensemble, scen, fld: Field, ph: Physics, d
     return t
 
 
-def set_launch(refill_every: int = 1, blocks_per_cu: int = 0, refill_min: int = 1):
+def set_launch(refill_every: int = 16, blocks_per_cu: int = 0, refill_min: int = 64):
     _rc(_lib.lpm_set_launch_ex(refill_every, blocks_per_cu, refill_min))
 
 

@@ -217,9 +217,12 @@ struct Dwell {
         for (int c = 0; c < ncorner; ++c) {
             const int ii = i0 + (c & 1), jj = j0 + (c >> 1);
             if (ii < 0 || jj < 0 || ii >= p.dnx || jj >= p.dny) continue;
+            // corner values by selects: a dynamic index into acc would put
+            // the array in scratch memory
             float v[NNUC];
 #pragma unroll
-            for (int n = 0; n < NNUC; ++n) v[n] = acc[n][c];
+            for (int n = 0; n < NNUC; ++n)
+                v[n] = c == 0 ? acc[n][0] : c == 1 ? acc[n][1] : c == 2 ? acc[n][2] : acc[n][3];
             tab.add(key_base + jj * p.dnx + ii, v, p.dep, plane);
         }
         i0 = INT_MIN;
@@ -290,7 +293,7 @@ __device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
     // decay factors at the start of the step
     float D[NNUC];
 #pragma unroll
-    for (int n = 0; n < NNUC; ++n) D[n] = exp2f(-p.lam_l2e[n] * age);
+    for (int n = 0; n < NNUC; ++n) D[n] = __builtin_amdgcn_exp2f(-p.lam_l2e[n] * age);
     float uvw[3];
     wind_interp<NCOMP, TIME>(tap, uvw);
     // move (Eq. 1 with Eq. 2)
@@ -316,17 +319,18 @@ __device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
         if (zn < p.h_s) k = fmaxf(fmaf(-sv.dry_c2, zn, sv.dry_c1), 0.0f);
         if (p.L0 > 0.0f) k += wet_rate(p, xn, yn);
     }
-    const float mn = k > 0.0f ? m * exp2f(-1.4426950408889634f * k * p.dt) : m;
+    const float mn = k > 0.0f ? m * __builtin_amdgcn_exp2f(-1.4426950408889634f * k * p.dt) : m;
     // decay and deposition of each nuclide's activity this step
     float dsum[NNUC];
 #pragma unroll
     for (int n = 0; n < NNUC; ++n) {
         const float A = sv.a0 * m * D[n];
-        if (DEP && k > 0.0f) {
-            // loss of activity this step, split by the rates
+        if constexpr (DEP) {
+            // loss of activity this step, split by the rates (no branch on
+            // k: lanes with and without deposition share the wave)
             const float r = p.lam[n] + k;
             const float loss = -A * expm1_neg(-r * p.dt);
-            const float dep = loss * (k * __builtin_amdgcn_rcpf(r));
+            const float dep = k > 0.0f ? loss * (k * __builtin_amdgcn_rcpf(r)) : 0.0f;
             dsum[n] = dep * p.dscale;
             led[3 * n + 0] += (double)dep;
             led[3 * n + 1] += (double)(loss - dep);
@@ -463,18 +467,18 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepConst pk)
                         b = (int)birth(g, p.s_release, p.n_total);
                     }
                     gid = (uint32_t)g;
-                    m = p.M[i];
+                    m = as_global(p.M)[i];
                     if (m > 0.0f) {
-                        x = p.X[i];
-                        y = p.Y[i];
-                        z = p.Z[i];
+                        x = as_global(p.X)[i];
+                        y = as_global(p.Y)[i];
+                        z = as_global(p.Z)[i];
                         s = b > p.step0 ? b : p.step0;
                         krec = s <= p.rec_step0 ? 0
                                                 : (s - p.rec_step0 + p.rec_every - 1) / p.rec_every;
                         next_rec = krec < p.n_rec ? p.rec_step0 + krec * p.rec_every : INT_MAX;
                         have = true;
                     } else if (p.n_rec > 0) {
-                        rec_exit[i] = INT_MIN;  // inactive before this window
+                        as_global(rec_exit)[i] = INT_MIN;  // inactive before this window
                     }
                 }
             }
@@ -485,18 +489,20 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepConst pk)
                 const int st = advance<NCOMP, TIME, LEVELS, NNUC, KZ, DEP, ENS>(
                     p, sv, tab, plane, gid, b, s, x, y, z, m, led, dw);
                 if (s == next_rec) {  // state after an output step, for gridding later
-                    rec4[(long long)krec * p.rec_stride + i] = make_float4(x, y, z, m);
+                    typedef float quad __attribute__((ext_vector_type(4)));
+                    as_global(reinterpret_cast<quad*>(rec4))[(long long)krec * p.rec_stride + i] =
+                        quad{x, y, z, m};
                     ++krec;
                     next_rec = krec < p.n_rec ? p.rec_step0 + krec * p.rec_every : INT_MAX;
                 }
                 ++s;
                 if (st != 0 || s >= p.step_end) {
                     if constexpr (DEP) dw.flush(p, tab, plane);
-                    p.X[i] = x;
-                    p.Y[i] = y;
-                    p.Z[i] = z;
-                    p.M[i] = m;
-                    if (p.n_rec > 0) rec_exit[i] = st != 0 ? s - 1 : INT_MAX;
+                    as_global(p.X)[i] = x;
+                    as_global(p.Y)[i] = y;
+                    as_global(p.Z)[i] = z;
+                    as_global(p.M)[i] = m;
+                    if (p.n_rec > 0) as_global(rec_exit)[i] = st != 0 ? s - 1 : INT_MAX;
                     if (st == 2) atomicOr(p.ctrl + LPM_CTRL_ERR, 1u);
                     have = false;
                 }
@@ -746,8 +752,8 @@ thread_local char g_msg[512] = "";
 
 // Launch tuning of the persistent step kernel (process-wide; set by the
 // autotuner or lpm_set_launch).
-int g_refill_every = 1;
-int g_refill_min = 1;
+int g_refill_every = 16;
+int g_refill_min = 64;
 int g_blocks_per_cu = 0;  // 0: as many as the device holds
 
 int fail(int code, const char* fmt, ...)
@@ -1324,7 +1330,9 @@ int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lp
     if (!st || !ens || !scen || !out) return fail(LPM_EINVAL, "null argument");
     if (trial_steps < 1 || trial_steps > ens->n_steps) return fail(LPM_EINVAL, "bad trial_steps");
     hipStream_t s = (hipStream_t)stream;
-    const int refills[] = {1, 2, 4, 8};
+    // queue schedules (refill interval, idle lanes before a refill) x blocks
+    // per compute unit
+    const int refills[][2] = {{1, 1}, {4, 1}, {16, 32}, {16, 64}};
     const int occupancy[] = {0, 3, 2};
     lpm_ensemble trial;
     int rc = lpm_ensemble_prepare(scen, ens->n_scen, st, ph, ens->step0, trial_steps, ens->table,
@@ -1333,12 +1341,13 @@ int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lp
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return hip_status("lpm_autotune_ensemble");
-    const int keep_refill = g_refill_every, keep_bpc = g_blocks_per_cu;
+    const int keep_refill = g_refill_every, keep_min = g_refill_min, keep_bpc = g_blocks_per_cu;
     double best = 1e300, worst = 0.0;
-    int best_r = keep_refill, best_o = keep_bpc, tried = 0;
-    for (int r : refills) {
+    int best_r = keep_refill, best_m = keep_min, best_o = keep_bpc, tried = 0;
+    for (const auto& r : refills) {
         for (int o : occupancy) {
-            g_refill_every = r;
+            g_refill_every = r[0];
+            g_refill_min = r[1];
             g_blocks_per_cu = o;
             for (int rep = 0; rep < 2; ++rep) {  // first repetition warms up
                 if ((rc = lpm_release_ensemble(st, &trial, ledgers, stream))) break;
@@ -1353,7 +1362,7 @@ int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lp
                 break;
             }
             ++tried;
-            if (ms < best) { best = ms; best_r = r; best_o = o; }
+            if (ms < best) { best = ms; best_r = r[0]; best_m = r[1]; best_o = o; }
             if (ms > worst) worst = ms;
         }
         if (rc) break;
@@ -1361,6 +1370,7 @@ int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lp
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     g_refill_every = rc ? keep_refill : best_r;
+    g_refill_min = rc ? keep_min : best_m;
     g_blocks_per_cu = rc ? keep_bpc : best_o;
     if (rc) return rc;
     // restore the caller's window in the table
@@ -1370,6 +1380,7 @@ int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lp
         return rc;
     out->refill_every = best_r;
     out->blocks_per_cu = best_o;
+    out->refill_min = best_m;
     out->best_ms = best;
     out->worst_ms = worst;
     out->n_tried = tried;

@@ -152,6 +152,21 @@ __device__ __forceinline__ void normals3(uint32_t id, uint32_t step, uint32_t k0
     xi2 = rho2 * __builtin_amdgcn_cosf(u3);
 }
 
+// Global-memory views of pointers.  Pointers read from LDS (the launch
+// constants are kept there) lose their address space, and loads through them
+// become flat loads, which also count against the LDS wait counter.
+typedef __attribute__((address_space(1))) const float gfloat;
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* as_global(const T* p)
+{
+    return (const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ float clampf(float v, float lo, float hi)
 {
     return fminf(fmaxf(v, lo), hi);
@@ -172,9 +187,10 @@ __device__ __forceinline__ void axis(float pos, float origin, float inv_d, float
 }
 
 // Vertical node and weight for explicitly given node heights (binary search).
-__device__ __forceinline__ void levels(const float* __restrict__ lev, int nz, float z,
+__device__ __forceinline__ void levels(const float* __restrict__ levp, int nz, float z,
                                        int& k0, float& w)
 {
+    const gfloat* lev = as_global(levp);
     if (nz == 1 || z <= lev[0]) { k0 = 0; w = 0.0f; return; }
     if (z >= lev[nz - 1]) { k0 = nz - 2; w = 1.0f; return; }
     int lo = 0, hi = nz - 1;  // lev[lo] <= z < lev[hi]
@@ -198,15 +214,36 @@ struct WindTap {
 };
 
 template <int NCOMP>
-__device__ __forceinline__ void gather8(const float* __restrict__ f, int base, int di, int dj,
+__device__ __forceinline__ void gather8(const float* __restrict__ fp, int base, int di, int dj,
                                         int dk, float (&c)[8][NCOMP])
 {
+    const gfloat* f = as_global(fp);
+    if constexpr (NCOMP == 2) {
+        if (di == 2) {
+            // (u, v) of the two x-neighbours are 16 contiguous, 8-byte aligned
+            // bytes: one 16-byte load per (y, z) corner pair
+            typedef float pair4 __attribute__((ext_vector_type(4), aligned(8)));
+            typedef __attribute__((address_space(1))) const pair4 gpair4;
+            const int o[4] = {base, base + dj, base + dk, base + dk + dj};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const pair4 v = *reinterpret_cast<gpair4*>(f + o[q]);
+                c[2 * q][0] = v.x;
+                c[2 * q][1] = v.y;
+                c[2 * q + 1][0] = v.z;
+                c[2 * q + 1][1] = v.w;
+            }
+            return;
+        }
+    }
     const int o[8] = {base, base + di, base + dj, base + dj + di,
                       base + dk, base + dk + di, base + dk + dj, base + dk + dj + di};
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         if constexpr (NCOMP == 2) {
-            const float2 v = *reinterpret_cast<const float2*>(f + o[q]);
+            typedef float pair2 __attribute__((ext_vector_type(2)));
+            typedef __attribute__((address_space(1))) const pair2 gpair2;
+            const pair2 v = *reinterpret_cast<gpair2*>(f + o[q]);
             c[q][0] = v.x;
             c[q][1] = v.y;
         } else {
