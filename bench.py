@@ -38,6 +38,37 @@ ALG_OPS_PER_PSTEP = 290
 HBM_PEAK = 8.0e12
 
 
+def kernel_source_hash() -> str:
+    """SHA-256 over the HIP sources and the public header (sorted by name)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_0912_3223_amd", "csrc")
+    files = [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))]
+    files.append(os.path.join(ROOT, "include", "lpm.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy of known size),
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "c1_1e6_step_kernel_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        k, _, v = line.strip().partition(": ")
+        if k in ("step_kernel_hbm_bytes_per_launch", "kernel_source_sha256"):
+            vals[k] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return float(vals["step_kernel_hbm_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,7 +260,8 @@ def main():
                    "steps_per_launch": a.spl or case.n_steps, "particle_steps_per_run": psteps},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                      "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
-                     "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": measured_traffic() if a.spl == 0 and a.n == 1_000_000 else None,
                      "kernel": "step_kernel", "avg_launch_ms": avg_launch_s * 1e3,
                      "launches_per_run": launches_per_run,
                      "step_kernel_share": step_total_s / (ms / 1e3)},
