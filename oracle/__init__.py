@@ -60,6 +60,12 @@ class Problem(C.Structure):
     ]
 
 
+class Receptors(C.Structure):
+    _fields_ = [("n", C.c_int32), ("pad", C.c_int32),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("sigma_h", C.c_double), ("sigma_z", C.c_double), ("weight", C.c_double)]
+
+
 _lib = None
 
 
@@ -90,6 +96,12 @@ def lib():
                                    C.POINTER(C.c_int64)]
         L.orc_simulate.restype = C.c_int
         L.orc_airborne.argtypes = [P, C.c_int32, dp, dp]
+        RP = C.POINTER(Receptors)
+        L.orc_receptor_forward.argtypes = [P, RP, C.c_int32, C.c_int32, dp, dp, C.c_int32,
+                                           C.POINTER(C.c_int64)]
+        L.orc_receptor_forward.restype = C.c_int
+        L.orc_receptor_adjoint.argtypes = [P, RP, C.c_int32, C.c_int32, dp, dp, C.c_int32]
+        L.orc_receptor_adjoint.restype = C.c_int
         _lib = L
     return _lib
 
@@ -191,6 +203,46 @@ class Oracle:
         arr = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, z, m)]
         lib().orc_grid_concentration(C.byref(self.p), s, *[_dp(a) for a in arr], _dp(out))
         return out
+
+    # -- receptor concentrations and their gradient ----------------------------
+    def _receptors(self, rec):
+        xyz = [np.ascontiguousarray(a, dtype=np.float64) for a in (rec.x, rec.y, rec.z)]
+        r = Receptors()
+        r.n = len(xyz[0])
+        r.x, r.y, r.z = (a.ctypes.data for a in xyz)
+        r.sigma_h, r.sigma_z, r.weight = rec.sigma_h, rec.sigma_z, rec.weight
+        return r, xyz
+
+    def receptor_forward(self, rec, s_end: Optional[int] = None, out_every: Optional[int] = None,
+                         tangent: bool = False, nthreads: int = 0):
+        """Receptor concentrations c [n] of the run over [0, s_end) and, with
+        ``tangent``, dc/d(h, q, s_w, v_d) [n][4] by forward mode."""
+        s_end = self.case.n_steps if s_end is None else s_end
+        out_every = self.case.out_every if out_every is None else out_every
+        r, keep = self._receptors(rec)
+        c = np.zeros(r.n)
+        dc = np.zeros((r.n, 4)) if tangent else None
+        ps = C.c_int64(0)
+        rc = lib().orc_receptor_forward(C.byref(self.p), C.byref(r), s_end, out_every, _dp(c),
+                                        _dp(dc) if tangent else None, nthreads, C.byref(ps))
+        if rc != 0:
+            raise ValueError("oracle rejected the receptor problem")
+        return {"c": c, "dc": dc, "psteps": ps.value}
+
+    def receptor_adjoint(self, rec, gbar, s_end: Optional[int] = None,
+                         out_every: Optional[int] = None, nthreads: int = 0):
+        """sum_r gbar_r dc_r/d(h, q, s_w, v_d) by reverse mode."""
+        s_end = self.case.n_steps if s_end is None else s_end
+        out_every = self.case.out_every if out_every is None else out_every
+        r, keep = self._receptors(rec)
+        g = np.ascontiguousarray(gbar, dtype=np.float64)
+        assert len(g) == r.n
+        grad = np.zeros(4)
+        rc = lib().orc_receptor_adjoint(C.byref(self.p), C.byref(r), s_end, out_every, _dp(g),
+                                        _dp(grad), nthreads)
+        if rc != 0:
+            raise ValueError("oracle rejected the receptor problem")
+        return grad
 
     def airborne(self, s: int, m):
         out = np.zeros(4)

@@ -499,3 +499,443 @@ void orc_airborne(const orc_problem* P, int32_t s, const double* m, double* out)
             out[n] += a0 * m[i] * exp(-P->lambda[n] * (double)(s + 1 - b) * P->dt);
     }
 }
+
+/* ======================================================================== */
+/* Receptor concentrations of a source and their gradient with respect to    */
+/* the source parameters theta = (h, q, s_w, v_d)                            */
+/* ======================================================================== */
+/*
+ * Ground-level concentrations at receptor points are the activities of the
+ * airborne particles spread with a Gaussian kernel (horizontal width
+ * sigma_h, vertical width sigma_z with its mirror image below the ground)
+ * and summed over the output steps s = out_every - 1, 2 out_every - 1, ...:
+ *
+ *   c_r = weight * sum_s sum_p A_p(s) G_h(x_p - X_r, y_p - Y_r)
+ *                               [N(z_p - Z_r) + N(z_p + Z_r)],
+ *   A_p(s) = a0 m_p sum_n exp(-lambda_n (s + 1 - b_p) dt)   (all nuclides),
+ *
+ * with the state taken after step s (the gridding time of Sec. 3.2).  The
+ * derivatives follow each particle's path with its random numbers held
+ * fixed (common random numbers): the path is a piecewise smooth function of
+ * theta, and the derivative is that of the smooth piece.  The exit step of a
+ * particle that leaves the domain is treated as fixed (its activity after
+ * the exit is zero whatever theta is).
+ *
+ * Three evaluations are provided:
+ *   orc_receptor_forward   c_r, and optionally dc_r/dtheta by propagating
+ *                          four tangents along each path (forward mode);
+ *   orc_receptor_adjoint   sum_r gbar_r dc_r/dtheta by a reverse sweep over
+ *                          each particle's stored path (reverse mode).
+ * Both use the step Jacobian below; central finite differences of the plain
+ * forward (the tests) pin that Jacobian independently.
+ */
+
+typedef struct {
+    int32_t n, pad;
+    const double* x;
+    const double* y;
+    const double* z;
+    double sigma_h, sigma_z;
+    double weight;  /* time weight of one output step (s) */
+} orc_receptors;
+
+/* Interpolated wind (before the wind-scale factor) and its gradient
+ * g[c][d] = d uvw[c] / d (x, y, z)[d]; a clamped coordinate has zero slope. */
+static void wind_gradient(const orc_problem* P, double x, double y, double z, double t,
+                          double uvw[3], double g[3][3])
+{
+    int i0, i1, j0, j1, k0, k1, t0, t1;
+    double wx, wy, wz, wt;
+    axis_weight(x, P->fx0, P->fdx, P->nx, &i0, &i1, &wx);
+    axis_weight(y, P->fy0, P->fdy, P->ny, &j0, &j1, &wy);
+    double fx = (x - P->fx0) / P->fdx - 0.5, fy = (y - P->fy0) / P->fdy - 0.5;
+    double sx = (fx > 0.0 && fx < (double)(P->nx - 1)) ? 1.0 / P->fdx : 0.0;
+    double sy = (fy > 0.0 && fy < (double)(P->ny - 1)) ? 1.0 / P->fdy : 0.0;
+    double sz;
+    if (P->z_levels) {
+        level_weight(z, P->z_levels, P->nz, &k0, &k1, &wz);
+        int inside = P->nz > 1 && z > (double)P->z_levels[0] &&
+                     z < (double)P->z_levels[P->nz - 1];
+        sz = inside ? 1.0 / ((double)P->z_levels[k1] - (double)P->z_levels[k0]) : 0.0;
+    } else {
+        axis_weight(z, 0.0, P->fdz, P->nz, &k0, &k1, &wz);
+        double fz = z / P->fdz - 0.5;
+        sz = (fz > 0.0 && fz < (double)(P->nz - 1)) ? 1.0 / P->fdz : 0.0;
+    }
+    double ft = (P->nt > 1) ? (t - P->ft0) / P->fdt : 0.0;
+    if (ft < 0.0) ft = 0.0;
+    if (ft > (double)(P->nt - 1)) ft = (double)(P->nt - 1);
+    t0 = (int)floor(ft);
+    if (t0 > P->nt - 2) t0 = (P->nt >= 2) ? P->nt - 2 : 0;
+    t1 = (t0 + 1 < P->nt) ? t0 + 1 : t0;
+    wt = ft - (double)t0;
+
+    for (int c = 0; c < 3; ++c) {
+        uvw[c] = 0.0;
+        g[c][0] = g[c][1] = g[c][2] = 0.0;
+        if (c >= P->ncomp) continue;
+        int tt[2] = {t0, t1};
+        double tw[2] = {1.0 - wt, wt};
+        for (int a = 0; a < 2; ++a) {
+            int T = tt[a];
+            /* corner values v[kk][jj][ii] */
+            double v[2][2][2];
+            int ks[2] = {k0, k1}, js[2] = {j0, j1}, is[2] = {i0, i1};
+            for (int kk = 0; kk < 2; ++kk)
+                for (int jj = 0; jj < 2; ++jj)
+                    for (int ii = 0; ii < 2; ++ii)
+                        v[kk][jj][ii] = node(P, T, ks[kk], js[jj], is[ii], c);
+            double val = 0.0, dx = 0.0, dy = 0.0, dz = 0.0;
+            for (int kk = 0; kk < 2; ++kk)
+                for (int jj = 0; jj < 2; ++jj)
+                    for (int ii = 0; ii < 2; ++ii) {
+                        double ax = ii ? wx : 1.0 - wx, ay = jj ? wy : 1.0 - wy;
+                        double az = kk ? wz : 1.0 - wz;
+                        double ex = ii ? 1.0 : -1.0, ey = jj ? 1.0 : -1.0, ez = kk ? 1.0 : -1.0;
+                        val += az * ay * ax * v[kk][jj][ii];
+                        dx += az * ay * ex * v[kk][jj][ii];
+                        dy += az * ey * ax * v[kk][jj][ii];
+                        dz += ez * ay * ax * v[kk][jj][ii];
+                    }
+            uvw[c] += tw[a] * val;
+            g[c][0] += tw[a] * dx * sx;
+            g[c][1] += tw[a] * dy * sy;
+            g[c][2] += tw[a] * dz * sz;
+        }
+    }
+}
+
+/* Second derivative of K_z(z) (zero where K_z is constant or zero). */
+static double kz_second(const orc_problem* P, double z)
+{
+    if (P->kz_kind == 0 || z < 0.0 || z >= P->H_mix) return 0.0;
+    double H = P->H_mix, ku = P->kappa_ustar, g = 1.0 - z / H;
+    if (P->kz_kind == 1) return -2.0 * ku / H;
+    return ku * (-4.0 * g / H + 2.0 * (z + P->z0) / (H * H));
+}
+
+/* Fold of z into [0, H] and its slope (+1 or -1). */
+static double fold_sign(double z, double H, double* sign)
+{
+    double sg = 1.0;
+    for (int it = 0; it < 64; ++it) {
+        if (z < 0.0) { z = -z; sg = -sg; }
+        else if (H > 0.0 && z > H) { z = 2.0 * H - z; sg = -sg; }
+        else break;
+    }
+    *sign = sg;
+    return z;
+}
+
+/* Wet-deposition rate and its gradient in (x, y). */
+static double wet_rate_gradient(const orc_problem* P, double x, double y, double* gx, double* gy)
+{
+    *gx = *gy = 0.0;
+    if (P->Lambda0 == 0.0) return 0.0;
+    double dx = x - P->rain_cx, dy = y - P->rain_cy;
+    double ca = cos(P->rain_angle), sa = sin(P->rain_angle);
+    double xr = ca * dx + sa * dy;
+    double yr = -sa * dx + ca * dy;
+    double a = P->rain_a, b = P->rain_b;
+    double re = sqrt((xr / a) * (xr / a) + (yr / b) * (yr / b));
+    double f = (1.0 - re) / P->rain_edge + 0.5;
+    if (f <= 0.0) return 0.0;
+    if (f >= 1.0) return P->Lambda0;
+    if (re > 0.0) {
+        double dre_dxr = xr / (a * a * re), dre_dyr = yr / (b * b * re);
+        double dre_dx = dre_dxr * ca - dre_dyr * sa;
+        double dre_dy = dre_dxr * sa + dre_dyr * ca;
+        *gx = -P->Lambda0 / P->rain_edge * dre_dx;
+        *gy = -P->Lambda0 / P->rain_edge * dre_dy;
+    }
+    return P->Lambda0 * f;
+}
+
+/* One step of one particle with its Jacobian.  u = (x, y, z, m) before step
+ * s; un receives the state after it (as step_particle computes it: same
+ * formulas, same order).  J[i][j] = d un_i / d u_j; Jsw[i], Jvd[i] =
+ * d un_i / d s_w, d un_i / d v_d.  Returns 1 if the particle left the domain
+ * in this step (un m = 0, Jacobian zero), else 0. */
+static int step_jacobian(const orc_problem* P, int64_t gid, int32_t s, const double u[4],
+                         double un[4], double J[4][4], double Jsw[4], double Jvd[4])
+{
+    const double dt = P->dt;
+    double x = u[0], y = u[1], z = u[2], m = u[3];
+    memset(J, 0, sizeof(double) * 16);
+    for (int i = 0; i < 4; ++i) Jsw[i] = Jvd[i] = 0.0;
+
+    double xi[4];
+    orc_normals(P->seed, P->scenario, (uint32_t)gid, (uint32_t)s, 0u, xi);
+    double uvw[3], g[3][3];
+    wind_gradient(P, x, y, z, (double)s * dt, uvw, g);
+    const double sw = P->wind_scale;
+
+    double Kz, dKz, Kzm, dKzm;
+    orc_kz(P, z, &Kz, &dKz);
+    double K2 = kz_second(P, z);
+    double zm_raw = z + 0.5 * dKz * dt;
+    double zm = zm_raw;
+    if (zm < 0.0) zm = 0.0;
+    if (zm > P->H_mix) zm = P->H_mix;
+    double dzm_dz = (zm_raw > 0.0 && zm_raw < P->H_mix) ? 1.0 + 0.5 * dt * K2 : 0.0;
+    orc_kz(P, zm, &Kzm, &dKzm);
+    double sq = sqrt(2.0 * Kzm * dt);
+    double dsq_dz = sq > 0.0 ? dt * dKzm * dzm_dz / sq : 0.0;
+
+    double sh = sqrt(2.0 * P->Kh * dt);
+    double xn = x + sw * uvw[0] * dt + xi[0] * sh;
+    double yn = y + sw * uvw[1] * dt + xi[1] * sh;
+    double zn0 = z + sw * uvw[2] * dt + dKz * dt + xi[2] * sq;
+    double sg;
+    double zn = fold_sign(zn0, P->H_lid, &sg);
+
+    /* position rows (before the fold for z) */
+    double Dx[3] = {1.0 + sw * dt * g[0][0], sw * dt * g[0][1], sw * dt * g[0][2]};
+    double Dy[3] = {sw * dt * g[1][0], 1.0 + sw * dt * g[1][1], sw * dt * g[1][2]};
+    double Dz[3] = {sw * dt * g[2][0], sw * dt * g[2][1],
+                    1.0 + sw * dt * g[2][2] + K2 * dt + xi[2] * dsq_dz};
+    double swx = uvw[0] * dt, swy = uvw[1] * dt, swz = uvw[2] * dt;
+
+    /* deposition rate at the new position */
+    double kd = orc_dry_rate(P, zn);
+    double phi = (zn >= 0.0 && zn < P->h_s) ? (2.0 / P->h_s) * (1.0 - zn / P->h_s) : 0.0;
+    double dkd_dz = (P->v_d != 0.0 && zn >= 0.0 && zn < P->h_s)
+                        ? -P->v_d * 2.0 / (P->h_s * P->h_s) : 0.0;
+    double gwx, gwy;
+    double kw = wet_rate_gradient(P, xn, yn, &gwx, &gwy);
+    double k = kd + kw;
+    double e = exp(-k * dt);
+    double mn = m * e;
+
+    if (P->bounded) {
+        double X1 = P->fx0 + P->nx * P->fdx, Y1 = P->fy0 + P->ny * P->fdy;
+        if (xn < P->fx0 || xn >= X1 || yn < P->fy0 || yn >= Y1) {
+            un[0] = xn; un[1] = yn; un[2] = zn; un[3] = 0.0;
+            return 1;
+        }
+    }
+    un[0] = xn; un[1] = yn; un[2] = zn; un[3] = mn;
+    for (int j = 0; j < 3; ++j) {
+        J[0][j] = Dx[j];
+        J[1][j] = Dy[j];
+        J[2][j] = sg * Dz[j];
+    }
+    Jsw[0] = swx;
+    Jsw[1] = swy;
+    Jsw[2] = sg * swz;
+    /* m row: mn = m exp(-k dt), k = k(xn, yn, zn) */
+    double dmn_dk = -dt * mn;
+    for (int j = 0; j < 3; ++j)
+        J[3][j] = dmn_dk * (gwx * J[0][j] + gwy * J[1][j] + dkd_dz * J[2][j]);
+    J[3][3] = e;
+    Jsw[3] = dmn_dk * (gwx * Jsw[0] + gwy * Jsw[1] + dkd_dz * Jsw[2]);
+    Jvd[3] = dmn_dk * phi;
+    return 0;
+}
+
+/* Receptor kernel value and its gradient in (x, y, z). */
+static double receptor_kernel(const orc_receptors* R, int r, double x, double y, double z,
+                              double gk[3])
+{
+    const double pi = 3.141592653589793238462643383279;
+    double sh2 = R->sigma_h * R->sigma_h, sz2 = R->sigma_z * R->sigma_z;
+    double dx = x - R->x[r], dy = y - R->y[r];
+    double gh = exp(-(dx * dx + dy * dy) / (2.0 * sh2)) / (2.0 * pi * sh2);
+    double d1 = z - R->z[r], d2 = z + R->z[r];
+    double cz = 1.0 / (sqrt(2.0 * pi) * R->sigma_z);
+    double n1 = cz * exp(-d1 * d1 / (2.0 * sz2)), n2 = cz * exp(-d2 * d2 / (2.0 * sz2));
+    double kv = gh * (n1 + n2);
+    gk[0] = -dx / sh2 * kv;
+    gk[1] = -dy / sh2 * kv;
+    gk[2] = gh * (-d1 / sz2 * n1 - d2 / sz2 * n2);
+    return kv;
+}
+
+/* Total activity factor sum_n exp(-lambda_n age) after step s. */
+static double decay_sum(const orc_problem* P, int64_t b, int32_t s)
+{
+    double age = (double)(s + 1 - b) * P->dt, f = 0.0;
+    for (int n = 0; n < P->n_nuc; ++n) f += exp(-P->lambda[n] * age);
+    return f;
+}
+
+static int receptor_args_ok(const orc_problem* P, const orc_receptors* R, int32_t s_end,
+                            int32_t out_every)
+{
+    return P && R && R->n >= 0 && (R->n == 0 || (R->x && R->y && R->z)) && R->sigma_h > 0.0 &&
+           R->sigma_z > 0.0 && out_every >= 1 && s_end >= 0 && P->n_nuc >= 1 && P->n_nuc <= 4 &&
+           P->n_total > 0 && P->s_release > 0 && P->n_local >= 0 && P->id_stride > 0 && P->f &&
+           (P->ncomp == 2 || P->ncomp == 3) && P->q != 0.0;
+}
+
+/* c[n_rec] (added to) receives the receptor concentrations of a run over
+ * steps [0, s_end) with the particles released at their birth steps; if dc
+ * is not NULL, dc[n_rec][4] (added to) receives dc_r / d(h, q, s_w, v_d) by
+ * forward-mode propagation.  *psteps (if not NULL) receives the number of
+ * particle-steps.  Returns 0, or -1 for invalid arguments. */
+int orc_receptor_forward(const orc_problem* P, const orc_receptors* R, int32_t s_end,
+                         int32_t out_every, double* c, double* dc, int32_t nthreads,
+                         int64_t* psteps)
+{
+    if (!receptor_args_ok(P, R, s_end, out_every) || !c) return -1;
+    int nth = 1;
+#ifdef _OPENMP
+    nth = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    const int nr = R->n;
+    double* acc = (double*)calloc((size_t)nth * nr * 5, sizeof(double));
+    int64_t* cnt = (int64_t*)calloc((size_t)nth, sizeof(int64_t));
+    if (!acc || !cnt) { free(acc); free(cnt); return -1; }
+    const double a0 = a0_of(P);
+
+#pragma omp parallel num_threads(nth)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* my = acc + (size_t)tid * nr * 5;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < P->n_local; ++i) {
+            int64_t gid = P->id_base + i * P->id_stride;
+            int64_t b = birth_of(P, gid);
+            if (b >= s_end) continue;
+            double u[4] = {P->xs, P->ys, P->h, 1.0};
+            /* tangents T[j][0..3] of (x, y, z, m), j = h, q, s_w, v_d */
+            double T[4][4] = {{0, 0, 1, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+            for (int32_t s = (int32_t)b; s < s_end; ++s) {
+                double un[4], J[4][4], Jsw[4], Jvd[4];
+                int gone = step_jacobian(P, gid, s, u, un, J, Jsw, Jvd);
+                cnt[tid] += 1;
+                if (gone) break;
+                if (dc) {
+                    double Tn[4][4];
+                    for (int j = 0; j < 4; ++j)
+                        for (int a = 0; a < 4; ++a) {
+                            double v = 0.0;
+                            for (int k = 0; k < 4; ++k) v += J[a][k] * T[j][k];
+                            if (j == 2) v += Jsw[a];
+                            if (j == 3) v += Jvd[a];
+                            Tn[j][a] = v;
+                        }
+                    memcpy(T, Tn, sizeof(T));
+                }
+                memcpy(u, un, sizeof(u));
+                if ((s + 1) % out_every != 0) continue;
+                double A = a0 * u[3] * decay_sum(P, b, s);
+                for (int r = 0; r < nr; ++r) {
+                    double gk[3];
+                    double kv = receptor_kernel(R, r, u[0], u[1], u[2], gk);
+                    double cv = R->weight * A * kv;
+                    my[r * 5] += cv;
+                    if (!dc) continue;
+                    for (int j = 0; j < 4; ++j) {
+                        double d = R->weight * (a0 * T[j][3] * decay_sum(P, b, s) * kv +
+                                                A * (gk[0] * T[j][0] + gk[1] * T[j][1] +
+                                                     gk[2] * T[j][2]));
+                        if (j == 1) d += cv / P->q;  /* a0 is proportional to q */
+                        my[r * 5 + 1 + j] += d;
+                    }
+                }
+            }
+        }
+    }
+    int64_t total = 0;
+    for (int t = 0; t < nth; ++t) {
+        for (int r = 0; r < nr; ++r) {
+            c[r] += acc[((size_t)t * nr + r) * 5];
+            if (dc)
+                for (int j = 0; j < 4; ++j) dc[r * 4 + j] += acc[((size_t)t * nr + r) * 5 + 1 + j];
+        }
+        total += cnt[t];
+    }
+    if (psteps) *psteps = total;
+    free(acc);
+    free(cnt);
+    return 0;
+}
+
+/* grad[4] (added to) receives sum_r gbar_r dc_r / d(h, q, s_w, v_d) by a
+ * reverse sweep over each particle's path (stored whole: this is the plain
+ * form of the checkpointed GPU adjoint).  Returns 0, or -1. */
+int orc_receptor_adjoint(const orc_problem* P, const orc_receptors* R, int32_t s_end,
+                         int32_t out_every, const double* gbar, double* grad, int32_t nthreads)
+{
+    if (!receptor_args_ok(P, R, s_end, out_every) || !gbar || !grad) return -1;
+    int nth = 1;
+#ifdef _OPENMP
+    nth = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    const int nr = R->n;
+    double* acc = (double*)calloc((size_t)nth * 4, sizeof(double));
+    double* paths = (double*)malloc((size_t)nth * ((size_t)s_end + 1) * 4 * sizeof(double));
+    if (!acc || !paths) { free(acc); free(paths); return -1; }
+    const double a0 = a0_of(P);
+
+#pragma omp parallel num_threads(nth)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* my = acc + (size_t)tid * 4;
+        double* path = paths + (size_t)tid * ((size_t)s_end + 1) * 4;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < P->n_local; ++i) {
+            int64_t gid = P->id_base + i * P->id_stride;
+            int64_t b = birth_of(P, gid);
+            if (b >= s_end) continue;
+            /* forward: path[s - b] = state before step s; e = first step not
+             * to differentiate (the exit step, or s_end) */
+            double u[4] = {P->xs, P->ys, P->h, 1.0};
+            int32_t e = s_end;
+            for (int32_t s = (int32_t)b; s < s_end; ++s) {
+                memcpy(path + (size_t)(s - b) * 4, u, sizeof(u));
+                double un[4], J[4][4], Jsw[4], Jvd[4];
+                if (step_jacobian(P, gid, s, u, un, J, Jsw, Jvd)) { e = s; break; }
+                memcpy(u, un, sizeof(u));
+            }
+            if (e == s_end) memcpy(path + (size_t)(s_end - b) * 4, u, sizeof(u));
+            /* reverse: ubar is the adjoint of the state after step s */
+            double ub[4] = {0, 0, 0, 0};
+            double sw_bar = 0.0, vd_bar = 0.0, q_bar = 0.0;
+            for (int32_t s = e - 1; s >= (int32_t)b; --s) {
+                if ((s + 1) % out_every == 0) {
+                    const double* v = path + (size_t)(s + 1 - b) * 4;
+                    double F = decay_sum(P, b, s), A = a0 * v[3] * F;
+                    for (int r = 0; r < nr; ++r) {
+                        double gk[3];
+                        double kv = receptor_kernel(R, r, v[0], v[1], v[2], gk);
+                        double w = gbar[r] * R->weight;
+                        ub[0] += w * A * gk[0];
+                        ub[1] += w * A * gk[1];
+                        ub[2] += w * A * gk[2];
+                        ub[3] += w * a0 * F * kv;
+                        q_bar += w * A * kv / P->q;
+                    }
+                }
+                double un[4], J[4][4], Jsw[4], Jvd[4];
+                step_jacobian(P, gid, s, path + (size_t)(s - b) * 4, un, J, Jsw, Jvd);
+                double nb[4];
+                for (int k = 0; k < 4; ++k) {
+                    nb[k] = 0.0;
+                    for (int a = 0; a < 4; ++a) nb[k] += J[a][k] * ub[a];
+                }
+                for (int a = 0; a < 4; ++a) {
+                    sw_bar += Jsw[a] * ub[a];
+                    vd_bar += Jvd[a] * ub[a];
+                }
+                memcpy(ub, nb, sizeof(ub));
+            }
+            my[0] += ub[2];  /* released at z = h */
+            my[1] += q_bar;
+            my[2] += sw_bar;
+            my[3] += vd_bar;
+        }
+    }
+    for (int t = 0; t < nth; ++t)
+        for (int j = 0; j < 4; ++j) grad[j] += acc[(size_t)t * 4 + j];
+    free(acc);
+    free(paths);
+    return 0;
+}

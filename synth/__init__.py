@@ -32,8 +32,9 @@ import numpy as np
 
 __all__ = [
     "Source", "Schedule", "Physics", "Rain", "Field", "Grid", "Case",
-    "c0", "c1", "c2", "c3", "wind_field", "rain_region", "uniform_field",
-    "uniform_state", "replace",
+    "c0", "c1", "c2", "c3", "c4", "wind_field", "rain_region", "uniform_field",
+    "uniform_state", "replace", "Receptors", "load_receptors", "with_theta",
+    "THETA0", "THETA_HIDDEN",
 ]
 
 
@@ -362,3 +363,57 @@ def uniform_state(n: int, box, seed: int):
     z = rng.uniform(zl, zh, n).astype(np.float32)
     m = np.ones(n, dtype=np.float32)
     return x, y, z, m
+
+
+# ---------------------------------------------------------------------------
+# receptor workload (source inversion): gradients of a receptor misfit with
+# respect to theta = (h, q, s_w, v_d)
+# ---------------------------------------------------------------------------
+
+THETA0 = (50.0, 1.0, 1.0, 0.002)        # where the gradient is taken
+THETA_HIDDEN = (80.0, 1.3, 1.1, 0.003)  # source that made the observations
+
+
+@dataclass(frozen=True)
+class Receptors:
+    """Receptor points and the Gaussian kernel that turns particle
+    activities into their concentrations: horizontal width ``sigma_h`` (m),
+    vertical width ``sigma_z`` (m, mirrored at the ground) and the time
+    weight of one output step ``weight`` (s)."""
+    x: Tuple[float, ...]
+    y: Tuple[float, ...]
+    z: Tuple[float, ...]
+    sigma_h: float = 250.0
+    sigma_z: float = 40.0
+    weight: float = 300.0
+
+    @property
+    def n(self) -> int:
+        return len(self.x)
+
+
+def with_theta(case: Case, theta) -> Case:
+    """The case with source height, release rate, wind scale and deposition
+    velocity set to ``theta``."""
+    h, q, sw, vd = (float(t) for t in theta)
+    return case.with_(source=replace(case.source, h=h, q=q, wind_scale=sw, v_d=vd))
+
+
+def c4(n_total: int = 1_000_000, n_steps: int = 4320, seed: int = 0) -> Case:
+    """The 1e6-particle 6 h gridded workload at theta0 (h = 50 m, q = 1,
+    s_w = 1, v_d = 0.002 m/s) with Philox seed ``seed``; output every 60
+    steps (the checkpoint interval of the gradient)."""
+    c = c1(n_total=n_total, n_steps=n_steps)
+    c = c.with_(physics=replace(c.physics, seed=seed))
+    return with_theta(c, THETA0)
+
+
+def load_receptors(path: str):
+    """Receptors and observations stored as JSON (written by the script
+    next to the file).  Returns (Receptors, observations, meta)."""
+    import json
+    with open(path) as f:
+        d = json.load(f)
+    r = Receptors(tuple(d["x"]), tuple(d["y"]), tuple(d["z"]), d["sigma_h"], d["sigma_z"],
+                  d["weight"])
+    return r, np.asarray(d["observations"], dtype=np.float64), d
