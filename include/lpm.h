@@ -349,6 +349,69 @@ int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens,
                           double* ledgers, uint32_t* ctrl, int32_t trial_steps,
                           lpm_tuning* out, lpm_stream stream);
 
+/* ---------------------------------------------------------------------------
+ * Receptor concentrations and their gradient (source inversion)
+ *
+ * Ground-level concentrations at receptor points are the activities of the
+ * airborne particles spread with a Gaussian kernel and summed over the output
+ * steps of a whole-run record (lpm_step_particles_record with rec_step0 =
+ * rec_every - 1, starting at step 0, every particle released at its birth):
+ *
+ *   c_r = weight * sum_k sum_p A_p(s_k) G(x_p - x_r, y_p - y_r)
+ *                             [N(z_p - z_r) + N(z_p + z_r)],
+ *   A_p(s) = a0 m_p sum_n exp(-lambda_n (s + 1 - b_p) dt)   (all nuclides),
+ *
+ * G the normalised 2-D Gaussian of width sigma_h, N the 1-D Gaussian of
+ * width sigma_z (its mirror image below the ground keeps a receptor at the
+ * ground seeing the reflected plume), s_k the recorded output steps and
+ * weight the time one output step stands for (e.g. rec_every dt).  This is
+ * the smooth gridding of a receptor-misfit loss; the activity bookkeeping is
+ * that of Sec. 2 and the output steps those of Sec. 3.2.
+ * ------------------------------------------------------------------------- */
+
+#define LPM_MAX_RECEPTORS 1024
+
+typedef struct {
+    const float* x; /* device, n receptor positions (m) */
+    const float* y;
+    const float* z; /* height above ground, >= 0 */
+    int32_t n;      /* 1 .. LPM_MAX_RECEPTORS */
+    float sigma_h;  /* horizontal kernel width (m), > 0 */
+    float sigma_z;  /* vertical kernel width (m), > 0 */
+    float weight;   /* time weight of one output step (s) */
+} lpm_receptors;
+
+/* c_out[n] (device, FP64, overwritten) = receptor concentrations of the n_rec
+ * recorded output steps rec_step0 + k rec_every (record layout as in
+ * lpm_step_particles_record).  Asynchronous. */
+int lpm_receptor_concentration(const float* rec, int64_t rec_stride, int32_t rec_step0,
+                               int32_t rec_every, int32_t n_rec, const lpm_source* src,
+                               const lpm_schedule* sch, const lpm_physics* ph,
+                               const lpm_receptors* rcp, double* c_out, lpm_stream stream);
+
+/* Bytes of device workspace lpm_receptor_adjoint needs for this field kind,
+ * schedule and checkpoint interval (written to *bytes). */
+int lpm_adjoint_workspace(const lpm_field* fld, const lpm_schedule* sch, int32_t rec_every,
+                          int64_t* bytes);
+
+/* Adjoint of the receptor concentrations (reverse mode along each particle's
+ * path, random numbers held fixed): with gbar[n] (device, FP64) = dL/dc_r,
+ * grad_out[5] (device, FP64, overwritten) receives dL/dh, dL/dq, dL/ds_w,
+ * dL/dv_d (source height, release rate q, wind scale, dry-deposition
+ * velocity) and sum_r gbar_r c_r.
+ * The record must be the whole-run record of the same source, schedule,
+ * field and physics: n_rec output steps s_k = (k + 1) rec_every - 1 of the
+ * run over steps [0, n_rec rec_every).  Record k - 1 is the checkpoint from
+ * which segment k (steps k rec_every .. (k + 1) rec_every - 1) is recomputed
+ * into the workspace, then swept backwards.  A particle that leaves the
+ * domain contributes only through the output steps before its exit step
+ * (the exit itself does not move with theta).  `work` (device, 16-byte
+ * aligned, work_bytes >= lpm_adjoint_workspace) is scratch.  Asynchronous. */
+int lpm_receptor_adjoint(const float* rec, int64_t rec_stride, int32_t rec_every, int32_t n_rec,
+                         const lpm_source* src, const lpm_schedule* sch, const lpm_field* fld,
+                         const lpm_physics* ph, const lpm_receptors* rcp, const double* gbar,
+                         double* grad_out, void* work, int64_t work_bytes, lpm_stream stream);
+
 /* Library version string. */
 const char* lpm_version(void);
 

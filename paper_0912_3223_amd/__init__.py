@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_PKG, "liblpm.so")
 LPM_OK, LPM_EINVAL, LPM_ECAPACITY, LPM_EHIP, LPM_ENONFINITE = 0, -1, -2, -3, -4
 LEDGER_SLOTS = 64
 MAX_SCENARIOS = 256
+LPM_MAX_RECEPTORS = 1024
 SCENARIO_BYTES = 96
 LEDGER_STRIDE = 32
 CTRL_WORDS = 64
@@ -89,6 +90,11 @@ class Tuning(C.Structure):
                 ("refill_min", C.c_int32)]
 
 
+class Receptors(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("n", C.c_int32),
+                ("sigma_h", C.c_float), ("sigma_z", C.c_float), ("weight", C.c_float)]
+
+
 class Accum(C.Structure):
     _fields_ = [("dep", C.c_void_p), ("ledger", C.c_void_p), ("ctrl", C.c_void_p),
                 ("n_nuc", C.c_int32), ("reserved", C.c_int32), ("dep_grid", Grid)]
@@ -127,6 +133,13 @@ def _load():
         "lpm_autotune_ensemble": [P(State), P(Ensemble), P(Scenario), P(Field), P(Physics),
                                   P(Grid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                   P(Tuning), C.c_void_p],
+        "lpm_receptor_concentration": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                       P(Source), P(Schedule), P(Physics), P(Receptors),
+                                       C.c_void_p, C.c_void_p],
+        "lpm_adjoint_workspace": [P(Field), P(Schedule), C.c_int32, P(C.c_int64)],
+        "lpm_receptor_adjoint": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, P(Source),
+                                 P(Schedule), P(Field), P(Physics), P(Receptors), C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -145,6 +158,7 @@ EXPORTS = ("lpm_accum_reset", "lpm_release_particles", "lpm_step_particles",
            "lpm_grid_concentration", "lpm_grid_records", "lpm_grid_deposition",
            "lpm_read_ledger", "lpm_check", "lpm_set_launch", "lpm_set_launch_ex", "lpm_ensemble_prepare",
            "lpm_release_ensemble", "lpm_step_ensemble", "lpm_autotune_ensemble",
+           "lpm_receptor_concentration", "lpm_adjoint_workspace", "lpm_receptor_adjoint",
            "lpm_last_error", "lpm_version")
 
 
@@ -263,6 +277,35 @@ def autotune_ensemble(st: State, ens: Ensemble, scen, fld: Field, ph: Physics, d
     return t
 
 
+def receptor_concentration(rec: torch.Tensor, rec_stride: int, rec_step0: int, rec_every: int,
+                           n_rec: int, src: Source, sch: Schedule, ph: Physics, rcp: Receptors,
+                           c_out: torch.Tensor, stream=None):
+    assert rec.dtype == torch.float32 and c_out.dtype == torch.float64
+    assert c_out.numel() >= rcp.n
+    _rc(_lib.lpm_receptor_concentration(C.c_void_p(rec.data_ptr()), rec_stride, rec_step0,
+                                        rec_every, n_rec, C.byref(src), C.byref(sch),
+                                        C.byref(ph), C.byref(rcp), C.c_void_p(c_out.data_ptr()),
+                                        _stream(stream)))
+
+
+def adjoint_workspace(fld: Field, sch: Schedule, rec_every: int) -> int:
+    n = C.c_int64(0)
+    _rc(_lib.lpm_adjoint_workspace(C.byref(fld), C.byref(sch), rec_every, C.byref(n)))
+    return n.value
+
+
+def receptor_adjoint(rec: torch.Tensor, rec_stride: int, rec_every: int, n_rec: int, src: Source,
+                     sch: Schedule, fld: Field, ph: Physics, rcp: Receptors, gbar: torch.Tensor,
+                     grad_out: torch.Tensor, work: torch.Tensor, stream=None):
+    assert gbar.dtype == torch.float64 and grad_out.dtype == torch.float64
+    assert gbar.numel() >= rcp.n and grad_out.numel() >= 5
+    _rc(_lib.lpm_receptor_adjoint(C.c_void_p(rec.data_ptr()), rec_stride, rec_every, n_rec,
+                                  C.byref(src), C.byref(sch), C.byref(fld), C.byref(ph),
+                                  C.byref(rcp), C.c_void_p(gbar.data_ptr()),
+                                  C.c_void_p(grad_out.data_ptr()), C.c_void_p(work.data_ptr()),
+                                  work.numel() * work.element_size(), _stream(stream)))
+
+
 def set_launch(refill_every: int = 16, blocks_per_cu: int = 0, refill_min: int = 64):
     _rc(_lib.lpm_set_launch_ex(refill_every, blocks_per_cu, refill_min))
 
@@ -271,5 +314,5 @@ def version() -> str:
     return _lib.lpm_version().decode()
 
 
-from .host import (DeviceRun, EnsembleRun, make_source, make_schedule, make_physics,  # noqa: E402
-                   make_grid)
+from .host import (DeviceRun, EnsembleRun, ReceptorRun, ReceptorConcentration,  # noqa: E402
+                   make_source, make_schedule, make_physics, make_grid)

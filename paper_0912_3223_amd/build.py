@@ -13,8 +13,9 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = [os.path.join(PKG, "csrc", "lpm.hip")]
-DEPS = SRC + [os.path.join(PKG, "csrc", "lpm_device.h"), os.path.join(ROOT, "include", "lpm.h")]
+SRC = [os.path.join(PKG, "csrc", "lpm.hip"), os.path.join(PKG, "csrc", "lpm_receptor.hip")]
+DEPS = SRC + [os.path.join(PKG, "csrc", "lpm_device.h"), os.path.join(PKG, "csrc", "lpm_host.h"),
+              os.path.join(ROOT, "include", "lpm.h")]
 LIB = os.path.join(PKG, "liblpm.so")
 ARCH = os.environ.get("LPM_OFFLOAD_ARCH", "gfx950")
 

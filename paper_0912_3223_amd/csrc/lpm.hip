@@ -35,17 +35,9 @@
 
 #include "lpm.h"
 #include "lpm_device.h"
+#include "lpm_host.h"
 
 namespace lpm {
-
-constexpr int kBlock = 256;
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ long long birth(long long gid, long long s_release,
-                                           long long n_total)
-{
-    return (gid * s_release) / n_total;
-}
 
 // exp(x) - 1 for x <= 0.  Per-step rates times dt are small (|x| < 1e-3 in
 // practice), where the Taylor series of exp to x^4/24 is exact to float
@@ -278,47 +270,15 @@ __device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
                                        double (&led)[3 * NNUC + 1], Dwell<NNUC>& dw)
 {
     const float age = (float)(s - b) * p.dt;
-    // weather at the start-of-step position and time (Eq. 1): the loads are
-    // issued first; everything up to the interpolation is independent of them
-    WindTap<NCOMP, TIME> tap;
-    wind_gather<NCOMP, TIME, LEVELS>(p, x, y, z, (float)s * p.dt, tap);
-    // random numbers of Eq. (2)
-    float xi0, xi1, xi2;
-    normals3<!ENS>(gid, (uint32_t)s, p.key0, sv.key1, xi0, xi1, xi2);
-    // diffusivity (Eq. 3) with the drift and midpoint evaluation
-    float K, dK, Km, dKm;
-    kz_profile<KZ>(p, z, K, dK);
-    const float zm = clampf(fmaf(p.half_dt, dK, z), 0.0f, p.H_mix);
-    kz_profile<KZ>(p, zm, Km, dKm);
+    // wind sample, random numbers, diffusivity, move and fold
+    float xn, yn, zn;
+    motion<NCOMP, TIME, LEVELS, KZ, !ENS>(p, sv.wscale, sv.key1, gid, s, x, y, z, xn, yn, zn);
     // decay factors at the start of the step
     float D[NNUC];
 #pragma unroll
     for (int n = 0; n < NNUC; ++n) D[n] = __builtin_amdgcn_exp2f(-p.lam_l2e[n] * age);
-    float uvw[3];
-    wind_interp<NCOMP, TIME>(tap, uvw);
-    // move (Eq. 1 with Eq. 2)
-    const float xn = fmaf(xi0, p.sKh, fmaf(sv.wscale * uvw[0], p.dt, x));
-    const float yn = fmaf(xi1, p.sKh, fmaf(sv.wscale * uvw[1], p.dt, y));
-    float zn = fmaf(xi2 * __builtin_amdgcn_sqrtf(Km), p.s2dt,
-                    fmaf(fmaf(sv.wscale, uvw[2], dK), p.dt, z));
-    // reflection at the ground and the lid: one fold each, and the general
-    // fold-until-inside for the (never seen) larger steps
-    zn = fabsf(zn);
-    if (zn > p.H_top) zn = 2.0f * p.H_top - zn;
-    if (zn < 0.0f || zn > p.H_top) {
-#pragma unroll 1
-        for (int it = 0; it < 64; ++it) {
-            if (zn < 0.0f) zn = -zn;
-            else if (zn > p.H_top) zn = 2.0f * p.H_top - zn;
-            else break;
-        }
-    }
     // deposition rate at the new position (Sec. 2)
-    float k = 0.0f;
-    if constexpr (DEP) {
-        if (zn < p.h_s) k = fmaxf(fmaf(-sv.dry_c2, zn, sv.dry_c1), 0.0f);
-        if (p.L0 > 0.0f) k += wet_rate(p, xn, yn);
-    }
+    const float k = DEP ? deposition_rate(p, sv.dry_c1, sv.dry_c2, xn, yn, zn) : 0.0f;
     const float mn = k > 0.0f ? m * __builtin_amdgcn_exp2f(-1.4426950408889634f * k * p.dt) : m;
     // decay and deposition of each nuclide's activity this step
     float dsum[NNUC];
@@ -746,9 +706,9 @@ __global__ __launch_bounds__(kBlock) void to_f32(const double* __restrict__ src,
 // ===========================================================================
 // Host side: validation, constant folding, launches.
 // ===========================================================================
-namespace {
+namespace lpm_host {
 
-thread_local char g_msg[512] = "";
+thread_local char g_msg[kMsgLen] = "";
 
 // Launch tuning of the persistent step kernel (process-wide; set by the
 // autotuner or lpm_set_launch).
@@ -858,7 +818,8 @@ unsigned blocks_for(long long n)
     return (unsigned)((n + lpm::kBlock - 1) / lpm::kBlock);
 }
 
-}  // namespace
+}  // namespace lpm_host
+using namespace lpm_host;
 
 extern "C" {
 
@@ -923,7 +884,7 @@ int lpm_release_particles(const lpm_state* st, const lpm_source* src, const lpm_
 
 }  // extern "C"
 
-namespace {
+namespace lpm_host {
 
 int fill_field(lpm::StepConst& p, const lpm_field* f)
 {
@@ -1106,7 +1067,8 @@ void launch_step_lev(bool lev, int nnuc, int kz, bool dep, unsigned nb, hipStrea
     else launch_step_n<NCOMP, TIME, false>(nnuc, kz, dep, nb, s, p);
 }
 
-}  // namespace
+}  // namespace lpm_host
+using namespace lpm_host;
 
 extern "C" {
 

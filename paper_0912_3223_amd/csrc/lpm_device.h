@@ -11,6 +11,15 @@
 
 namespace lpm {
 
+constexpr int kBlock = 256;  // threads per block of every kernel
+
+// Birth step of global particle id gid (continuous uniform release).
+__device__ __forceinline__ long long birth(long long gid, long long s_release,
+                                           long long n_total)
+{
+    return (gid * s_release) / n_total;
+}
+
 // One scenario of an ensemble launch, as uploaded to device memory.
 struct DevScen {
     long long qbase;    // first work-queue index of the scenario
@@ -337,6 +346,69 @@ __device__ __forceinline__ float wet_rate(const StepConst& p, float x, float y)
     const float yr = fmaf(p.r_ca_b, dy, -p.r_sa_b * dx);
     const float re = __builtin_amdgcn_sqrtf(fmaf(xr, xr, yr * yr));
     return p.L0 * clampf(fmaf(1.0f - re, p.inv_edge, 0.5f), 0.0f, 1.0f);
+}
+
+// Fold of z into [0, H_top] (reflection at the ground and the lid): one
+// fold each, and the general fold-until-inside for the (never seen) larger
+// steps.  *sign receives the slope of the fold (+1 or -1).
+__device__ __forceinline__ float fold_z(float zn, float H_top, float* sign = nullptr)
+{
+    float sg = zn < 0.0f ? -1.0f : 1.0f;
+    zn = fabsf(zn);
+    if (zn > H_top) {
+        zn = 2.0f * H_top - zn;
+        sg = -sg;
+    }
+    if (zn < 0.0f || zn > H_top) {
+#pragma unroll 1
+        for (int it = 0; it < 64; ++it) {
+            if (zn < 0.0f) zn = -zn;
+            else if (zn > H_top) zn = 2.0f * H_top - zn;
+            else break;
+            sg = -sg;
+        }
+    }
+    if (sign) *sign = sg;
+    return zn;
+}
+
+// Motion of one particle over step s (Eq. 1 with Eq. 2, the Ito drift and
+// Visser's midpoint for K_z, then the fold): the wind is sampled at the
+// start-of-step position and time.  The loads are issued first; everything
+// up to the interpolation is independent of them.  Returns the vertical
+// normal xi2 (the one random number the derivative of the step needs).
+template <int NCOMP, bool TIME, bool LEVELS, int KZ, bool UNIFORM_KEY>
+__device__ __forceinline__ float motion(const StepConst& p, float wscale, uint32_t key1,
+                                        uint32_t gid, int s, float x, float y, float z,
+                                        float& xn, float& yn, float& zn)
+{
+    WindTap<NCOMP, TIME> tap;
+    wind_gather<NCOMP, TIME, LEVELS>(p, x, y, z, (float)s * p.dt, tap);
+    float xi0, xi1, xi2;
+    normals3<UNIFORM_KEY>(gid, (uint32_t)s, p.key0, key1, xi0, xi1, xi2);
+    float K, dK, Km, dKm;
+    kz_profile<KZ>(p, z, K, dK);
+    const float zm = clampf(fmaf(p.half_dt, dK, z), 0.0f, p.H_mix);
+    kz_profile<KZ>(p, zm, Km, dKm);
+    float uvw[3];
+    wind_interp<NCOMP, TIME>(tap, uvw);
+    xn = fmaf(xi0, p.sKh, fmaf(wscale * uvw[0], p.dt, x));
+    yn = fmaf(xi1, p.sKh, fmaf(wscale * uvw[1], p.dt, y));
+    zn = fold_z(fmaf(xi2 * __builtin_amdgcn_sqrtf(Km), p.s2dt,
+                     fmaf(fmaf(wscale, uvw[2], dK), p.dt, z)),
+                p.H_top);
+    return xi2;
+}
+
+// Deposition rate at the post-move position (Sec. 2): dry v_d phi(z) =
+// c1 - c2 z below h_s, plus wet scavenging in the rain region.
+__device__ __forceinline__ float deposition_rate(const StepConst& p, float dry_c1, float dry_c2,
+                                                 float x, float y, float z)
+{
+    float k = 0.0f;
+    if (z < p.h_s) k = fmaxf(fmaf(-dry_c2, z, dry_c1), 0.0f);
+    if (p.L0 > 0.0f) k += wet_rate(p, x, y);
+    return k;
 }
 
 }  // namespace lpm

@@ -11,11 +11,12 @@ from typing import Callable, Iterable, Optional
 import numpy as np
 import torch
 
-from . import (Accum, Field, Grid, Physics, Schedule, Scenario, Source, State, CTRL_WORDS,
-               LEDGER_SLOTS, LEDGER_STRIDE, SCENARIO_BYTES, accum_reset, autotune_ensemble,
-               ensemble_prepare, grid_concentration, grid_deposition, grid_records, read_ledger,
-               release_ensemble, release_particles, step_ensemble, step_particles,
-               step_particles_record, check)
+from . import (Accum, Field, Grid, Physics, Receptors, Schedule, Scenario, Source, State,
+               CTRL_WORDS, LEDGER_SLOTS, LEDGER_STRIDE, SCENARIO_BYTES, accum_reset,
+               adjoint_workspace, autotune_ensemble, ensemble_prepare, grid_concentration,
+               grid_deposition, grid_records, read_ledger, receptor_adjoint,
+               receptor_concentration, release_ensemble, release_particles, step_ensemble,
+               step_particles, step_particles_record, check)
 
 
 def make_source(src) -> Source:
@@ -295,3 +296,81 @@ class EnsembleRun:
     def state(self, c: int):
         a, n = int(self.offsets[c]), self.counts[c]
         return {k: getattr(self, k)[a:a + n].double().cpu().numpy() for k in "xyzm"}
+
+
+class ReceptorRun:
+    """Receptor concentrations of one release and their gradient with respect
+    to theta = (h, q, s_w, v_d) (source height, release rate, wind scale,
+    dry-deposition velocity), all on the device.
+
+    forward: release, one whole-run step launch that records the state after
+    every ``case.out_every``-th step (the output steps, which are also the
+    checkpoints of the gradient), and the Gaussian-kernel receptor gridding.
+    backward: the adjoint sweep, segment by segment from the checkpoints."""
+
+    def __init__(self, case, receptors, device: str = "cuda"):
+        if case.n_steps % case.out_every:
+            raise ValueError("the run length must be a multiple of the output interval")
+        self.case = case
+        self.run = DeviceRun(case, device)
+        self.every = case.out_every
+        self.n_rec = case.n_steps // case.out_every
+        self.rec = self.run.record_buffer(self.n_rec)
+        dev = self.run.device
+        self.rx = torch.tensor(receptors.x, dtype=torch.float32, device=dev)
+        self.ry = torch.tensor(receptors.y, dtype=torch.float32, device=dev)
+        self.rz = torch.tensor(receptors.z, dtype=torch.float32, device=dev)
+        self.rcp = Receptors(self.rx.data_ptr(), self.ry.data_ptr(), self.rz.data_ptr(),
+                             len(receptors.x), receptors.sigma_h, receptors.sigma_z,
+                             receptors.weight)
+        self.c = torch.zeros(len(receptors.x), dtype=torch.float64, device=dev)
+        self.grad = torch.zeros(5, dtype=torch.float64, device=dev)
+        nbytes = adjoint_workspace(self.run.fld, self.run.sch, self.every)
+        self.work = torch.empty((nbytes + 15) // 16 * 4, dtype=torch.float32, device=dev)
+        self.theta = (case.source.h, case.source.q, case.source.wind_scale, case.source.v_d)
+
+    def set_theta(self, theta):
+        h, q, sw, vd = (float(t) for t in theta)
+        self.theta = (h, q, sw, vd)
+        src = self.run.src
+        src.h, src.q, src.wind_scale, src.v_d = h, q, sw, vd
+
+    def forward(self, theta=None) -> torch.Tensor:
+        """Receptor concentrations c [n] (float64, device; reused buffer)."""
+        if theta is not None:
+            self.set_theta(theta)
+        r = self.run
+        r.reset()
+        r.release(0, self.case.n_steps)
+        r.step_record(0, self.case.n_steps, self.every - 1, self.every, self.n_rec, self.rec)
+        receptor_concentration(self.rec, r.rec_stride, self.every - 1, self.every, self.n_rec,
+                               r.src, r.sch, r.ph, self.rcp, self.c)
+        return self.c
+
+    def backward(self, gbar: torch.Tensor) -> torch.Tensor:
+        """grad [5] (float64, device; reused buffer): sum_r gbar_r dc_r/dtheta
+        for theta = (h, q, s_w, v_d), then sum_r gbar_r c_r.  Uses the
+        record of the last forward()."""
+        g = gbar.to(device=self.run.device, dtype=torch.float64).contiguous()
+        r = self.run
+        receptor_adjoint(self.rec, r.rec_stride, self.every, self.n_rec, r.src, r.sch, r.fld,
+                         r.ph, self.rcp, g, self.grad, self.work)
+        return self.grad
+
+
+class ReceptorConcentration(torch.autograd.Function):
+    """c = ReceptorConcentration.apply(theta, run): receptor concentrations
+    as a differentiable function of theta = (h, q, s_w, v_d) (a float64
+    tensor of 4); the backward pass is liblpm's adjoint."""
+
+    @staticmethod
+    def forward(ctx, theta, run):
+        run.forward(theta.detach().cpu().tolist())
+        ctx.run = run
+        ctx.theta_device = theta.device
+        return run.c.clone()
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        g = ctx.run.backward(grad_c)
+        return g[:4].to(ctx.theta_device).clone(), None

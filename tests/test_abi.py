@@ -35,7 +35,7 @@ def test_struct_layout_matches_header(tmp_path):
     structs = {"lpm_state": L.State, "lpm_source": L.Source, "lpm_schedule": L.Schedule,
                "lpm_field": L.Field, "lpm_physics": L.Physics, "lpm_grid": L.Grid,
                "lpm_accum": L.Accum, "lpm_scenario": L.Scenario, "lpm_ensemble": L.Ensemble,
-               "lpm_tuning": L.Tuning}
+               "lpm_tuning": L.Tuning, "lpm_receptors": L.Receptors}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lpm.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -161,3 +161,30 @@ def test_empty_window_launches_nothing(args):
     empty.n_local = 0
     assert code(L, "lpm_step_particles", st, src, empty, fld, ph, 0, 1, acc, None) == L.LPM_OK
     assert code(L, "lpm_release_particles", st, src, empty, ph, 0, 1, acc, None) == L.LPM_OK
+
+
+def test_receptor_entry_points_reject_bad_arguments(args):
+    L, st, src, sch, ph, fld, acc, grid = args
+    fake = C.c_void_p(0x10000)
+    rcp = L.Receptors(0x10000, 0x10000, 0x10000, 50, 250.0, 40.0, 300.0)
+    conc = lambda r, *o: code(L, "lpm_receptor_concentration", fake, 1000, 59, 60, 72, src, sch,
+                              ph, r, *o)
+    bad_n = L.Receptors.from_buffer_copy(rcp)
+    bad_n.n = L.LPM_MAX_RECEPTORS + 1 if hasattr(L, "LPM_MAX_RECEPTORS") else 1025
+    assert conc(bad_n, fake, None) == L.LPM_EINVAL
+    bad_s = L.Receptors.from_buffer_copy(rcp)
+    bad_s.sigma_h = 0.0
+    assert conc(bad_s, fake, None) == L.LPM_EINVAL
+    assert conc(rcp, C.c_void_p(0x10004), None) == L.LPM_EINVAL  # misaligned c_out
+    assert b"c_out" in L.lib().lpm_last_error()
+    # records shorter than the particles
+    assert code(L, "lpm_receptor_concentration", fake, 999, 59, 60, 72, src, sch, ph, rcp, fake,
+                None) == L.LPM_EINVAL
+    adj = lambda work_bytes, s=src: code(L, "lpm_receptor_adjoint", fake, 1000, 60, 72, s, sch,
+                                         fld, ph, rcp, fake, fake, fake, work_bytes, None)
+    assert adj(16) == L.LPM_EINVAL and b"workspace" in L.lib().lpm_last_error()
+    q0 = L.Source.from_buffer_copy(src)
+    q0.q = 0.0
+    assert adj(1 << 40, q0) == L.LPM_EINVAL
+    n = C.c_int64(0)
+    assert code(L, "lpm_adjoint_workspace", fld, sch, 0, C.byref(n)) == L.LPM_EINVAL
