@@ -13,6 +13,12 @@ on the 200 x 200 x 30 x 2 cloud-in-cell grid every 60 steps, and the final
 deposition grid.  `value` = active particle-steps per second over the timed
 runs (inputs resident in HBM).
 
+Also reported on the same line: gradient evaluations per second of a
+receptor log-misfit with respect to (source height, release rate, wind
+scale, deposition velocity) on the same workload (forward + adjoint), the
+64-scenario batched ensemble against 64 sequential plain runs, and the FP64
+oracle's rate on the host cores.
+
     python bench.py [--steps K] [--warmup W] [--spl STEPS_PER_LAUNCH]
 """
 from __future__ import annotations
@@ -84,6 +90,10 @@ def parse():
     ap.add_argument("--ensemble-steps", type=int, default=2)
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the 64-scenario batched-vs-sequential comparison")
+    ap.add_argument("--adjoint-steps", type=int, default=3,
+                    help="timed gradient evaluations of the receptor misfit")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the gradient (adjoint) measurement")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one plain device-to-device copy of this size before timing "
                          "(reference dispatch for hardware byte counters)")
@@ -158,6 +168,55 @@ def ensemble_vs_plain(a):
             "autotuned": {"refill_every": tune.refill_every, "refill_min": tune.refill_min,
                           "blocks_per_cu": tune.blocks_per_cu,
                           "best_trial_ms": tune.best_ms, "worst_trial_ms": tune.worst_ms}}
+
+
+def adjoint_bench(a):
+    """Gradient evaluations per second of the receptor misfit at theta0 on
+    the 1e6-particle 6 h workload: forward (release, whole-run step with the
+    output-step states recorded every 60 steps, Gaussian-kernel receptor
+    gridding) plus the adjoint sweep from those checkpoints."""
+    import torch
+    import synth
+    import paper_0912_3223_amd as L
+    rec, obs, _ = synth.load_receptors(os.path.join(ROOT, "tests", "golden", "c4_receptors.json"))
+    case = synth.c4()
+    run = L.ReceptorRun(case, rec)
+    o = torch.as_tensor(obs, device="cuda")
+    eps = 1e-6 * float(o.max())
+    stream = torch.cuda.current_stream()
+    ev = []
+
+    def evaluate(timed):
+        c = run.forward(synth.THETA0)
+        gbar = 2.0 * (torch.log(c + eps) - torch.log(o + eps)) / (c + eps)
+        if timed:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        g = run.backward(gbar)
+        if timed:
+            e1.record(stream)
+            ev.append((e0, e1))
+        return c, g
+
+    evaluate(False)
+    torch.cuda.synchronize()
+    psteps = run.run.particle_steps()
+    t0 = time.perf_counter()
+    for _ in range(a.adjoint_steps):
+        c, g = evaluate(True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.adjoint_steps
+    back_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
+    loss = float(((torch.log(c + eps) - torch.log(o + eps)) ** 2).sum())
+    return {"workload": "receptor log-misfit gradient in (h, q, s_w, v_d) at theta0 = "
+                        "(50 m, 1, 1, 0.002 m/s); 1e6 particles, 4320 steps, 50 ground "
+                        "receptors (Gaussian kernel 250 m / 40 m), checkpoints every 60 steps",
+            "gradient_evals_per_s": 1.0 / dt, "ms_per_gradient": dt * 1e3,
+            "adjoint_kernel_ms": back_ms, "forward_ms": dt * 1e3 - back_ms,
+            "particle_steps_forward": psteps,
+            "adjoint_particle_steps_per_s": psteps / (back_ms / 1e3),
+            "loss": loss, "grad": [float(v) for v in g[:4].cpu()]}
 
 
 def main():
@@ -267,6 +326,8 @@ def main():
                      "step_kernel_share": step_total_s / (ms / 1e3)},
         "ledger_first_nuclide": list(map(float, ledger[0])),
     }
+    if not a.no_adjoint:
+        out["adjoint"] = adjoint_bench(a)
     if not a.no_ensemble:
         out["ensemble"] = ensemble_vs_plain(a)
     if not a.no_cpu_baseline:
