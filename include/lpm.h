@@ -120,22 +120,43 @@ typedef struct {
 
 /* Physical constants (Sec. 2, Eqs. 2-3).
  *  kz_kind 0: K_z = Kz_const;  1: K_z = kappa_ustar (z + z0)(1 - z/H_mix);
- *  2: K_z = kappa_ustar (z + z0)(1 - z/H_mix)^2 (Eq. 3 with Phi = 1); K_z = 0
- *  above H_mix.  The vertical step adds the drift dK_z/dz dt and evaluates
- *  K_z at z + dK_z/dz dt / 2 clamped to [0, H_mix]; with constant K_z this is
- *  Eq. (2) as printed.
+ *  2: K_z = kappa_ustar (z + z0)(1 - z/H_mix)^2 (Eq. 3 with Phi = 1);
+ *  3: Eq. 3 with the similarity function for heat, K_z = kappa_ustar (z + z0)
+ *     (1 - z/H_mix)^2 / Phi_h((z + z0) inv_L), Phi_h(s) = 1 + 5 s for stable
+ *     (inv_L >= 0) and (1 - 16 s)^(-1/2) for unstable stratification
+ *     (Businger-Dyer forms; inv_L = 1/L, the inverse Monin-Obukhov length,
+ *     0 = neutral, which is kind 2; see lpm_surface_layer).
+ *  K_z = 0 above H_mix.  The vertical step adds the drift dK_z/dz dt and
+ *  evaluates K_z at z + dK_z/dz dt / 2 clamped to [0, H_mix]; with constant
+ *  K_z this is Eq. (2) as printed.
  *  H_lid > 0: z is folded into [0, H_lid]; H_lid <= 0: ground reflection only.
  *  Dry deposition rate v_d * (2/h_s)(1 - z/h_s) for z < h_s; wet rate
  *  Lambda0 * clamp((1 - r)/rain_edge + 1/2, 0, 1), r the elliptical radius
  *  about (rain_cx, rain_cy) with semi-axes rain_a, rain_b, major axis at
  *  rain_angle (radians, counter-clockwise from +x).
- *  lambda[n]: decay constants (1/s) of n_nuc <= 4 nuclides. */
+ *  lambda[n]: decay constants (1/s) of n_nuc <= 4 nuclides.
+ *  chain 0: every nuclide is released with activity a0 = q s_release dt /
+ *     n_total per particle and decays on its own.  chain 1: the nuclides
+ *     form the decay chain 0 -> 1 -> ... -> n_nuc - 1 (each decay of n makes
+ *     one atom of n + 1; Bateman), only nuclide 0 is released (activity a0)
+ *     and the lambdas must be positive and distinct.  In a chain, entry 0
+ *     ("released") of nuclide n > 0 in the ledger counts its ingrowth
+ *     (lambda_n times the atoms made by the parent's decay), so released =
+ *     airborne + deposited + decayed + exited holds per nuclide.
+ *  dep_mode 0: deposition depletes the particle's mass at rate k (mass
+ *     depletion).  1: deposition is stochastic (Sec. 2): a particle with rate
+ *     k at its post-move position is removed in the step with probability
+ *     1 - exp(-k dt), decided by the uniform of Philox counter (g, step, 1, 0),
+ *     and its whole activity at the end of the step is deposited. */
 typedef struct {
     double dt, Kh, Kz_const, kappa_ustar, z0, H_mix, H_lid, h_s;
     int32_t kz_kind, n_nuc;
     double lambda[4];
     double Lambda0, rain_cx, rain_cy, rain_a, rain_b, rain_angle, rain_edge;
     uint64_t seed;
+    double inv_L;     /* kz_kind 3: inverse Monin-Obukhov length (1/m) */
+    int32_t chain;    /* 0 or 1, see above */
+    int32_t dep_mode; /* 0 or 1, see above */
 } lpm_physics;
 
 /* Output grid (Sec. 3.2: activities summed on a rectangular grid).  mode 0:
@@ -348,6 +369,22 @@ int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens,
                           const lpm_physics* ph, const lpm_grid* dep_grid, double* dep,
                           double* ledgers, uint32_t* ctrl, int32_t trial_steps,
                           lpm_tuning* out, lpm_stream stream);
+
+/* Friction velocity and inverse Monin-Obukhov length of the surface layer
+ * from the vertical stratification (Sec. 2: u* and L computed iteratively
+ * from the actual stratification), for kz_kind 3: wind speed U (m/s) at
+ * height z_ref (m) over roughness length z0 (m), potential-temperature
+ * difference dtheta = theta(z_ref) - theta(z0) (K), mean temperature T0 (K).
+ * Monin-Obukhov similarity with the Businger-Dyer gradients (heat: 1 + 5 s
+ * stable, (1 - 16 s)^(-1/2) unstable; momentum: 1 + 5 s, (1 - 16 s)^(-1/4))
+ * in Paulson's integrated forms, iterated from the neutral solution
+ * u* = kappa U / ln(z_ref / z0) (kappa = 0.4, g = 9.81 m/s^2) until inv_L
+ * changes by less than 1e-12 relative.  Host-only, synchronous.  Writes
+ * *ustar (m/s) and *inv_L (1/m); LPM_EINVAL for invalid input or when the
+ * iteration does not converge (e.g. too stable: the bulk Richardson number
+ * beyond the critical value of the stable profile, 0.2). */
+int lpm_surface_layer(double U, double z_ref, double z0, double dtheta, double T0,
+                      double* ustar, double* inv_L);
 
 /* ---------------------------------------------------------------------------
  * Receptor concentrations and their gradient (source inversion)

@@ -57,6 +57,7 @@ class Problem(C.Structure):
         ("cdx", C.c_double), ("cdy", C.c_double), ("cdz", C.c_double),
         ("dnx", C.c_int32), ("dny", C.c_int32), ("dmode", C.c_int32), ("ddensity", C.c_int32),
         ("dx0", C.c_double), ("dy0", C.c_double), ("ddx", C.c_double), ("ddy", C.c_double),
+        ("inv_L", C.c_double), ("chain", C.c_int32), ("dep_mode", C.c_int32),
     ]
 
 
@@ -96,6 +97,10 @@ def lib():
                                    C.POINTER(C.c_int64)]
         L.orc_simulate.restype = C.c_int
         L.orc_airborne.argtypes = [P, C.c_int32, dp, dp]
+        L.orc_activity_fraction.argtypes = [P, C.c_int, C.c_double]
+        L.orc_activity_fraction.restype = C.c_double
+        L.orc_surface_layer.argtypes = [C.c_double] * 5 + [dp, dp]
+        L.orc_surface_layer.restype = C.c_int
         RP = C.POINTER(Receptors)
         L.orc_receptor_forward.argtypes = [P, RP, C.c_int32, C.c_int32, dp, dp, C.c_int32,
                                            C.POINTER(C.c_int64)]
@@ -129,6 +134,7 @@ class Oracle:
         p.kappa_ustar, p.z0, p.H_mix, p.H_lid, p.h_s = (ph.kappa_ustar, ph.z0, ph.H_mix,
                                                         ph.H_lid, ph.h_s)
         p.kz_kind, p.n_nuc = ph.kz_kind, ph.n_nuc
+        p.inv_L, p.chain, p.dep_mode = ph.inv_L, ph.chain, ph.dep_mode
         for n, lam in enumerate(ph.lambdas):
             p.lam[n] = lam
         r = ph.rain
@@ -204,6 +210,10 @@ class Oracle:
         lib().orc_grid_concentration(C.byref(self.p), s, *[_dp(a) for a in arr], _dp(out))
         return out
 
+    def activity_fraction(self, n: int, t: float) -> float:
+        """Activity of nuclide n at age t per unit released activity."""
+        return lib().orc_activity_fraction(C.byref(self.p), n, t)
+
     # -- receptor concentrations and their gradient ----------------------------
     def _receptors(self, rec):
         xyz = [np.ascontiguousarray(a, dtype=np.float64) for a in (rec.x, rec.y, rec.z)]
@@ -249,6 +259,14 @@ class Oracle:
         mm = np.ascontiguousarray(m, dtype=np.float64)
         lib().orc_airborne(C.byref(self.p), s, _dp(mm), _dp(out))
         return out[: self.case.physics.n_nuc]
+
+
+def surface_layer(U, z_ref, z0, dtheta, T0):
+    """(u*, 1/L) of the surface layer by the oracle's iteration."""
+    us, il = C.c_double(), C.c_double()
+    if lib().orc_surface_layer(U, z_ref, z0, dtheta, T0, C.byref(us), C.byref(il)) != 0:
+        raise ValueError("no surface-layer solution")
+    return us.value, il.value
 
 
 def philox(ctr, key):

@@ -67,6 +67,10 @@ typedef struct {
     /* deposition grid */
     int32_t dnx, dny, dmode, ddensity;
     double dx0, dy0, ddx, ddy;
+    /* variants: Eq. (3) stability (kz_kind 3), decay chain, stochastic
+     * deposition */
+    double inv_L;
+    int32_t chain, dep_mode;
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -213,6 +217,20 @@ void orc_wind(const orc_problem* P, double x, double y, double z, double t,
 /* Vertical diffusivity, Eq. (3) in the neutral limit Phi = 1                 */
 /* ------------------------------------------------------------------------ */
 
+/* Similarity function for heat Phi_h(s), s = z/L, and its derivative in s
+ * (Businger-Dyer: 1 + 5 s stable, (1 - 16 s)^(-1/2) unstable). */
+static void phi_heat(double s, double* phi, double* dphi)
+{
+    if (s >= 0.0) {
+        *phi = 1.0 + 5.0 * s;
+        *dphi = 5.0;
+    } else {
+        double w = 1.0 - 16.0 * s;
+        *phi = 1.0 / sqrt(w);
+        *dphi = 8.0 / (w * sqrt(w));
+    }
+}
+
 void orc_kz(const orc_problem* P, double z, double* K, double* dK)
 {
     if (P->kz_kind == 0) { *K = P->Kz_const; *dK = 0.0; return; }
@@ -223,9 +241,17 @@ void orc_kz(const orc_problem* P, double z, double* K, double* dK)
     if (P->kz_kind == 1) {
         *K = ku * (z + P->z0) * g;
         *dK = ku * (g - (z + P->z0) / H);
-    } else {
+    } else if (P->kz_kind == 2) {
         *K = ku * (z + P->z0) * g * g;
         *dK = ku * (g * g - 2.0 * (z + P->z0) * g / H);
+    } else {
+        /* Eq. (3): k u* z / Phi(z/L) (1 - z/H)^2, with z + z0 for z */
+        double zz = z + P->z0, phi, dphi;
+        phi_heat(zz * P->inv_L, &phi, &dphi);
+        double f = ku * zz * g * g;
+        double df = ku * (g * g - 2.0 * zz * g / H);
+        *K = f / phi;
+        *dK = df / phi - f * dphi * P->inv_L / (phi * phi);
     }
 }
 
@@ -304,6 +330,51 @@ static double a0_of(const orc_problem* P)
     return P->q * (double)P->s_release * P->dt / (double)P->n_total;
 }
 
+/* Activity bookkeeping per nuclide.  With independent nuclides nuclide n
+ * keeps a0 exp(-lambda_n t).  In a decay chain 0 -> 1 -> ... released as
+ * pure parent (activity a0), the Bateman solution gives nuclide n the
+ * activity a0 sum_j c_nj exp(-lambda_j t) with the textbook coefficients
+ *   c_nj = (lambda_n / lambda_0) prod_{p<n} lambda_p / prod_{p<=n, p!=j} (lambda_p - lambda_j)
+ * (j <= n; distinct lambdas). */
+static double act_coef(const orc_problem* P, int n, int j)
+{
+    if (!P->chain) return n == j ? 1.0 : 0.0;
+    if (j > n) return 0.0;
+    double num = P->lambda[n] / P->lambda[0];
+    for (int p = 0; p < n; ++p) num *= P->lambda[p];
+    double den = 1.0;
+    for (int p = 0; p <= n; ++p)
+        if (p != j) den *= P->lambda[p] - P->lambda[j];
+    return num / den;
+}
+
+/* Activity of nuclide n at age t per unit released activity. */
+double orc_activity_fraction(const orc_problem* P, int n, double t)
+{
+    double a = 0.0;
+    for (int j = 0; j < P->n_nuc; ++j) {
+        double c = act_coef(P, n, j);
+        if (c != 0.0) a += c * exp(-P->lambda[j] * t);
+    }
+    return a;
+}
+
+/* Time integral over one step, starting at age t, of the activity fraction
+ * of nuclide n times exp(-k tau) (tau the time into the step): the
+ * activity-seconds exposed to a removal rate k. */
+static double step_integral(const orc_problem* P, int n, double t, double k)
+{
+    double a = 0.0;
+    for (int j = 0; j < P->n_nuc; ++j) {
+        double c = act_coef(P, n, j);
+        if (c == 0.0) continue;
+        double r = P->lambda[j] + k;
+        double g = r > 0.0 ? -expm1(-r * P->dt) / r : P->dt;
+        a += c * exp(-P->lambda[j] * t) * g;
+    }
+    return a;
+}
+
 /* Concentration after step s (time (s + 1) dt) of the given particles:
  * A_n = a0 m exp(-lambda_n age), summed per nuclide on the concentration
  * grid; out[n_nuc][cnz][cny][cnx] is added to. */
@@ -320,7 +391,7 @@ void orc_grid_concentration(const orc_problem* P, int32_t s, const double* x,
         if (b > s || !(m[i] > 0.0)) continue;
         double age = (double)(s + 1 - b) * P->dt;
         for (int n = 0; n < P->n_nuc; ++n) {
-            double A = a0 * m[i] * exp(-P->lambda[n] * age);
+            double A = a0 * m[i] * orc_activity_fraction(P, n, age);
             bin3(out + n * cells, P->cnx, P->cny, P->cnz, P->cx0, P->cy0, P->cz0,
                  P->cdx, P->cdy, P->cdz, P->cmode, x[i], y[i], z[i], A / vol, 0);
         }
@@ -378,32 +449,45 @@ static void step_particle(const orc_problem* P, int64_t gid, int64_t b, int32_t 
     double zn = z + w * dt + dKz * dt + xi[2] * sqrt(2.0 * Kzm * dt);
     zn = fold(zn, P->H_lid);
 
-    /* decay and deposition at the new position */
+    /* decay and deposition at the new position.  Over the step, nuclide n
+     * spends S_n activity-seconds in the air (its activity times the
+     * surviving mass, integrated); k S_n is deposited, lambda_n S_n decays,
+     * and in a chain lambda_{n+1} S_n grows into the daughter. */
     double k = orc_dry_rate(P, zn) + orc_wet_rate(P, xn, yn);
-    double mn = m * exp(-k * dt);
     size_t cells = (size_t)P->dnx * P->dny;
     double area = P->ddensity ? P->ddx * P->ddy : 1.0;
+    double mn = m;
+    int removed = 0;
+    /* mass depletion: the rate acts on the mass; stochastic deposition: the
+     * particle stays whole in the air for the step, then is removed with
+     * probability 1 - exp(-k dt) (Sec. 2) */
+    double kk = P->dep_mode == 0 ? k : 0.0;
+    if (P->dep_mode == 0) {
+        mn = m * exp(-k * dt);
+    } else if (k > 0.0) {
+        double u[4];
+        orc_uniforms(P->seed, P->scenario, (uint32_t)gid, (uint32_t)s, 1u, u);
+        removed = u[0] <= -expm1(-k * dt);
+    }
     for (int n = 0; n < P->n_nuc; ++n) {
-        double lam = P->lambda[n];
-        double A = a0 * m * exp(-lam * age);
-        double r = lam + k;
-        if (r <= 0.0) continue;
-        double loss = A * (-expm1(-r * dt));
-        double d = loss * (k / r);
-        double c = loss * (lam / r);
+        double S = a0 * m * step_integral(P, n, age, kk);
+        double d = kk * S;
+        if (removed) d += a0 * m * orc_activity_fraction(P, n, age + dt);
         led[n * 4 + 1] += d;
-        led[n * 4 + 2] += c;
+        led[n * 4 + 2] += P->lambda[n] * S;
+        if (P->chain && n + 1 < P->n_nuc) led[(n + 1) * 4 + 0] += P->lambda[n + 1] * S;
         if (d != 0.0)
             bin3(dep + n * cells, P->dnx, P->dny, 1, P->dx0, P->dy0, 0.0, P->ddx,
                  P->ddy, 1.0, P->dmode, xn, yn, 0.0, d / area, 1);
     }
+    if (removed) mn = 0.0;
 
     /* leaving the simulated area inactivates the particle (Sec. 3.2) */
-    if (P->bounded) {
+    if (P->bounded && !removed) {
         double X1 = P->fx0 + P->nx * P->fdx, Y1 = P->fy0 + P->ny * P->fdy;
         if (xn < P->fx0 || xn >= X1 || yn < P->fy0 || yn >= Y1) {
             for (int n = 0; n < P->n_nuc; ++n)
-                led[n * 4 + 3] += a0 * mn * exp(-P->lambda[n] * (age + dt));
+                led[n * 4 + 3] += a0 * mn * orc_activity_fraction(P, n, age + dt);
             mn = 0.0;
         }
     }
@@ -430,8 +514,16 @@ int orc_simulate(const orc_problem* P, int32_t s_begin, int32_t s_end,
     if (!P || P->n_nuc < 1 || P->n_nuc > 4 || P->n_total <= 0 || P->s_release <= 0 ||
         P->n_local < 0 || P->id_stride <= 0 || !x || !y || !z || !m || !dep || !ledger ||
         (n_snap > 0 && (!snaps || !snap_steps)) || !P->f || P->nx < 1 || P->ny < 1 ||
-        P->nz < 1 || P->nt < 1 || (P->ncomp != 2 && P->ncomp != 3))
+        P->nz < 1 || P->nt < 1 || (P->ncomp != 2 && P->ncomp != 3) || P->kz_kind < 0 ||
+        P->kz_kind > 3 || (P->dep_mode != 0 && P->dep_mode != 1) || (P->chain != 0 && P->chain != 1))
         return -1;
+    if (P->chain) {
+        for (int n = 0; n < P->n_nuc; ++n) {
+            if (!(P->lambda[n] > 0.0)) return -1;
+            for (int j = 0; j < n; ++j)
+                if (P->lambda[j] == P->lambda[n]) return -1;
+        }
+    }
     int nth = 1;
 #ifdef _OPENMP
     nth = nthreads > 0 ? nthreads : omp_get_max_threads();
@@ -459,7 +551,7 @@ int orc_simulate(const orc_problem* P, int32_t s_begin, int32_t s_end,
                 int64_t b = birth_of(P, gid);
                 if (b == s) {
                     x[i] = P->xs; y[i] = P->ys; z[i] = P->h; m[i] = 1.0;
-                    for (int n = 0; n < P->n_nuc; ++n) my_led[n * 4 + 0] += a0;
+                    for (int n = 0; n < (P->chain ? 1 : P->n_nuc); ++n) my_led[n * 4 + 0] += a0;
                 }
                 if (b <= s && m[i] > 0.0) {
                     step_particle(P, gid, b, s, &x[i], &y[i], &z[i], &m[i], my_led, my_dep);
@@ -496,7 +588,7 @@ void orc_airborne(const orc_problem* P, int32_t s, const double* m, double* out)
         int64_t b = birth_of(P, gid);
         if (b > s || !(m[i] > 0.0)) continue;
         for (int n = 0; n < P->n_nuc; ++n)
-            out[n] += a0 * m[i] * exp(-P->lambda[n] * (double)(s + 1 - b) * P->dt);
+            out[n] += a0 * m[i] * orc_activity_fraction(P, n, (double)(s + 1 - b) * P->dt);
     }
 }
 
@@ -755,7 +847,7 @@ static double receptor_kernel(const orc_receptors* R, int r, double x, double y,
 static double decay_sum(const orc_problem* P, int64_t b, int32_t s)
 {
     double age = (double)(s + 1 - b) * P->dt, f = 0.0;
-    for (int n = 0; n < P->n_nuc; ++n) f += exp(-P->lambda[n] * age);
+    for (int n = 0; n < P->n_nuc; ++n) f += orc_activity_fraction(P, n, age);
     return f;
 }
 
@@ -765,7 +857,8 @@ static int receptor_args_ok(const orc_problem* P, const orc_receptors* R, int32_
     return P && R && R->n >= 0 && (R->n == 0 || (R->x && R->y && R->z)) && R->sigma_h > 0.0 &&
            R->sigma_z > 0.0 && out_every >= 1 && s_end >= 0 && P->n_nuc >= 1 && P->n_nuc <= 4 &&
            P->n_total > 0 && P->s_release > 0 && P->n_local >= 0 && P->id_stride > 0 && P->f &&
-           (P->ncomp == 2 || P->ncomp == 3) && P->q != 0.0;
+           (P->ncomp == 2 || P->ncomp == 3) && P->q != 0.0 && P->dep_mode == 0 &&
+           P->kz_kind >= 0 && P->kz_kind <= 2;
 }
 
 /* c[n_rec] (added to) receives the receptor concentrations of a run over
@@ -938,4 +1031,59 @@ int orc_receptor_adjoint(const orc_problem* P, const orc_receptors* R, int32_t s
     free(acc);
     free(paths);
     return 0;
+}
+
+
+/* ======================================================================== */
+/* Surface layer: friction velocity and Monin-Obukhov length               */
+/* ======================================================================== */
+/*
+ * Sec. 2 computes u* and L iteratively from the vertical stratification.
+ * Monin-Obukhov similarity with the Businger-Dyer gradient functions,
+ * integrated (Paulson 1970):
+ *   U      = (u*) / kappa [ln(z/z0) - psi_m(z/L) + psi_m(z0/L)]
+ *   dtheta = (theta*) / kappa [ln(z/z0) - psi_h(z/L) + psi_h(z0/L)]
+ *   L      = u*^2 T0 / (kappa g theta*)
+ * stable (s >= 0): psi_m = psi_h = -5 s;
+ * unstable: x = (1 - 16 s)^(1/4), psi_m = 2 ln((1 + x)/2) + ln((1 + x^2)/2)
+ *           - 2 atan(x) + pi/2, psi_h = 2 ln((1 + x^2)/2).
+ * Fixed-point iteration in 1/L from neutral (1/L = 0).
+ */
+static double psi_m(double s)
+{
+    if (s >= 0.0) return -5.0 * s;
+    double x = pow(1.0 - 16.0 * s, 0.25);
+    return 2.0 * log(0.5 * (1.0 + x)) + log(0.5 * (1.0 + x * x)) - 2.0 * atan(x) +
+           0.5 * 3.141592653589793238462643383279;
+}
+
+static double psi_h(double s)
+{
+    if (s >= 0.0) return -5.0 * s;
+    double x = pow(1.0 - 16.0 * s, 0.25);
+    return 2.0 * log(0.5 * (1.0 + x * x));
+}
+
+int orc_surface_layer(double U, double z_ref, double z0, double dtheta, double T0, double* ustar,
+                      double* inv_L)
+{
+    const double kappa = 0.4, g = 9.81;
+    if (!(U > 0.0 && z_ref > z0 && z0 > 0.0 && T0 > 0.0) || !ustar || !inv_L) return -1;
+    double il = 0.0, us = kappa * U / log(z_ref / z0);
+    for (int it = 0; it < 200; ++it) {
+        double fm = log(z_ref / z0) - psi_m(z_ref * il) + psi_m(z0 * il);
+        double fh = log(z_ref / z0) - psi_h(z_ref * il) + psi_h(z0 * il);
+        if (!(fm > 0.0) || !(fh > 0.0)) return -1;
+        us = kappa * U / fm;
+        double ts = kappa * dtheta / fh;
+        double nl = kappa * g * ts / (us * us * T0);
+        if (!isfinite(nl) || !(us > 0.0)) return -1;  /* diverged: too stable */
+        if (fabs(nl - il) <= 1e-12 * fabs(nl) || nl == il) {
+            *ustar = us;
+            *inv_L = nl;
+            return 0;
+        }
+        il = nl;
+    }
+    return -1;
 }

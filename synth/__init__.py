@@ -95,7 +95,8 @@ class Physics:
 
     kz_kind: 0 = constant ``Kz_const``; 1 = parabolic
     ``kappa_ustar (z + z0) (1 - z/H_mix)``; 2 = Eq. (3) with Phi = 1,
-    ``kappa_ustar (z + z0) (1 - z/H_mix)^2``.
+    ``kappa_ustar (z + z0) (1 - z/H_mix)^2``; 3 = Eq. (3) with the heat
+    similarity function of (z + z0) inv_L.
     """
     dt: float
     Kh: float
@@ -110,6 +111,9 @@ class Physics:
     Lambda0: float = 0.0
     rain: Rain = Rain()
     seed: int = 0
+    inv_L: float = 0.0    # kz_kind 3: inverse Monin-Obukhov length (1/m)
+    chain: int = 0        # 1: decay chain 0 -> 1 -> ..., parent released
+    dep_mode: int = 0     # 1: stochastic deposition (removal), 0: mass depletion
 
     @property
     def n_nuc(self) -> int:
