@@ -63,7 +63,8 @@ class Physics(C.Structure):
                 ("kz_kind", C.c_int32), ("n_nuc", C.c_int32), ("lam", C.c_double * 4),
                 ("Lambda0", C.c_double), ("rain_cx", C.c_double), ("rain_cy", C.c_double),
                 ("rain_a", C.c_double), ("rain_b", C.c_double), ("rain_angle", C.c_double),
-                ("rain_edge", C.c_double), ("seed", C.c_uint64)]
+                ("rain_edge", C.c_double), ("seed", C.c_uint64), ("inv_L", C.c_double),
+                ("chain", C.c_int32), ("dep_mode", C.c_int32)]
 
 
 class Grid(C.Structure):
@@ -137,6 +138,7 @@ def _load():
                                        P(Source), P(Schedule), P(Physics), P(Receptors),
                                        C.c_void_p, C.c_void_p],
         "lpm_adjoint_workspace": [P(Field), P(Schedule), C.c_int32, P(C.c_int64)],
+        "lpm_surface_layer": [C.c_double] * 5 + [P(C.c_double), P(C.c_double)],
         "lpm_receptor_adjoint": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, P(Source),
                                  P(Schedule), P(Field), P(Physics), P(Receptors), C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
@@ -159,6 +161,7 @@ EXPORTS = ("lpm_accum_reset", "lpm_release_particles", "lpm_step_particles",
            "lpm_read_ledger", "lpm_check", "lpm_set_launch", "lpm_set_launch_ex", "lpm_ensemble_prepare",
            "lpm_release_ensemble", "lpm_step_ensemble", "lpm_autotune_ensemble",
            "lpm_receptor_concentration", "lpm_adjoint_workspace", "lpm_receptor_adjoint",
+           "lpm_surface_layer",
            "lpm_last_error", "lpm_version")
 
 
@@ -304,6 +307,13 @@ def receptor_adjoint(rec: torch.Tensor, rec_stride: int, rec_every: int, n_rec: 
                                   C.byref(rcp), C.c_void_p(gbar.data_ptr()),
                                   C.c_void_p(grad_out.data_ptr()), C.c_void_p(work.data_ptr()),
                                   work.numel() * work.element_size(), _stream(stream)))
+
+
+def surface_layer(U: float, z_ref: float, z0: float, dtheta: float, T0: float):
+    """(u*, 1/L) of the surface layer (lpm_surface_layer)."""
+    us, il = C.c_double(), C.c_double()
+    _rc(_lib.lpm_surface_layer(U, z_ref, z0, dtheta, T0, C.byref(us), C.byref(il)))
+    return us.value, il.value
 
 
 def set_launch(refill_every: int = 16, blocks_per_cu: int = 0, refill_min: int = 64):

@@ -259,15 +259,31 @@ struct Dwell {
     }
 };
 
+// Per-lane ledger partials: deposited, decayed, exited per nuclide, the
+// particle-steps, and (general kernels, KZ == 4) the ingrowth of each nuclide
+// of a decay chain, booked into its "released" entry.
+template <int NNUC, int KZ>
+struct Ledger {
+    static constexpr int kSize = 3 * NNUC + 1 + (KZ == 4 ? NNUC : 0);
+    __device__ static constexpr int offset(int q)
+    {
+        return q < 3 * NNUC ? (q / 3) * 4 + 1 + q % 3
+                            : (q == 3 * NNUC ? LPM_LEDGER_PSTEPS : (q - 3 * NNUC - 1) * 4);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // One time step of one particle (Sec. 3.2 main loop; Eqs. 1-3).  Returns 1
-// when the particle left the area, 2 when it became non-finite, else 0.
+// when the particle left the area, 2 when it became non-finite, 3 when it was
+// removed by stochastic deposition, else 0.  KZ == 4 is the general kernel:
+// K_z kind at run time (including Eq. 3 with stability), decay chains and
+// stochastic deposition.
 // ---------------------------------------------------------------------------
 template <int NCOMP, bool TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS>
 __device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
                                        DepTable<NNUC>& tab, long long plane, uint32_t gid,
                                        int b, int s, float& x, float& y, float& z, float& m,
-                                       double (&led)[3 * NNUC + 1], Dwell<NNUC>& dw)
+                                       double (&led)[(Ledger<NNUC, KZ>::kSize)], Dwell<NNUC>& dw)
 {
     const float age = (float)(s - b) * p.dt;
     // wind sample, random numbers, diffusivity, move and fold
@@ -279,9 +295,46 @@ __device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
     for (int n = 0; n < NNUC; ++n) D[n] = __builtin_amdgcn_exp2f(-p.lam_l2e[n] * age);
     // deposition rate at the new position (Sec. 2)
     const float k = DEP ? deposition_rate(p, sv.dry_c1, sv.dry_c2, xn, yn, zn) : 0.0f;
-    const float mn = k > 0.0f ? m * __builtin_amdgcn_exp2f(-1.4426950408889634f * k * p.dt) : m;
+    float mn = k > 0.0f ? m * __builtin_amdgcn_exp2f(-1.4426950408889634f * k * p.dt) : m;
     // decay and deposition of each nuclide's activity this step
     float dsum[NNUC];
+    bool removed = false;
+    if constexpr (KZ == 4) {
+        // Over the step nuclide n spends S_n activity-seconds in the air
+        // (activity times surviving mass, integrated): k S_n deposits,
+        // lambda_n S_n decays and lambda_{n+1} S_n grows into the daughter of
+        // a chain.  With stochastic deposition the particle stays whole and is
+        // removed at the end of the step with probability 1 - exp(-k dt).
+        const float kk = p.dep_mode ? 0.0f : k;
+        if (p.dep_mode) {
+            mn = m;
+            if (k > 0.0f)
+                removed = removal_uniform<!ENS>(gid, (uint32_t)s, p.key0, sv.key1) <=
+                          -expm1_neg(-k * p.dt);
+        }
+        float DG[NNUC];
+#pragma unroll
+        for (int j = 0; j < NNUC; ++j) {
+            const float r = p.lam[j] + kk;
+            DG[j] = D[j] * (r > 0.0f ? -expm1_neg(-r * p.dt) * __builtin_amdgcn_rcpf(r) : p.dt);
+        }
+#pragma unroll
+        for (int n = 0; n < NNUC; ++n) {
+            float sa = 0.0f, se = 0.0f;
+#pragma unroll
+            for (int j = 0; j <= n; ++j) {
+                sa = fmaf(p.bc[n][j], DG[j], sa);
+                se = fmaf(p.bc[n][j], D[j] * p.edec[j], se);
+            }
+            const float S = sv.a0 * m * sa;
+            const float dep = removed ? sv.a0 * m * se : kk * S;
+            dsum[n] = dep * p.dscale;
+            led[3 * n + 0] += (double)dep;
+            led[3 * n + 1] += (double)(p.lam[n] * S);
+            if (n + 1 < NNUC && p.chain) led[3 * NNUC + 2 + n] += (double)(p.lam[n + 1] * S);
+        }
+        if (removed) mn = 0.0f;
+    } else {
 #pragma unroll
     for (int n = 0; n < NNUC; ++n) {
         const float A = sv.a0 * m * D[n];
@@ -299,6 +352,7 @@ __device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
             led[3 * n + 1] += (double)(A * p.cdec[n]);
         }
     }
+    }
     if (DEP && k > 0.0f) dw.add(p, tab, plane, xn, yn, dsum);
     x = xn;
     y = yn;
@@ -308,10 +362,19 @@ __device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
     if (!(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z) &&
           __builtin_isfinite(m)))
         return 2;
+    if (removed) return 3;
     // leaving the simulated area inactivates the particle
     if (p.bounded && (x < p.X0 || x >= p.X1 || y < p.Y0 || y >= p.Y1)) {
 #pragma unroll
-        for (int n = 0; n < NNUC; ++n) led[3 * n + 2] += (double)(sv.a0 * m * D[n] * p.edec[n]);
+        for (int n = 0; n < NNUC; ++n) {
+            float se = D[n] * p.edec[n];
+            if constexpr (KZ == 4) {
+                se = 0.0f;
+#pragma unroll
+                for (int j = 0; j <= n; ++j) se = fmaf(p.bc[n][j], D[j] * p.edec[j], se);
+            }
+            led[3 * n + 2] += (double)(sv.a0 * m * se);
+        }
         m = 0.0f;
         return 1;
     }
@@ -320,13 +383,12 @@ __device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
 
 // Adds one lane's ledger partials into a ledger slot (ensemble launches,
 // where lanes may hold different scenarios).
-template <int NNUC>
-__device__ __forceinline__ void lane_ledger(double (&led)[3 * NNUC + 1], double* slot)
+template <int NNUC, int KZ>
+__device__ __forceinline__ void lane_ledger(double (&led)[(Ledger<NNUC, KZ>::kSize)], double* slot)
 {
 #pragma unroll
-    for (int q = 0; q <= 3 * NNUC; ++q) {
-        const int off = q == 3 * NNUC ? LPM_LEDGER_PSTEPS : (q / 3) * 4 + 1 + q % 3;
-        if (led[q] != 0.0) atomicAdd(slot + off, led[q]);
+    for (int q = 0; q < Ledger<NNUC, KZ>::kSize; ++q) {
+        if (led[q] != 0.0) atomicAdd(slot + Ledger<NNUC, KZ>::offset(q), led[q]);
         led[q] = 0.0;
     }
 }
@@ -344,14 +406,14 @@ __device__ __forceinline__ void lane_ledger(double (&led)[3 * NNUC + 1], double*
 // Blocks per CU the compiler must fit: the lighter variants are held to 128
 // VGPRs (4 waves per SIMD; 15 % faster on the 1e6-particle run than the 3
 // waves the register allocation picks by itself); heavier ones would spill.
-template <int NCOMP, bool TIME, int NNUC, bool DEP, bool ENS>
+template <int NCOMP, bool TIME, int NNUC, int KZ, bool DEP, bool ENS>
 constexpr int step_min_blocks()
 {
-    return (NCOMP == 3) + TIME + DEP + (NNUC >= 3) + ENS <= 1 ? 4 : 1;
+    return (NCOMP == 3) + TIME + DEP + (NNUC >= 3) + ENS + (KZ == 4) <= 1 ? 4 : 1;
 }
 
 template <int NCOMP, bool TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS>
-__global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, DEP, ENS>())) void step_kernel(const StepConst pk)
+__global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP, ENS>())) void step_kernel(const StepConst pk)
 {
     constexpr int kWaves = kBlock / 64;
     // The launch constants live in LDS: kept in SGPRs across the persistent
@@ -380,9 +442,10 @@ __global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, DEP, EN
     int* rec_exit = reinterpret_cast<int*>(p.rec + 4ll * p.n_rec * p.rec_stride);
     const int slot_index = blockIdx.x % LPM_LEDGER_SLOTS;
 
-    double led[3 * NNUC + 1];  // deposited, decayed, exited per nuclide; steps
+    using LG = Ledger<NNUC, KZ>;
+    double led[LG::kSize];
 #pragma unroll
-    for (int q = 0; q <= 3 * NNUC; ++q) led[q] = 0.0;
+    for (int q = 0; q < LG::kSize; ++q) led[q] = 0.0;
 
     SrcVals sv{p.a0, p.wscale, p.dry_c1, p.dry_c2, p.key1, 0};
     int led_scen = 0;  // scenario the ledger partials belong to
@@ -422,7 +485,7 @@ __global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, DEP, EN
                         }
                         const DevScen& ds = p.scen[lo];
                         if (lo != led_scen) {
-                            lane_ledger<NNUC>(led, p.ledger + ((long long)led_scen * LPM_LEDGER_SLOTS + slot_index) * LPM_LEDGER_STRIDE);
+                            lane_ledger<NNUC, KZ>(led, p.ledger + ((long long)led_scen * LPM_LEDGER_SLOTS + slot_index) * LPM_LEDGER_STRIDE);
                             led_scen = lo;
                         }
                         sv = SrcVals{ds.a0, ds.wscale, ds.dry_c1, ds.dry_c2, ds.key1, lo};
@@ -482,7 +545,7 @@ __global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, DEP, EN
     if constexpr (DEP) tab.flush(lane, p.dep, plane);
 
     // ledger slot: [nuclide][released, deposited, decayed, exited], steps
-    constexpr int NV = 3 * NNUC + 1;
+    constexpr int NV = LG::kSize;
     if constexpr (ENS) {
         // lanes of a wave usually finish in one scenario: one atomic per entry
         const int s0 = __shfl(led_scen, 0, 64);
@@ -491,11 +554,10 @@ __global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, DEP, EN
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 const double v = wave_sum(led[q]);
-                const int off = q == 3 * NNUC ? LPM_LEDGER_PSTEPS : (q / 3) * 4 + 1 + q % 3;
-                if (lane == 0 && v != 0.0) atomicAdd(slot + off, v);
+                if (lane == 0 && v != 0.0) atomicAdd(slot + LG::offset(q), v);
             }
         } else {
-            lane_ledger<NNUC>(led, slot);
+            lane_ledger<NNUC, KZ>(led, slot);
         }
         return;
     }
@@ -512,8 +574,7 @@ __global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, DEP, EN
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) v += part[w][threadIdx.x];
         const int q = threadIdx.x;
-        const int off = q == 3 * NNUC ? LPM_LEDGER_PSTEPS : (q / 3) * 4 + 1 + q % 3;
-        if (v != 0.0) atomicAdd(slot + off, v);
+        if (v != 0.0) atomicAdd(slot + LG::offset(q), v);
     }
 }
 
@@ -568,11 +629,31 @@ struct GridConst {
     int s_release, step, nnuc, mode;
     float a0, dt, scale;
     float lam_l2e[4];
-    int nx, ny, nz, pad;
+    float bc[4][4];  // chain activity coefficients (identity: independent nuclides)
+    int nx, ny, nz, chain;
     double x0, y0, z0, inv_dx, inv_dy, inv_dz;
     long long cells;
     double* acc;
 };
+
+// Activities of the nuclides at age t, scaled by f.
+template <int NNUC>
+__device__ __forceinline__ void activities(const GridConst& g, float t, float f, float (&A)[NNUC])
+{
+    float E[NNUC];
+#pragma unroll
+    for (int n = 0; n < NNUC; ++n) E[n] = exp2f(-g.lam_l2e[n] * t);
+#pragma unroll
+    for (int n = 0; n < NNUC; ++n) {
+        float a = E[n];
+        if (g.chain) {
+            a = 0.0f;
+#pragma unroll
+            for (int j = 0; j <= n; ++j) a = fmaf(g.bc[n][j], E[j], a);
+        }
+        A[n] = f * a;
+    }
+}
 
 template <int NNUC>
 __global__ __launch_bounds__(kBlock) void conc_kernel(const GridConst g)
@@ -590,8 +671,7 @@ __global__ __launch_bounds__(kBlock) void conc_kernel(const GridConst g)
     if (m > 0.0f && b <= g.step) {
         const float age = (float)(g.step + 1 - (int)b) * g.dt;
         float A[NNUC];
-#pragma unroll
-        for (int n = 0; n < NNUC; ++n) A[n] = g.a0 * m * exp2f(-g.lam_l2e[n] * age) * g.scale;
+        activities<NNUC>(g, age, g.a0 * m * g.scale, A);
         // cell index and weights in double precision (see Dwell::add)
         const double fx = ((double)g.X[i] - g.x0) * g.inv_dx;
         const double fy = ((double)g.Y[i] - g.y0) * g.inv_dy;
@@ -656,8 +736,7 @@ __global__ __launch_bounds__(kBlock) void rec_conc_kernel(const GridConst g, con
     if (live) {
         const float age = (float)(step + 1 - (int)b) * g.dt;
         float A[NNUC];
-#pragma unroll
-        for (int n = 0; n < NNUC; ++n) A[n] = g.a0 * r.w * exp2f(-g.lam_l2e[n] * age) * g.scale;
+        activities<NNUC>(g, age, g.a0 * r.w * g.scale, A);
         const double fx = ((double)r.x - g.x0) * g.inv_dx;
         const double fy = ((double)r.y - g.y0) * g.inv_dy;
         const double fz = ((double)r.z - g.z0) * g.inv_dz;
@@ -783,7 +862,18 @@ int check_physics(const lpm_physics* ph)
     if (!(ph->dt > 0.0)) return fail(LPM_EINVAL, "dt must be positive");
     if (ph->Kh < 0.0 || ph->Kz_const < 0.0 || ph->kappa_ustar < 0.0)
         return fail(LPM_EINVAL, "diffusivities must be non-negative");
-    if (ph->kz_kind < 0 || ph->kz_kind > 2) return fail(LPM_EINVAL, "kz_kind must be 0, 1 or 2");
+    if (ph->kz_kind < 0 || ph->kz_kind > 3) return fail(LPM_EINVAL, "kz_kind must be 0..3");
+    if (ph->kz_kind == 3 && !isfinite(ph->inv_L)) return fail(LPM_EINVAL, "inv_L must be finite");
+    if (ph->chain != 0 && ph->chain != 1) return fail(LPM_EINVAL, "chain must be 0 or 1");
+    if (ph->dep_mode != 0 && ph->dep_mode != 1) return fail(LPM_EINVAL, "dep_mode must be 0 or 1");
+    if (ph->chain) {
+        for (int n = 0; n < ph->n_nuc; ++n) {
+            if (!(ph->lambda[n] > 0.0)) return fail(LPM_EINVAL, "a decay chain needs positive lambdas");
+            for (int j = 0; j < n; ++j)
+                if (ph->lambda[j] == ph->lambda[n])
+                    return fail(LPM_EINVAL, "a decay chain needs distinct lambdas");
+        }
+    }
     if (ph->kz_kind != 0 && !(ph->H_mix > 0.0)) return fail(LPM_EINVAL, "H_mix must be positive");
     for (int n = 0; n < ph->n_nuc; ++n)
         if (ph->lambda[n] < 0.0) return fail(LPM_EINVAL, "decay constants must be >= 0");
@@ -836,6 +926,47 @@ const char* lpm_last_error(void) { return g_msg; }
 
 const char* lpm_version(void) { return "lpm 0.1 gfx950"; }
 
+// Monin-Obukhov similarity (Businger-Dyer gradients, Paulson's integrated
+// profile corrections) solved for 1/L by fixed-point iteration from neutral.
+int lpm_surface_layer(double U, double z_ref, double z0, double dtheta, double T0,
+                      double* ustar, double* inv_L)
+{
+    g_msg[0] = 0;
+    if (!ustar || !inv_L) return fail(LPM_EINVAL, "null output");
+    if (!(U > 0.0 && z0 > 0.0 && z_ref > z0 && T0 > 0.0 && isfinite(dtheta)))
+        return fail(LPM_EINVAL, "need U > 0, z_ref > z0 > 0, T0 > 0");
+    const double kappa = 0.4, grav = 9.81, half_pi = 1.5707963267948966;
+    // profile corrections for momentum (m) and heat (h) at s = z/L
+    auto corr = [&](double s, double& pm, double& ph) {
+        if (s >= 0.0) {
+            pm = ph = -5.0 * s;
+            return;
+        }
+        const double x2 = sqrt(1.0 - 16.0 * s), x = sqrt(x2);
+        pm = 2.0 * log(0.5 * (1.0 + x)) + log(0.5 * (1.0 + x2)) - 2.0 * atan(x) + half_pi;
+        ph = 2.0 * log(0.5 * (1.0 + x2));
+    };
+    const double lz = log(z_ref / z0);
+    double il = 0.0;
+    for (int it = 0; it < 200; ++it) {
+        double pm1, ph1, pm0, ph0;
+        corr(z_ref * il, pm1, ph1);
+        corr(z0 * il, pm0, ph0);
+        const double fm = lz - pm1 + pm0, fh = lz - ph1 + ph0;
+        if (!(fm > 0.0 && fh > 0.0)) break;
+        const double us = kappa * U / fm, ts = kappa * dtheta / fh;
+        const double next = kappa * grav * ts / (us * us * T0);
+        if (!isfinite(next)) break;
+        if (next == il || fabs(next - il) <= 1e-12 * fabs(next)) {
+            *ustar = us;
+            *inv_L = next;
+            return LPM_OK;
+        }
+        il = next;
+    }
+    return fail(LPM_EINVAL, "no surface-layer solution (too stable?)");
+}
+
 int lpm_set_launch(int32_t refill_every, int32_t blocks_per_cu)
 {
     return lpm_set_launch_ex(refill_every, blocks_per_cu, g_refill_min);
@@ -885,15 +1016,26 @@ int lpm_release_particles(const lpm_state* st, const lpm_source* src, const lpm_
     const long long hi = first_local_born_at_or_after(sch, (long long)step0 + n_steps);
     if (hi <= lo) return LPM_OK;
     const double released = a0_of(src, sch, ph) * (double)(hi - lo);
+    // a decay chain releases its parent only
     hipLaunchKernelGGL(lpm::release_kernel, dim3(blocks_for(hi - lo)), dim3(lpm::kBlock), 0,
                        (hipStream_t)stream, st->x, st->y, st->z, st->m, lo, hi, (float)src->xs,
-                       (float)src->ys, (float)src->h, acc->ledger, ph->n_nuc, released);
+                       (float)src->ys, (float)src->h, acc->ledger, ph->chain ? 1 : ph->n_nuc,
+                       released);
     return hip_status("lpm_release_particles");
 }
 
 }  // extern "C"
 
 namespace lpm_host {
+
+void fill_chain(lpm::GridConst& g, const lpm_physics* ph)
+{
+    double bc[4][4];
+    activity_coefficients(ph, bc);
+    for (int n = 0; n < 4; ++n)
+        for (int j = 0; j < 4; ++j) g.bc[n][j] = (float)bc[n][j];
+    g.chain = ph->chain;
+}
 
 int fill_field(lpm::StepConst& p, const lpm_field* f)
 {
@@ -982,6 +1124,36 @@ void fill_physics(lpm::StepConst& p, const lpm_physics* ph)
         p.cdec[n] = (float)(-expm1(-lam * dt));
         p.edec[n] = (float)exp(-lam * dt);
     }
+    p.inv_L = ph->kz_kind == 3 ? (float)ph->inv_L : 0.0f;
+    p.chain = ph->chain;
+    p.dep_mode = ph->dep_mode;
+    p.n_nuc = ph->n_nuc;
+    double bc[4][4];
+    activity_coefficients(ph, bc);
+    for (int n = 0; n < 4; ++n)
+        for (int j = 0; j < 4; ++j) p.bc[n][j] = (float)bc[n][j];
+}
+
+// Activity of nuclide n per unit released activity = sum_j bc[n][j]
+// exp(-lambda_j t).  Independent nuclides: the identity.  A chain released as
+// pure parent: the daughter equation dA_n/dt = lambda_n (A_{n-1} - A_n) maps
+// each exponential of A_{n-1} to the same exponential times
+// lambda_n / (lambda_n - lambda_j), and A_n(0) = 0 fixes the coefficient of
+// exp(-lambda_n t).
+void activity_coefficients(const lpm_physics* ph, double bc[4][4])
+{
+    for (int n = 0; n < 4; ++n)
+        for (int j = 0; j < 4; ++j) bc[n][j] = (!ph->chain && n == j) ? 1.0 : 0.0;
+    if (!ph->chain) return;
+    bc[0][0] = 1.0;
+    for (int n = 1; n < ph->n_nuc; ++n) {
+        double sum = 0.0;
+        for (int j = 0; j < n; ++j) {
+            bc[n][j] = bc[n - 1][j] * ph->lambda[n] / (ph->lambda[n] - ph->lambda[j]);
+            sum += bc[n][j];
+        }
+        bc[n][n] = -sum;
+    }
 }
 
 void fill_depgrid(lpm::StepConst& p, const lpm_grid& dg)
@@ -1053,7 +1225,12 @@ void launch_step_kz(int kz, bool dep, unsigned nb, hipStream_t s, const lpm::Ste
     switch (kz) {
     case 0: launch_step_dep<NCOMP, TIME, LEV, NNUC, 0>(dep, nb, s, p); break;
     case 1: launch_step_dep<NCOMP, TIME, LEV, NNUC, 1>(dep, nb, s, p); break;
-    default: launch_step_dep<NCOMP, TIME, LEV, NNUC, 2>(dep, nb, s, p); break;
+    case 2: launch_step_dep<NCOMP, TIME, LEV, NNUC, 2>(dep, nb, s, p); break;
+    default: {  // general kernel (Eq. 3 stability, chains, stochastic deposition)
+        auto k = lpm::step_kernel<NCOMP, TIME, LEV, NNUC, 4, true, false>;
+        hipLaunchKernelGGL(k, dim3(resident_blocks(k, nb)), dim3(lpm::kBlock), 0, s, p);
+        break;
+    }
     }
 }
 
@@ -1133,7 +1310,8 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
     hipLaunchKernelGGL(lpm::fill_u32, dim3(1), dim3(lpm::kBlock), 0, s, acc->ctrl + LPM_CTRL_QUEUE, 2ll);
     const bool time = fld->nt > 1;
     const bool dep = p.dry_c1 > 0.0f || p.L0 > 0.0f;
-    const int kz = ph->kz_kind;
+    // the general kernel (K_z kind at run time) serves the paper-literal variants
+    const int kz = (ph->chain || ph->dep_mode || ph->kz_kind == 3) ? 4 : ph->kz_kind;
     const bool lev = fld->z_levels != nullptr;
     if (fld->ncomp == 2) {
         if (time) launch_step_lev<2, true>(lev, ph->n_nuc, kz, dep, nb, s, p);
@@ -1172,6 +1350,8 @@ int lpm_ensemble_prepare(const lpm_scenario* scen, int32_t n_scen, const lpm_sta
     int rc;
     if (!scen || !st || !out) return fail(LPM_EINVAL, "null argument");
     if ((rc = check_physics(ph))) return rc;
+    if (ph->chain || ph->dep_mode || ph->kz_kind == 3)
+        return fail(LPM_EINVAL, "ensemble launches do not take chains, stochastic deposition or kz_kind 3");
     if (n_scen < 1 || n_scen > LPM_MAX_SCENARIOS)
         return fail(LPM_EINVAL, "n_scen must be in [1, %d]", LPM_MAX_SCENARIOS);
     if (!table || ((uintptr_t)table & 15u) || table_bytes < (int64_t)n_scen * LPM_SCENARIO_BYTES)
@@ -1256,6 +1436,8 @@ int lpm_step_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_fi
     if ((rc = check_physics(ph)) || (rc = check_grid(dep_grid, true))) return rc;
     if (ph->n_nuc != ens->n_nuc) return fail(LPM_EINVAL, "physics and ensemble n_nuc differ");
     if (ph->n_nuc > 2) return fail(LPM_EINVAL, "ensemble launches support one or two nuclides");
+    if (ph->chain || ph->dep_mode || ph->kz_kind == 3)
+        return fail(LPM_EINVAL, "ensemble launches do not take chains, stochastic deposition or kz_kind 3");
     if ((double)dep_grid->nx * dep_grid->ny * ens->n_scen >= 2147483647.0)
         return fail(LPM_EINVAL, "scenarios x deposition cells must stay below 2^31 - 1");
     if (fld && fld->z_levels) return fail(LPM_EINVAL, "ensemble launches need uniform levels");
@@ -1383,6 +1565,7 @@ int lpm_grid_concentration(const lpm_state* st, const lpm_source* src, const lpm
     g.dt = (float)ph->dt;
     g.scale = 1.0f;
     for (int n = 0; n < ph->n_nuc; ++n) g.lam_l2e[n] = (float)(ph->lambda[n] * 1.4426950408889634);
+    fill_chain(g, ph);
     g.nx = grid->nx; g.ny = grid->ny; g.nz = grid->nz;
     g.x0 = grid->x0; g.y0 = grid->y0; g.z0 = grid->z0;
     g.inv_dx = 1.0 / grid->dx; g.inv_dy = 1.0 / grid->dy; g.inv_dz = 1.0 / grid->dz;
@@ -1437,6 +1620,7 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     g.dt = (float)ph->dt;
     g.scale = 1.0f;
     for (int n = 0; n < ph->n_nuc; ++n) g.lam_l2e[n] = (float)(ph->lambda[n] * 1.4426950408889634);
+    fill_chain(g, ph);
     g.nx = grid->nx; g.ny = grid->ny; g.nz = grid->nz;
     g.x0 = grid->x0; g.y0 = grid->y0; g.z0 = grid->z0;
     g.inv_dx = 1.0 / grid->dx; g.inv_dy = 1.0 / grid->dy; g.inv_dz = 1.0 / grid->dz;

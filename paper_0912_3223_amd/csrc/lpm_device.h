@@ -78,6 +78,10 @@ struct StepConst {
     // ensemble launches: scenario table (device) and its length
     const DevScen* scen;
     int n_scen;
+    // variants: Eq. 3 stability, decay chain, stochastic deposition
+    float inv_L;                          // 1/L (kz_kind 3)
+    int chain, dep_mode, n_nuc;
+    float bc[4][4];  // activity of nuclide n per unit a0: sum_j bc[n][j] exp(-lambda_j age)
     // deposition grid and accumulators
     double* dep;
     double* ledger;
@@ -93,10 +97,10 @@ struct StepConst {
 // stream, which removes one multiply from the first round.
 // ---------------------------------------------------------------------------
 template <bool UNIFORM_KEY>
-__device__ __forceinline__ void philox_10(uint32_t c0, uint32_t c1, uint32_t k0,
+__device__ __forceinline__ void philox_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t k0,
                                           uint32_t k1, uint32_t r[4])
 {
-    uint32_t c2 = 0u, c3 = 0u;
+    uint32_t c3 = 0u;
     if constexpr (UNIFORM_KEY) {  // one key for the whole launch: keep it scalar
         k0 = __builtin_amdgcn_readfirstlane(k0);
         k1 = __builtin_amdgcn_readfirstlane(k1);
@@ -148,7 +152,7 @@ __device__ __forceinline__ void normals3(uint32_t id, uint32_t step, uint32_t k0
                                          float& xi2)
 {
     uint32_t r[4];
-    philox_10<UNIFORM_KEY>(id, step, k0, k1, r);
+    philox_10<UNIFORM_KEY>(id, step, 0u, k0, k1, r);
     const float m2ln2 = -1.3862943611198906f;  // -2 ln 2
     const float u0 = lattice_uniform(r[0]);
     const float u1 = lattice_uniform(r[1]);
@@ -174,6 +178,17 @@ template <class T>
 __device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p)
 {
     return (__attribute__((address_space(1))) T*)p;
+}
+
+// First uniform of the stochastic-deposition stream: Philox counter
+// (id, step, 1, 0).
+template <bool UNIFORM_KEY>
+__device__ __forceinline__ float removal_uniform(uint32_t id, uint32_t step, uint32_t k0,
+                                                 uint32_t k1)
+{
+    uint32_t r[4];
+    philox_10<UNIFORM_KEY>(id, step, 1u, k0, k1, r);
+    return lattice_uniform(r[0]);
 }
 
 __device__ __forceinline__ float clampf(float v, float lo, float hi)
@@ -318,9 +333,46 @@ __device__ __forceinline__ void wind_interp(const WindTap<NCOMP, TIME>& w, float
 // Vertical diffusivity and its slope (Eq. 3 with Phi = 1, or constant);
 // KZ is the profile kind (0 constant, 1 parabolic, 2 Eq. 3 exponent).
 template <int KZ>
+__device__ __forceinline__ void kz_profile(const StepConst& p, float z, float& K, float& dK);
+
+// Eq. (3) with the Businger-Dyer similarity function for heat of
+// s = (z + z0)/L: Phi = 1 + 5 s (stable), (1 - 16 s)^(-1/2) (unstable).
+__device__ __forceinline__ void kz_stability(const StepConst& p, float z, float& K, float& dK)
+{
+    const float zc = fmaxf(z, 0.0f);
+    const float g = fmaf(-zc, p.inv_Hmix, 1.0f);
+    const float zz = zc + p.z0;
+    const bool inside = zc < p.H_mix;
+    const float f = p.ku * zz * g * g;                        // Phi = 1 profile
+    const float df = p.ku * g * fmaf(-2.0f * zz, p.inv_Hmix, g);
+    float rphi, drphi;  // 1/Phi and its slope in z
+    if (p.inv_L >= 0.0f) {
+        const float q = __builtin_amdgcn_rcpf(fmaf(5.0f * zz, p.inv_L, 1.0f));
+        rphi = q;
+        drphi = -5.0f * p.inv_L * q * q;
+    } else {
+        const float w = fmaf(-16.0f * zz, p.inv_L, 1.0f);
+        const float sw = __builtin_amdgcn_sqrtf(w);
+        rphi = sw;
+        drphi = -8.0f * p.inv_L * __builtin_amdgcn_rcpf(sw);
+    }
+    K = inside ? f * rphi : 0.0f;
+    dK = inside ? fmaf(df, rphi, f * drphi) : 0.0f;
+}
+
+template <int KZ>
 __device__ __forceinline__ void kz_profile(const StepConst& p, float z, float& K, float& dK)
 {
-    if constexpr (KZ == 0) {
+    if constexpr (KZ == 4) {  // kind chosen at run time (general kernels)
+        switch (p.kz_kind) {
+        case 0: kz_profile<0>(p, z, K, dK); break;
+        case 1: kz_profile<1>(p, z, K, dK); break;
+        case 2: kz_profile<2>(p, z, K, dK); break;
+        default: kz_stability(p, z, K, dK); break;
+        }
+    } else if constexpr (KZ == 3) {
+        kz_stability(p, z, K, dK);
+    } else if constexpr (KZ == 0) {
         K = p.Kz_const;
         dK = 0.0f;
     } else {

@@ -25,5 +25,6 @@ int fill_field(lpm::StepConst& p, const lpm_field* f);
 void fill_source(lpm::StepConst& p, const lpm_source* src, const lpm_schedule* sch,
                  const lpm_physics* ph);
 void fill_physics(lpm::StepConst& p, const lpm_physics* ph);
+void activity_coefficients(const lpm_physics* ph, double bc[4][4]);
 
 }  // namespace lpm_host

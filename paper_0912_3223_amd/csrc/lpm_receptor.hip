@@ -42,6 +42,7 @@ struct RecConst {
     int s_release, nnuc, n_rcp, rec_step0, rec_every, pad;
     float a0, dt, weight;
     float lam_l2e[4];
+    float bsum[4];  // sum over nuclides of the chain activity coefficients
     KernelConst kc;
     const float* rx;
     const float* ry;
@@ -76,7 +77,8 @@ __global__ __launch_bounds__(kBlock) void receptor_kernel(const RecConst g, cons
             if (r.w > 0.0f) {
                 const float age = (float)(step + 1 - (int)b) * g.dt;
                 float F = 0.0f;
-                for (int n = 0; n < g.nnuc; ++n) F += __builtin_amdgcn_exp2f(-g.lam_l2e[n] * age);
+                for (int n = 0; n < g.nnuc; ++n)
+                    F = fmaf(g.bsum[n], __builtin_amdgcn_exp2f(-g.lam_l2e[n] * age), F);
                 e = make_float4(r.x, r.y, r.z, g.a0 * r.w * F);
             }
         }
@@ -120,6 +122,7 @@ struct AdjConst {
     float* tapem;   // [rec_every + 1][T]: m
     float phi_c1, phi_c2;  // dry-deposition shape 2/h_s (1 - z/h_s) = c1 - c2 z
     float inv_q, weight;
+    float bsum[4];  // sum over nuclides of the chain activity coefficients
     KernelConst kc;
     const float* rx;
     const float* ry;
@@ -349,7 +352,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(const StepConst pk, con
             // output of the segment's last step (state after s_hi)
             const float age = (float)(s_hi + 1 - b) * p.dt;
             float F = 0.0f;
-            for (int n = 0; n < a.nnuc; ++n) F += __builtin_amdgcn_exp2f(-p.lam_l2e[n] * age);
+            for (int n = 0; n < a.nnuc; ++n)
+                F = fmaf(a.bsum[n], __builtin_amdgcn_exp2f(-p.lam_l2e[n] * age), F);
             const float aF = p.a0 * F, A = aF * m;
             for (int r = 0; r < a.n_rcp; ++r) {
                 const float4 q = rcp[r];
@@ -442,6 +446,19 @@ lpm::KernelConst kernel_const(const lpm_receptors* r)
     k.ch = (float)(1.0 / (2.0 * pi * sh * sh));
     k.cz = (float)(1.0 / (sqrt(2.0 * pi) * sz));
     return k;
+}
+
+// Total activity per unit a0 = sum_j bsum[j] exp(-lambda_j t): the column
+// sums of the chain coefficients (ones for independent nuclides).
+void coefficient_sums(const lpm_physics* ph, float bsum[4])
+{
+    double bc[4][4];
+    activity_coefficients(ph, bc);
+    for (int j = 0; j < 4; ++j) {
+        double s = 0.0;
+        for (int n = 0; n < ph->n_nuc; ++n) s += bc[n][j];
+        bsum[j] = (float)s;
+    }
 }
 
 int check_schedule(const lpm_schedule* sch)
@@ -546,6 +563,7 @@ int lpm_receptor_concentration(const float* rec, int64_t rec_stride, int32_t rec
     for (int n = 0; n < ph->n_nuc; ++n) g.lam_l2e[n] = (float)(ph->lambda[n] * 1.4426950408889634);
     g.kc = kernel_const(rcp);
     g.rx = rcp->x; g.ry = rcp->y; g.rz = rcp->z;
+    coefficient_sums(ph, g.bsum);
     if (n_rec > 0)
         g.i_hi = first_local_born_at_or_after(sch, (long long)rec_step0 + (long long)(n_rec - 1) * rec_every + 1);
     if (g.i_hi > 0) {
@@ -587,6 +605,8 @@ int lpm_receptor_adjoint(const float* rec, int64_t rec_stride, int32_t rec_every
     if (!rec || ((uintptr_t)rec & 15u)) return fail(LPM_EINVAL, "null or misaligned record buffer");
     if (rec_stride < sch->n_local) return fail(LPM_EINVAL, "rec_stride below n_local");
     if (src->q == 0.0) return fail(LPM_EINVAL, "release rate q must be non-zero");
+    if (ph->kz_kind == 3 || ph->dep_mode != 0)
+        return fail(LPM_EINVAL, "the adjoint covers kz_kind 0..2 and mass-depletion deposition");
     lpm::StepConst p;
     memset(&p, 0, sizeof p);
     if ((rc = fill_field(p, fld))) return rc;
@@ -620,6 +640,7 @@ int lpm_receptor_adjoint(const float* rec, int64_t rec_stride, int32_t rec_every
     a.weight = rcp->weight;
     a.kc = kernel_const(rcp);
     a.rx = rcp->x; a.ry = rcp->y; a.rz = rcp->z;
+    coefficient_sums(ph, a.bsum);
     a.gbar = gbar;
     a.grad = grad_out;
 

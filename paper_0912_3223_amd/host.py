@@ -32,7 +32,7 @@ def make_physics(ph) -> Physics:
     r = ph.rain
     return Physics(ph.dt, ph.Kh, ph.Kz_const, ph.kappa_ustar, ph.z0, ph.H_mix, ph.H_lid, ph.h_s,
                    ph.kz_kind, ph.n_nuc, lam, ph.Lambda0, r.cx, r.cy, r.a, r.b, r.angle,
-                   r.edge, ph.seed)
+                   r.edge, ph.seed, ph.inv_L, ph.chain, ph.dep_mode)
 
 
 def make_grid(g) -> Grid:
