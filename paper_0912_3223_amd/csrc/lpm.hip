@@ -140,7 +140,10 @@ struct WaveTable {
 #pragma unroll
             for (int n = 0; n < NNUC; ++n) val[n * kSlots + t] = 0.0;
         }
-        if (lane == 0) *used = 0;
+        if (lane == 0) {
+            *used = 0;
+            *sn = 0;
+        }
     }
 
     __device__ void add(int cell, const float (&v)[NNUC], double* grid, long long plane)
@@ -186,10 +189,76 @@ struct WaveTable {
         const int u = __hip_atomic_load(used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         if (__builtin_amdgcn_readfirstlane(u) > kSlots / 2) flush(lane, grid, plane);
     }
+
+    // Staging list in front of the table.  A particle that moves to another
+    // cell quad hands over its quad (origin and the four corner sums) in
+    // whatever lanes happen to do so in that step, a few of the wave's 64:
+    // hashing its corners there would run the probe loops with most lanes
+    // masked off.  Instead the quad is appended to a per-wave list (one
+    // ballot and a prefix count for all of them), and the whole wave expands
+    // the quads into corners and inserts them when the list fills up.
+    static constexpr int kStage = 128;                // quads
+    static constexpr int kDrainAt = kStage - 64;      // room for every lane
+    int* sq;       // [3][kStage]: i0, j0, key base of each quad
+    float* sval;   // [4 NNUC][kStage]: corner sums, corner-major per nuclide
+    int* sn;       // quads staged
+
+    // Called by the active lanes together; lanes with has = false only take
+    // part in the count.  Returns false (nothing staged) when the list is
+    // full, and the caller inserts directly.
+    __device__ bool stage(bool has, int i0, int j0, int kb, const float (&acc)[NNUC][4])
+    {
+        const unsigned long long m = __ballot(has);
+        if (m == 0ull) return true;
+        const int lane = __lane_id();
+        const int cnt = __popcll(m);
+        const int base = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(sn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT));
+        if (base + cnt > kStage) return false;  // never: see the drain points
+        if (has) {
+            const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+            sq[pos] = i0;
+            sq[kStage + pos] = j0;
+            sq[2 * kStage + pos] = kb;
+#pragma unroll
+            for (int n = 0; n < NNUC; ++n)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sval[(4 * n + c) * kStage + pos] = acc[n][c];
+        }
+        if (lane == __ffsll((long long)m) - 1)
+            __hip_atomic_store(sn, base + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        return true;
+    }
+
+    // Called by all lanes of the wave at the same point: inserts the staged
+    // quads' corners (ncorner = 1 for nearest-cell deposition) when at least
+    // at_least quads are staged.
+    __device__ void drain(int lane, double* grid, long long plane, int at_least, int ncorner,
+                          int dnx, int dny)
+    {
+        const int n = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(sn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT));
+        if (n < at_least || n == 0) return;
+        __builtin_amdgcn_wave_barrier();
+        // lane -> (quad, corner): 64 / ncorner quads per pass
+        const int per = 64 / ncorner;
+        const int c = lane % ncorner;
+        for (int e = lane / ncorner; e < n; e += per) {
+            const int ii = sq[e] + (c & 1), jj = sq[kStage + e] + (c >> 1);
+            if (ii < 0 || jj < 0 || ii >= dnx || jj >= dny) continue;
+            float v[NNUC];
+#pragma unroll
+            for (int q = 0; q < NNUC; ++q) v[q] = sval[(4 * q + c) * kStage + e];
+            add(sq[2 * kStage + e] + jj * dnx + ii, v, grid, plane);
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) __hip_atomic_store(sn, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __builtin_amdgcn_wave_barrier();
+    }
 };
 
 template <int NNUC>
-using DepTable = WaveTable<NNUC, 8>;
+using DepTable = WaveTable<NNUC, 7>;
 
 // Per-thread deposition while the particle stays in one grid cell (nearest
 // cell) or above one cell quad (cloud-in-cell): partial sums of the corner
@@ -204,19 +273,12 @@ struct Dwell {
 
     __device__ void flush(const StepConst& p, DepTable<NNUC>& tab, long long plane)
     {
-        if (i0 == INT_MIN) return;
-        const int ncorner = p.dmode == 0 ? 1 : 4;
-        for (int c = 0; c < ncorner; ++c) {
-            const int ii = i0 + (c & 1), jj = j0 + (c >> 1);
-            if (ii < 0 || jj < 0 || ii >= p.dnx || jj >= p.dny) continue;
-            // corner values by selects: a dynamic index into acc would put
-            // the array in scratch memory
-            float v[NNUC];
-#pragma unroll
-            for (int n = 0; n < NNUC; ++n)
-                v[n] = c == 0 ? acc[n][0] : c == 1 ? acc[n][1] : c == 2 ? acc[n][2] : acc[n][3];
-            tab.add(key_base + jj * p.dnx + ii, v, p.dep, plane);
-        }
+        // A lane stages at most one quad between two drain points of its wave
+        // (the kernel drains whenever 64 free entries are not left), so the
+        // list cannot overflow; if it ever did, the error word says so.
+        const bool any = i0 != INT_MIN;
+        if (!tab.stage(any, i0, j0, key_base, acc) && any)
+            atomicOr(p.ctrl + LPM_CTRL_ERR, 2u);
         i0 = INT_MIN;
     }
 
@@ -431,8 +493,12 @@ __global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP
     __shared__ int tab_key[kWaves][DepTable<NNUC>::kSlots];
     __shared__ double tab_val[kWaves][NNUC * DepTable<NNUC>::kSlots];
     __shared__ int tab_used[kWaves];
+    __shared__ int stage_key[kWaves][DEP ? 3 * DepTable<NNUC>::kStage : 1];
+    __shared__ float stage_val[kWaves][DEP ? 4 * NNUC * DepTable<NNUC>::kStage : 1];
+    __shared__ int stage_n[kWaves];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    DepTable<NNUC> tab{tab_key[wv], tab_val[wv], &tab_used[wv]};
+    DepTable<NNUC> tab{tab_key[wv], tab_val[wv], &tab_used[wv], stage_key[wv], stage_val[wv],
+                       &stage_n[wv]};
     const long long plane = (long long)p.dnx * p.dny;
     if constexpr (DEP) tab.init(lane);
     __builtin_amdgcn_wave_barrier();
@@ -489,6 +555,10 @@ __global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP
                             led_scen = lo;
                         }
                         sv = SrcVals{ds.a0, ds.wscale, ds.dry_c1, ds.dry_c2, ds.key1, lo};
+                        // the lane's dwell outlives its particle; its sums go
+                        // to the scenario they were made in
+                        if constexpr (DEP)
+                            if ((int)(lo * plane) != dw.key_base) dw.flush(p, tab, plane);
                         dw.key_base = (int)(lo * plane);
                         g = q - ds.qbase;                  // local id of the scenario
                         b = (int)birth(g, ds.s_release, ds.n_total);
@@ -515,6 +585,10 @@ __global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP
                 }
             }
         }
+        // refills may have staged a quad per lane (ensembles: scenario change)
+        if constexpr (DEP && ENS)
+            tab.drain(lane, p.dep, plane, DepTable<NNUC>::kDrainAt, p.dmode == 0 ? 1 : 4, p.dnx,
+                      p.dny);
         if (!__any(have)) break;
         for (int j = 0; j < p.refill_every; ++j) {
             if (have) {
@@ -529,7 +603,8 @@ __global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP
                 }
                 ++s;
                 if (st != 0 || s >= p.step_end) {
-                    if constexpr (DEP) dw.flush(p, tab, plane);
+                    // (the lane's dwell stays: deposits are keyed by cell, and
+                    // the lane's next particle or the kernel's end flushes it)
                     as_global(p.X)[i] = x;
                     as_global(p.Y)[i] = y;
                     as_global(p.Z)[i] = z;
@@ -539,10 +614,17 @@ __global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP
                     have = false;
                 }
             }
+            if constexpr (DEP)
+                tab.drain(lane, p.dep, plane, DepTable<NNUC>::kDrainAt, p.dmode == 0 ? 1 : 4,
+                          p.dnx, p.dny);
         }
         if constexpr (DEP) tab.flush_if_half_full(lane, p.dep, plane);
     }
-    if constexpr (DEP) tab.flush(lane, p.dep, plane);
+    if constexpr (DEP) {
+        dw.flush(p, tab, plane);  // every lane: its last particle's sums
+        tab.drain(lane, p.dep, plane, 1, p.dmode == 0 ? 1 : 4, p.dnx, p.dny);
+        tab.flush(lane, p.dep, plane);
+    }
 
     // ledger slot: [nuclide][released, deposited, decayed, exited], steps
     constexpr int NV = LG::kSize;
@@ -662,13 +744,15 @@ __global__ __launch_bounds__(kBlock) void conc_kernel(const GridConst g)
     __shared__ int tab_key[Table::kSlots];
     __shared__ double tab_val[NNUC * Table::kSlots];
     Table tab{tab_key, tab_val};
-    tab.init();
-    __syncthreads();
     const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
     const float m = i < g.i_hi ? g.M[i] : 0.0f;
     long long b = 0;
     if (m > 0.0f) b = birth(g.id_base + i * g.id_stride, g.s_release, g.n_total);
-    if (m > 0.0f && b <= g.step) {
+    const bool live = m > 0.0f && b <= g.step;
+    if (!__syncthreads_or(live)) return;  // no airborne particle in this block
+    tab.init();
+    __syncthreads();
+    if (live) {
         const float age = (float)(g.step + 1 - (int)b) * g.dt;
         float A[NNUC];
         activities<NNUC>(g, age, g.a0 * m * g.scale, A);
@@ -717,8 +801,6 @@ __global__ __launch_bounds__(kBlock) void rec_conc_kernel(const GridConst g, con
     __shared__ int tab_key[Table::kSlots];
     __shared__ double tab_val[NNUC * Table::kSlots];
     Table tab{tab_key, tab_val};
-    tab.init();
-    __syncthreads();
     const int k = blockIdx.y;
     const int step = rec_step0 + k * rec_every;
     double* acc = g.acc + (long long)k * NNUC * g.cells;
@@ -733,6 +815,11 @@ __global__ __launch_bounds__(kBlock) void rec_conc_kernel(const GridConst g, con
             live = r.w > 0.0f;
         }
     }
+    // most (block, output step) pairs hold no airborne particle: the block's
+    // ids are born later or gone; skip the table for them
+    if (!__syncthreads_or(live)) return;
+    tab.init();
+    __syncthreads();
     if (live) {
         const float age = (float)(step + 1 - (int)b) * g.dt;
         float A[NNUC];
@@ -1695,6 +1782,7 @@ int lpm_check(const lpm_accum* acc, lpm_stream stream)
         hipStreamSynchronize(s) != hipSuccess)
         return hip_status("lpm_check");
     if (e & 1u) return fail(LPM_ENONFINITE, "a particle coordinate or mass became non-finite");
+    if (e & 2u) return fail(LPM_EHIP, "internal error: deposition staging list overflowed");
     return LPM_OK;
 }
 
