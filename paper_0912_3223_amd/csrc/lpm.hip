@@ -791,7 +791,11 @@ __global__ __launch_bounds__(kBlock) void conc_kernel(const GridConst g)
 
 // Concentration of recorded states: blockIdx.y selects the record (output
 // step s_k); a record counts if the particle was born by s_k and still
-// active after it.
+// active after it.  A block grids kRecChunk consecutive particle ids: released
+// close together they share cells, so the block's LDS table folds more of
+// their contributions before the FP64 global atomics.
+constexpr int kRecChunk = 8 * kBlock;
+
 template <int NNUC>
 __global__ __launch_bounds__(kBlock) void rec_conc_kernel(const GridConst g, const float4* rec,
                                                           const int* last, long long rec_stride,
@@ -804,23 +808,31 @@ __global__ __launch_bounds__(kBlock) void rec_conc_kernel(const GridConst g, con
     const int k = blockIdx.y;
     const int step = rec_step0 + k * rec_every;
     double* acc = g.acc + (long long)k * NNUC * g.cells;
-    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-    bool live = false;
-    long long b = 0;
-    float4 r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (i < g.i_hi) {
+    const long long i0 = (long long)blockIdx.x * kRecChunk;
+    // particle (i0 + u kBlock + threadIdx.x) is gridded if born by the output
+    // step and still airborne after it
+    auto live_at = [&](long long i, long long& b) {
+        if (i >= g.i_hi) return false;
         b = birth(g.id_base + i * g.id_stride, g.s_release, g.n_total);
-        if (b <= step && step < last[i]) {
-            r = rec[(long long)k * rec_stride + i];
-            live = r.w > 0.0f;
-        }
+        return b <= step && step < last[i];
+    };
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < kRecChunk / kBlock; ++u) {
+        long long b;
+        any |= live_at(i0 + u * kBlock + threadIdx.x, b);
     }
-    // most (block, output step) pairs hold no airborne particle: the block's
+    // most (chunk, output step) pairs hold no airborne particle: the chunk's
     // ids are born later or gone; skip the table for them
-    if (!__syncthreads_or(live)) return;
+    if (!__syncthreads_or(any)) return;
     tab.init();
     __syncthreads();
-    if (live) {
+    for (int u = 0; u < kRecChunk / kBlock; ++u) {
+        const long long i = i0 + u * kBlock + threadIdx.x;
+        long long b = 0;
+        if (!live_at(i, b)) continue;
+        const float4 r = rec[(long long)k * rec_stride + i];
+        if (!(r.w > 0.0f)) continue;
         const float age = (float)(step + 1 - (int)b) * g.dt;
         float A[NNUC];
         activities<NNUC>(g, age, g.a0 * r.w * g.scale, A);
@@ -1723,7 +1735,8 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     if (g.i_hi > 0) {
         const float4* r4 = reinterpret_cast<const float4*>(rec);
         const int* last = reinterpret_cast<const int*>(rec + 4ll * n_rec * rec_stride);
-        const dim3 nb(blocks_for(g.i_hi), (unsigned)n_rec), bs(lpm::kBlock);
+        const dim3 nb((unsigned)((g.i_hi + lpm::kRecChunk - 1) / lpm::kRecChunk), (unsigned)n_rec),
+            bs(lpm::kBlock);
         switch (ph->n_nuc) {
         case 1: hipLaunchKernelGGL(lpm::rec_conc_kernel<1>, nb, bs, 0, s, g, r4, last, rec_stride, rec_step0, rec_every); break;
         case 2: hipLaunchKernelGGL(lpm::rec_conc_kernel<2>, nb, bs, 0, s, g, r4, last, rec_stride, rec_step0, rec_every); break;
