@@ -233,12 +233,12 @@ struct WaveTable {
     // Called by all lanes of the wave at the same point: inserts the staged
     // quads' corners (ncorner = 1 for nearest-cell deposition) when at least
     // at_least quads are staged.
-    __device__ void drain(int lane, double* grid, long long plane, int at_least, int ncorner,
+    __device__ bool drain(int lane, double* grid, long long plane, int at_least, int ncorner,
                           int dnx, int dny)
     {
         const int n = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(sn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT));
-        if (n < at_least || n == 0) return;
+        if (n < at_least || n == 0) return false;
         __builtin_amdgcn_wave_barrier();
         // lane -> (quad, corner): 64 / ncorner quads per pass
         const int per = 64 / ncorner;
@@ -254,6 +254,7 @@ struct WaveTable {
         __builtin_amdgcn_wave_barrier();
         if (lane == 0) __hip_atomic_store(sn, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         __builtin_amdgcn_wave_barrier();
+        return true;
     }
 };
 
@@ -466,12 +467,14 @@ __device__ __forceinline__ void lane_ledger(double (&led)[(Ledger<NNUC, KZ>::kSi
 // deposition and ledger go to that scenario's accumulators.
 // ---------------------------------------------------------------------------
 // Blocks per CU the compiler must fit: the lighter variants are held to 128
-// VGPRs (4 waves per SIMD; 15 % faster on the 1e6-particle run than the 3
-// waves the register allocation picks by itself); heavier ones would spill.
+// VGPRs (4 waves per SIMD), which beats the 3 waves the register allocation
+// picks by itself even where it spills a few registers (1e6-particle run:
+// 7.3 vs 7.8 ms; 64-scenario ensemble: 94 vs 103 ms); heavier variants keep
+// the default.
 template <int NCOMP, bool TIME, int NNUC, int KZ, bool DEP, bool ENS>
 constexpr int step_min_blocks()
 {
-    return (NCOMP == 3) + TIME + DEP + (NNUC >= 3) + ENS + (KZ == 4) <= 1 ? 4 : 1;
+    return (NCOMP == 3) + TIME + DEP + (NNUC >= 3) + (KZ == 4) <= 1 ? 4 : 1;
 }
 
 template <int NCOMP, bool TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS>
@@ -586,9 +589,11 @@ __global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP
             }
         }
         // refills may have staged a quad per lane (ensembles: scenario change)
-        if constexpr (DEP && ENS)
-            tab.drain(lane, p.dep, plane, DepTable<NNUC>::kDrainAt, p.dmode == 0 ? 1 : 4, p.dnx,
-                      p.dny);
+        if constexpr (DEP && ENS) {
+            if (tab.drain(lane, p.dep, plane, DepTable<NNUC>::kDrainAt, p.dmode == 0 ? 1 : 4,
+                          p.dnx, p.dny))
+                tab.flush_if_half_full(lane, p.dep, plane);
+        }
         if (!__any(have)) break;
         for (int j = 0; j < p.refill_every; ++j) {
             if (have) {
@@ -614,11 +619,13 @@ __global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP
                     have = false;
                 }
             }
-            if constexpr (DEP)
-                tab.drain(lane, p.dep, plane, DepTable<NNUC>::kDrainAt, p.dmode == 0 ? 1 : 4,
-                          p.dnx, p.dny);
+            if constexpr (DEP) {
+                // a drain fills the table: move it out before it overflows
+                if (tab.drain(lane, p.dep, plane, DepTable<NNUC>::kDrainAt,
+                              p.dmode == 0 ? 1 : 4, p.dnx, p.dny))
+                    tab.flush_if_half_full(lane, p.dep, plane);
+            }
         }
-        if constexpr (DEP) tab.flush_if_half_full(lane, p.dep, plane);
     }
     if constexpr (DEP) {
         dw.flush(p, tab, plane);  // every lane: its last particle's sums
