@@ -238,7 +238,7 @@ def main():
     ev = []
 
     rec = run.record_buffer(len(snaps)) if a.spl == 0 else None
-    gbufs = run.grid_buffers(len(snaps)) if a.spl == 0 else None
+    gbufs = run.grid_buffers(snaps[0], case.out_every, len(snaps)) if a.spl == 0 else None
 
     def one_run(timed):
         run.reset()

@@ -251,16 +251,30 @@ int lpm_grid_concentration(const lpm_state* st, const lpm_source* src,
                            const lpm_grid* grid, int32_t step,
                            double* acc_scratch, float* out, lpm_stream stream);
 
+/* Bytes of device workspace lpm_grid_records needs for these arguments:
+ * per (output step, bin of grid columns) two 64-bit offsets, and one 32-bit
+ * particle index per particle born by each recorded step (at most
+ * 4 n_rec n_local bytes).  0 when n_rec == 0.  Errors: the argument checks
+ * of lpm_grid_records that do not involve buffers; LPM_EINVAL also when
+ * n_nuc * nz > 6144 (a full grid column of FP64 sums must fit one block's
+ * LDS) or n_local >= 2^32. */
+int lpm_grid_records_workspace(const lpm_schedule* sch, const lpm_physics* ph,
+                               const lpm_grid* grid, int32_t rec_step0,
+                               int32_t rec_every, int32_t n_rec, int64_t* bytes);
+
 /* Concentration at every recorded step of rec (lpm_step_particles_record
  * with the same schedule, source, physics, rec_step0, rec_every, n_rec and
- * rec_stride): out[k] = the grid of lpm_grid_concentration after step s_k.
- * acc_scratch: device double [n_rec][n_nuc][nz][ny][nx], overwritten;
- * out: device float [n_rec][n_nuc][nz][ny][nx], overwritten. */
+ * rec_stride): out[k] = the grid of lpm_grid_concentration after step s_k
+ * (Sec. 3.2: activities summed on a rectangular grid every n-th step), the
+ * same FP32 contributions summed in FP64.  work: caller-owned device
+ * scratch, 256-byte aligned, of at least lpm_grid_records_workspace bytes,
+ * overwritten; out: device float [n_rec][n_nuc][nz][ny][nx], overwritten
+ * (every cell).  Asynchronous on `stream`; no allocation. */
 int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0,
                      int32_t rec_every, int32_t n_rec, const lpm_source* src,
                      const lpm_schedule* sch, const lpm_physics* ph,
-                     const lpm_grid* grid, double* acc_scratch, float* out,
-                     lpm_stream stream);
+                     const lpm_grid* grid, void* work, int64_t work_bytes,
+                     float* out, lpm_stream stream);
 
 /* Deposited activity so far on the deposition grid, converted to float and
  * divided by the cell area when dep_grid.density != 0.

@@ -118,8 +118,10 @@ def _load():
                                       C.c_int32, C.c_void_p, C.c_int64, C.c_void_p],
         "lpm_grid_concentration": [P(State), P(Source), P(Schedule), P(Physics), P(Grid),
                                    C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
+        "lpm_grid_records_workspace": [P(Schedule), P(Physics), P(Grid), C.c_int32, C.c_int32,
+                                       C.c_int32, P(C.c_int64)],
         "lpm_grid_records": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, P(Source),
-                             P(Schedule), P(Physics), P(Grid), C.c_void_p, C.c_void_p,
+                             P(Schedule), P(Physics), P(Grid), C.c_void_p, C.c_int64, C.c_void_p,
                              C.c_void_p],
         "lpm_grid_deposition": [P(Accum), C.c_void_p, C.c_void_p],
         "lpm_read_ledger": [P(Accum), P(C.c_double), C.c_void_p],
@@ -157,7 +159,8 @@ _lib = _load()
 #: C entry points exported by include/lpm.h (checked by the test suite).
 EXPORTS = ("lpm_accum_reset", "lpm_release_particles", "lpm_step_particles",
            "lpm_step_particles_record",
-           "lpm_grid_concentration", "lpm_grid_records", "lpm_grid_deposition",
+           "lpm_grid_concentration", "lpm_grid_records_workspace", "lpm_grid_records",
+           "lpm_grid_deposition",
            "lpm_read_ledger", "lpm_check", "lpm_set_launch", "lpm_set_launch_ex", "lpm_ensemble_prepare",
            "lpm_release_ensemble", "lpm_step_ensemble", "lpm_autotune_ensemble",
            "lpm_receptor_concentration", "lpm_adjoint_workspace", "lpm_receptor_adjoint",
@@ -217,14 +220,22 @@ def grid_concentration(st: State, src: Source, sch: Schedule, ph: Physics, grid:
                                     C.c_void_p(out.data_ptr()), _stream(stream)))
 
 
+def grid_records_workspace(sch: Schedule, ph: Physics, grid: Grid, rec_step0: int,
+                           rec_every: int, n_rec: int) -> int:
+    n = C.c_int64(0)
+    _rc(_lib.lpm_grid_records_workspace(C.byref(sch), C.byref(ph), C.byref(grid), rec_step0,
+                                        rec_every, n_rec, C.byref(n)))
+    return n.value
+
+
 def grid_records(rec: torch.Tensor, rec_stride: int, rec_step0: int, rec_every: int, n_rec: int,
-                 src: Source, sch: Schedule, ph: Physics, grid: Grid, acc_scratch: torch.Tensor,
+                 src: Source, sch: Schedule, ph: Physics, grid: Grid, work: torch.Tensor,
                  out: torch.Tensor, stream=None):
-    assert rec.dtype == torch.float32 and acc_scratch.dtype == torch.float64
-    assert out.dtype == torch.float32
+    assert rec.dtype == torch.float32 and out.dtype == torch.float32
+    nbytes = work.numel() * work.element_size()
     _rc(_lib.lpm_grid_records(C.c_void_p(rec.data_ptr()), rec_stride, rec_step0, rec_every, n_rec,
                               C.byref(src), C.byref(sch), C.byref(ph), C.byref(grid),
-                              C.c_void_p(acc_scratch.data_ptr()), C.c_void_p(out.data_ptr()),
+                              C.c_void_p(work.data_ptr()), nbytes, C.c_void_p(out.data_ptr()),
                               _stream(stream)))
 
 

@@ -796,50 +796,301 @@ __global__ __launch_bounds__(kBlock) void conc_kernel(const GridConst g)
     tab.flush(g.acc, g.cells);
 }
 
-// Concentration of recorded states: blockIdx.y selects the record (output
-// step s_k); a record counts if the particle was born by s_k and still
-// active after it.  A block grids kRecChunk consecutive particle ids: released
-// close together they share cells, so the block's LDS table folds more of
-// their contributions before the FP64 global atomics.
+// Concentration of recorded states (output steps s_k = rec_step0 + k
+// rec_every), owner-computes.  Particles released far apart in time spread
+// over thousands of cells, so a per-block hash of cells cannot fold their
+// contributions; instead the records are binned by the horizontal tile of the
+// grid they touch, and one block per (tile, output step) sums every
+// contribution to its own cells in a dense FP64 LDS array and writes each
+// cell once, as float.  No global floating-point atomics, no FP64 grid in HBM.
+//
+// Bins.  Tiles are TX x TY columns of full height.  A record's CIC base corner
+// (ix, iy) = floor(f - 1/2) touches columns ix, ix + 1 (and iy, iy + 1); with
+// ax = ix + 1 it is binned to tile (ax / TX, ay / TY) of a bin lattice one
+// wider than the owner tiles, where both of its columns lie in that tile
+// except, when ax is a multiple of TX, column ix, which lies in the tile to
+// the left (an "x edge" record; the same in y).  Each bin holds four classes
+// in the order: interior, x edge, x and y edge, y edge, so that the owner of
+// tile (ox, oy) reads its own bin whole, classes 1-2 of bin (ox + 1, oy),
+// classes 2-3 of bin (ox, oy + 1) and class 2 of bin (ox + 1, oy + 1): four
+// contiguous index ranges.  Nearest-grid-point records (mode 0) use class 0 of
+// the tile of their cell.
+// A record counts if the particle was born by s_k and still active after it
+// and its mass is positive.
 constexpr int kRecChunk = 8 * kBlock;
+constexpr int kBinLds = 4096;  // bins per output step held in LDS by the binning kernels
 
-template <int NNUC>
-__global__ __launch_bounds__(kBlock) void rec_conc_kernel(const GridConst g, const float4* rec,
-                                                          const int* last, long long rec_stride,
-                                                          int rec_step0, int rec_every)
+struct TileConst {
+    int tx, ty;        // tile width and depth in cells
+    int ntx, nty;      // owner tiles
+    int nbx, nby;      // bin tiles (nx / tx + 1, ny / ty + 1)
+    long long nbk;     // bins per output step: nbx nby 4
+    unsigned long long* off;  // [n_rec nbk] first index of each bin
+    unsigned long long* cur;  // [n_rec nbk] counts, then end of each bin
+    unsigned long long* bsum; // per-block sums of the scan
+    uint32_t* idx;            // particle index of each binned record
+    unsigned long long cap;   // entries of idx
+    float* out;
+    double inv_vol;
+};
+
+// Bin of a record within its output step, or -1 if no grid cell receives
+// any of it (also for a non-finite position).  The cell index and weights use
+// the same double-precision arithmetic as conc_kernel.
+__device__ __forceinline__ int record_bin(const GridConst& g, const TileConst& t, float x, float y,
+                                          float z)
 {
-    using Table = CellTable<NNUC, NNUC <= 2 ? 11 : 10>;
-    __shared__ int tab_key[Table::kSlots];
-    __shared__ double tab_val[NNUC * Table::kSlots];
-    Table tab{tab_key, tab_val};
+    const double fx = ((double)x - g.x0) * g.inv_dx;
+    const double fy = ((double)y - g.y0) * g.inv_dy;
+    const double fz = ((double)z - g.z0) * g.inv_dz;
+    if (g.mode == 0) {
+        const double ix = floor(fx), iy = floor(fy), iz = floor(fz);
+        if (!(ix >= 0.0 && iy >= 0.0 && iz >= 0.0 && ix < (double)g.nx && iy < (double)g.ny &&
+              iz < (double)g.nz))
+            return -1;
+        return (((int)iy / t.ty) * t.nbx + (int)ix / t.tx) * 4;
+    }
+    const double ix = floor(fx - 0.5), iy = floor(fy - 0.5), iz = floor(fz - 0.5);
+    if (!(ix >= -1.0 && iy >= -1.0 && iz >= -1.0 && ix < (double)g.nx && iy < (double)g.ny &&
+          iz < (double)g.nz))
+        return -1;
+    const int ax = (int)ix + 1, ay = (int)iy + 1;
+    const bool ex = ax > 0 && ax % t.tx == 0, ey = ay > 0 && ay % t.ty == 0;
+    const int cls = ex ? (ey ? 2 : 1) : (ey ? 3 : 0);
+    return ((ay / t.ty) * t.nbx + ax / t.tx) * 4 + cls;
+}
+
+// Shared by the two binning kernels: the record of local particle i at output
+// step `step`, and its bin (-1 if it does not count).
+__device__ __forceinline__ int binned_record(const GridConst& g, const TileConst& t,
+                                             const float4* rec_k, const int* last, long long i,
+                                             int step)
+{
+    if (i >= g.i_hi) return -1;
+    if (birth(g.id_base + i * g.id_stride, g.s_release, g.n_total) > step || step >= last[i])
+        return -1;
+    const float4 r = rec_k[i];
+    if (!(r.w > 0.0f)) return -1;
+    return record_bin(g, t, r.x, r.y, r.z);
+}
+
+// Local ids are born in increasing order: a chunk whose first id is born
+// after the output step holds no record of it.
+__device__ __forceinline__ bool chunk_unborn(const GridConst& g, long long i0, int step)
+{
+    return i0 >= g.i_hi || birth(g.id_base + i0 * g.id_stride, g.s_release, g.n_total) > step;
+}
+
+// Pass 1: records per bin.  LDS: nbk counters when nbk <= kBinLds.
+__global__ __launch_bounds__(kBlock) void bin_count_kernel(const GridConst g, const TileConst t,
+                                                           const float4* rec, const int* last,
+                                                           long long rec_stride, int rec_step0,
+                                                           int rec_every)
+{
+    extern __shared__ unsigned long long lds_u64[];
+    uint32_t* hist = reinterpret_cast<uint32_t*>(lds_u64);
     const int k = blockIdx.y;
     const int step = rec_step0 + k * rec_every;
-    double* acc = g.acc + (long long)k * NNUC * g.cells;
     const long long i0 = (long long)blockIdx.x * kRecChunk;
-    // particle (i0 + u kBlock + threadIdx.x) is gridded if born by the output
-    // step and still airborne after it
-    auto live_at = [&](long long i, long long& b) {
-        if (i >= g.i_hi) return false;
-        b = birth(g.id_base + i * g.id_stride, g.s_release, g.n_total);
-        return b <= step && step < last[i];
-    };
+    if (chunk_unborn(g, i0, step)) return;
+    const float4* rec_k = rec + (long long)k * rec_stride;
+    unsigned long long* cnt = t.cur + (long long)k * t.nbk;
+    int bin[kRecChunk / kBlock];
     bool any = false;
 #pragma unroll
     for (int u = 0; u < kRecChunk / kBlock; ++u) {
-        long long b;
-        any |= live_at(i0 + u * kBlock + threadIdx.x, b);
+        bin[u] = binned_record(g, t, rec_k, last, i0 + u * kBlock + threadIdx.x, step);
+        any |= bin[u] >= 0;
     }
-    // most (chunk, output step) pairs hold no airborne particle: the chunk's
-    // ids are born later or gone; skip the table for them
+    const bool lds = t.nbk <= kBinLds;
+    if (!lds) {
+#pragma unroll
+        for (int u = 0; u < kRecChunk / kBlock; ++u)
+            if (bin[u] >= 0) atomicAdd(cnt + bin[u], 1ull);
+        return;
+    }
     if (!__syncthreads_or(any)) return;
-    tab.init();
+    for (int b = threadIdx.x; b < (int)t.nbk; b += kBlock) hist[b] = 0u;
     __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kRecChunk / kBlock; ++u)
+        if (bin[u] >= 0) atomicAdd(hist + bin[u], 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < (int)t.nbk; b += kBlock)
+        if (hist[b]) atomicAdd(cnt + b, (unsigned long long)hist[b]);
+}
+
+// Pass 3: particle indices into their bins.  With LDS, a block ranks its
+// records per bin, reserves one range per bin with a single global atomic and
+// writes the indices there.
+__global__ __launch_bounds__(kBlock) void bin_scatter_kernel(const GridConst g, const TileConst t,
+                                                             const float4* rec, const int* last,
+                                                             long long rec_stride, int rec_step0,
+                                                             int rec_every)
+{
+    extern __shared__ unsigned long long lds_u64[];
+    const int k = blockIdx.y;
+    const int step = rec_step0 + k * rec_every;
+    const long long i0 = (long long)blockIdx.x * kRecChunk;
+    if (chunk_unborn(g, i0, step)) return;
+    const float4* rec_k = rec + (long long)k * rec_stride;
+    unsigned long long* cur = t.cur + (long long)k * t.nbk;
+    int bin[kRecChunk / kBlock];
+    bool any = false;
+#pragma unroll
     for (int u = 0; u < kRecChunk / kBlock; ++u) {
-        const long long i = i0 + u * kBlock + threadIdx.x;
-        long long b = 0;
-        if (!live_at(i, b)) continue;
+        bin[u] = binned_record(g, t, rec_k, last, i0 + u * kBlock + threadIdx.x, step);
+        any |= bin[u] >= 0;
+    }
+    const bool lds = t.nbk <= kBinLds;
+    if (!lds) {
+#pragma unroll
+        for (int u = 0; u < kRecChunk / kBlock; ++u)
+            if (bin[u] >= 0) {
+                const unsigned long long pos = atomicAdd(cur + bin[u], 1ull);
+                if (pos < t.cap) t.idx[pos] = (uint32_t)(i0 + u * kBlock + threadIdx.x);
+            }
+        return;
+    }
+    if (!__syncthreads_or(any)) return;
+    unsigned long long* base = lds_u64;                             // [nbk]
+    uint32_t* rank = reinterpret_cast<uint32_t*>(lds_u64 + t.nbk);  // [nbk]
+    for (int b = threadIdx.x; b < (int)t.nbk; b += kBlock) rank[b] = 0u;
+    __syncthreads();
+    uint32_t r[kRecChunk / kBlock];
+#pragma unroll
+    for (int u = 0; u < kRecChunk / kBlock; ++u)
+        r[u] = bin[u] >= 0 ? atomicAdd(rank + bin[u], 1u) : 0u;
+    __syncthreads();
+    for (int b = threadIdx.x; b < (int)t.nbk; b += kBlock)
+        if (rank[b]) base[b] = atomicAdd(cur + b, (unsigned long long)rank[b]);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kRecChunk / kBlock; ++u)
+        if (bin[u] >= 0) {
+            const unsigned long long pos = base[bin[u]] + r[u];
+            if (pos < t.cap) t.idx[pos] = (uint32_t)(i0 + u * kBlock + threadIdx.x);
+        }
+}
+
+// Pass 2: exclusive scan of the counts (cur) into off, and cur = off.  Three
+// launches: block sums, a one-block scan of the sums, the block scans.
+constexpr int kScanPer = 8;
+constexpr int kScanChunk = kScanPer * kBlock;
+
+__device__ __forceinline__ unsigned long long block_exclusive_scan(unsigned long long v,
+                                                                   unsigned long long* s,
+                                                                   unsigned long long* total)
+{
+    s[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int d = 1; d < kBlock; d <<= 1) {
+        const unsigned long long a = threadIdx.x >= (unsigned)d ? s[threadIdx.x - d] : 0ull;
+        __syncthreads();
+        s[threadIdx.x] += a;
+        __syncthreads();
+    }
+    const unsigned long long incl = s[threadIdx.x];
+    *total = s[kBlock - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_sums_kernel(const unsigned long long* cnt,
+                                                           long long n, unsigned long long* bsum)
+{
+    __shared__ unsigned long long s[kBlock];
+    const long long a = (long long)blockIdx.x * kScanChunk + (long long)threadIdx.x * kScanPer;
+    unsigned long long v = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j)
+        if (a + j < n) v += cnt[a + j];
+    unsigned long long tot;
+    block_exclusive_scan(v, s, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_bsum_kernel(unsigned long long* bsum, long long nb)
+{
+    __shared__ unsigned long long s[kBlock];
+    unsigned long long carry = 0;
+    for (long long a = 0; a < nb; a += kBlock) {
+        const long long j = a + threadIdx.x;
+        const unsigned long long v = j < nb ? bsum[j] : 0ull;
+        unsigned long long tot;
+        const unsigned long long ex = block_exclusive_scan(v, s, &tot);
+        if (j < nb) bsum[j] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void scan_apply_kernel(unsigned long long* cur,
+                                                            unsigned long long* off, long long n,
+                                                            const unsigned long long* bsum)
+{
+    __shared__ unsigned long long s[kBlock];
+    const long long a = (long long)blockIdx.x * kScanChunk + (long long)threadIdx.x * kScanPer;
+    unsigned long long c[kScanPer], v = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        c[j] = a + j < n ? cur[a + j] : 0ull;
+        v += c[j];
+    }
+    unsigned long long tot;
+    unsigned long long run = bsum[blockIdx.x] + block_exclusive_scan(v, s, &tot);
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j)
+        if (a + j < n) {
+            off[a + j] = run;
+            cur[a + j] = run;
+            run += c[j];
+        }
+}
+
+// Pass 4: one block per (owner tile, output step).  LDS: the tile's cells,
+// double [NNUC][nz][ty][tx].
+template <int NNUC>
+__global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, const TileConst t,
+                                                           const float4* rec, long long rec_stride,
+                                                           int rec_step0, int rec_every)
+{
+    extern __shared__ double tile[];
+    const int ox = blockIdx.x % t.ntx, oy = blockIdx.x / t.ntx, k = blockIdx.y;
+    const int step = rec_step0 + k * rec_every;
+    const int xa = ox * t.tx, ya = oy * t.ty;
+    const int wx_n = min(t.tx, g.nx - xa), wy_n = min(t.ty, g.ny - ya);
+    const int ncell = g.nz * t.ty * t.tx;
+    // the four index ranges (see the bin layout above)
+    const long long b0 = (long long)k * t.nbk + ((long long)oy * t.nbx + ox) * 4;
+    const long long bx1 = b0 + 4, by1 = b0 + (long long)t.nbx * 4, bxy = by1 + 4;
+    const bool has_x = ox + 1 < t.nbx, has_y = oy + 1 < t.nby;
+    const long long lo0 = (long long)t.off[b0];
+    const long long e0 = (long long)t.cur[b0 + 3] - lo0;
+    const long long lo1 = has_x ? (long long)t.off[bx1 + 1] : 0;
+    const long long e1 = e0 + (has_x ? (long long)t.cur[bx1 + 2] - lo1 : 0);
+    const long long lo2 = has_y ? (long long)t.off[by1 + 2] : 0;
+    const long long e2 = e1 + (has_y ? (long long)t.cur[by1 + 3] - lo2 : 0);
+    const long long lo3 = has_x && has_y ? (long long)t.off[bxy + 2] : 0;
+    const long long total = e2 + (has_x && has_y ? (long long)t.cur[bxy + 2] - lo3 : 0);
+    float* out = t.out + (long long)k * NNUC * g.cells;
+    if (total == 0) {
+        for (int c = threadIdx.x; c < NNUC * ncell; c += kBlock) {
+            const int xx = c % t.tx, yy = (c / t.tx) % t.ty, zn = c / (t.tx * t.ty);
+            if (xx < wx_n && yy < wy_n)
+                out[((long long)zn * g.ny + ya + yy) * g.nx + xa + xx] = 0.0f;
+        }
+        return;
+    }
+    for (int c = threadIdx.x; c < NNUC * ncell; c += kBlock) tile[c] = 0.0;
+    __syncthreads();
+    for (long long j = threadIdx.x; j < total; j += kBlock) {
+        const long long pos = j < e0 ? lo0 + j
+                              : j < e1 ? lo1 + (j - e0)
+                              : j < e2 ? lo2 + (j - e1) : lo3 + (j - e2);
+        const long long i = t.idx[pos];
         const float4 r = rec[(long long)k * rec_stride + i];
-        if (!(r.w > 0.0f)) continue;
+        const long long b = birth(g.id_base + i * g.id_stride, g.s_release, g.n_total);
         const float age = (float)(step + 1 - (int)b) * g.dt;
         float A[NNUC];
         activities<NNUC>(g, age, g.a0 * r.w * g.scale, A);
@@ -847,32 +1098,34 @@ __global__ __launch_bounds__(kBlock) void rec_conc_kernel(const GridConst g, con
         const double fy = ((double)r.y - g.y0) * g.inv_dy;
         const double fz = ((double)r.z - g.z0) * g.inv_dz;
         if (g.mode == 0) {
-            const double ix = floor(fx), iy = floor(fy), iz = floor(fz);
-            if (ix >= 0.0 && iy >= 0.0 && iz >= 0.0 && ix < (double)g.nx && iy < (double)g.ny &&
-                iz < (double)g.nz)  // false for NaN
-                tab.add((int)(((long long)iz * g.ny + (long long)iy) * g.nx + (long long)ix), A,
-                        acc, g.cells);
-        } else {
-            const double ix = floor(fx - 0.5), iy = floor(fy - 0.5), iz = floor(fz - 0.5);
-            const float wx = (float)(fx - 0.5 - ix), wy = (float)(fy - 0.5 - iy);
-            const float wz = (float)(fz - 0.5 - iz);
-            for (int c = 0; c < 8; ++c) {
-                const double kx = ix + (c & 1), ky = iy + ((c >> 1) & 1), kz = iz + (c >> 2);
-                if (!(kx >= 0.0 && ky >= 0.0 && kz >= 0.0 && kx < (double)g.nx &&
-                      ky < (double)g.ny && kz < (double)g.nz))  // also skips NaN
-                    continue;
-                const float w = ((c & 1) ? wx : 1.0f - wx) * (((c >> 1) & 1) ? wy : 1.0f - wy) *
-                                ((c >> 2) ? wz : 1.0f - wz);
-                float v[NNUC];
+            const int cx = (int)floor(fx) - xa, cy = (int)floor(fy) - ya, cz = (int)floor(fz);
+            if (cx >= 0 && cx < wx_n && cy >= 0 && cy < wy_n && cz >= 0 && cz < g.nz) {
 #pragma unroll
-                for (int n = 0; n < NNUC; ++n) v[n] = A[n] * w;
-                tab.add((int)(((long long)kz * g.ny + (long long)ky) * g.nx + (long long)kx), v,
-                        acc, g.cells);
+                for (int n = 0; n < NNUC; ++n)
+                    atomicAdd(&tile[((n * g.nz + cz) * t.ty + cy) * t.tx + cx], (double)A[n]);
             }
+            continue;
+        }
+        const double ix = floor(fx - 0.5), iy = floor(fy - 0.5), iz = floor(fz - 0.5);
+        const float wx = (float)(fx - 0.5 - ix), wy = (float)(fy - 0.5 - iy);
+        const float wz = (float)(fz - 0.5 - iz);
+        const int cx0 = (int)ix - xa, cy0 = (int)iy - ya, cz0 = (int)iz;
+        for (int c = 0; c < 8; ++c) {
+            const int cx = cx0 + (c & 1), cy = cy0 + ((c >> 1) & 1), cz = cz0 + (c >> 2);
+            if (!(cx >= 0 && cx < wx_n && cy >= 0 && cy < wy_n && cz >= 0 && cz < g.nz)) continue;
+            const float w = ((c & 1) ? wx : 1.0f - wx) * (((c >> 1) & 1) ? wy : 1.0f - wy) *
+                            ((c >> 2) ? wz : 1.0f - wz);
+#pragma unroll
+            for (int n = 0; n < NNUC; ++n)
+                atomicAdd(&tile[((n * g.nz + cz) * t.ty + cy) * t.tx + cx], (double)(A[n] * w));
         }
     }
     __syncthreads();
-    tab.flush(acc, g.cells);
+    for (int c = threadIdx.x; c < NNUC * ncell; c += kBlock) {
+        const int xx = c % t.tx, yy = (c / t.tx) % t.ty, zn = c / (t.tx * t.ty);
+        if (xx < wx_n && yy < wy_n)
+            out[((long long)zn * g.ny + ya + yy) * g.nx + xa + xx] = (float)(tile[c] * t.inv_vol);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void fill_f64(double* p, long long n)
@@ -1276,10 +1529,11 @@ unsigned resident_blocks(K kernel, unsigned wanted)
 {
     static int per_cu = -1;  // one cache per kernel instance
     int dev = 0;
-    hipGetDevice(&dev);
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     static int cus_dev = -1, cus = 0;
     if (cus_dev != dev) {
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 0;  // one block per CU-less device: the launch still drains its queue
         cus_dev = dev;
     }
     if (per_cu < 0) {
@@ -1610,9 +1864,9 @@ int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lp
             g_blocks_per_cu = o;
             for (int rep = 0; rep < 2; ++rep) {  // first repetition warms up
                 if ((rc = lpm_release_ensemble(st, &trial, ledgers, stream))) break;
-                hipEventRecord(e0, s);
+                if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(LPM_EHIP, "lpm_autotune_ensemble: hipEventRecord failed"); break; }
                 if ((rc = lpm_step_ensemble(st, &trial, fld, ph, dep_grid, dep, ledgers, ctrl, stream))) break;
-                hipEventRecord(e1, s);
+                if (hipEventRecord(e1, s) != hipSuccess) { rc = fail(LPM_EHIP, "lpm_autotune_ensemble: hipEventRecord failed"); break; }
             }
             if (rc) break;
             float ms = 0.0f;
@@ -1626,8 +1880,8 @@ int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lp
         }
         if (rc) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     g_refill_every = rc ? keep_refill : best_r;
     g_refill_min = rc ? keep_min : best_m;
     g_blocks_per_cu = rc ? keep_bpc : best_o;
@@ -1696,26 +1950,95 @@ int lpm_grid_concentration(const lpm_state* st, const lpm_source* src, const lpm
     return hip_status("lpm_grid_concentration");
 }
 
-int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, int32_t rec_every,
-                     int32_t n_rec, const lpm_source* src, const lpm_schedule* sch,
-                     const lpm_physics* ph, const lpm_grid* grid, double* acc_scratch, float* out,
-                     lpm_stream stream)
+namespace lpm_host {
+
+// Layout of the record-gridding workspace and the tile shape: the widest
+// tile of full height whose cells (double, n_nuc of them each) fit the LDS
+// budget of one block.
+struct RecordPlan {
+    int tx, ty, ntx, nty, nbx, nby;
+    long long nbk, nb, nscan;
+    unsigned long long cap;        // binned records at most
+    size_t o_off, o_cur, o_bsum, o_idx, bytes;
+    size_t tile_lds;
+};
+
+constexpr size_t kTileLds = 49152;
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int plan_records(const lpm_schedule* sch, const lpm_physics* ph, const lpm_grid* grid,
+                 int32_t rec_step0, int32_t rec_every, int32_t n_rec, RecordPlan* rp)
 {
-    g_msg[0] = 0;
-    if (!src || !sch) return fail(LPM_EINVAL, "null source or schedule");
     int rc;
+    if (!sch) return fail(LPM_EINVAL, "null schedule");
     if ((rc = check_physics(ph)) || (rc = check_grid(grid, false))) return rc;
     if (sch->n_total <= 0 || sch->s_release <= 0 || sch->n_local < 0 || sch->id_stride <= 0)
         return fail(LPM_EINVAL, "bad schedule");
     if (n_rec < 0 || rec_every < 1 || rec_step0 < 0) return fail(LPM_EINVAL, "bad record steps");
+    if ((long long)rec_step0 + (long long)(n_rec > 0 ? n_rec - 1 : 0) * rec_every > 0x7FFFFFFFll)
+        return fail(LPM_EINVAL, "record steps overflow");
+    if (n_rec > 65535) return fail(LPM_EINVAL, "at most 65535 records per call");
+    if (sch->n_local > 0xFFFFFFFFll) return fail(LPM_EINVAL, "at most 2^32 - 1 local particles");
+    const size_t column = (size_t)ph->n_nuc * grid->nz * sizeof(double);
+    static const int shapes[][2] = {{16, 4}, {8, 4}, {8, 2}, {4, 2}, {2, 2}, {2, 1}, {1, 1}};
+    int pick = -1;
+    for (int j = 0; j < 7 && pick < 0; ++j)
+        if (column * shapes[j][0] * shapes[j][1] <= kTileLds) pick = j;
+    if (pick < 0) return fail(LPM_EINVAL, "n_nuc * nz must be at most 6144 to grid records");
+    RecordPlan r;
+    r.tx = shapes[pick][0]; r.ty = shapes[pick][1];
+    r.ntx = (grid->nx + r.tx - 1) / r.tx; r.nty = (grid->ny + r.ty - 1) / r.ty;
+    r.nbx = grid->nx / r.tx + 1; r.nby = grid->ny / r.ty + 1;
+    r.nbk = (long long)r.nbx * r.nby * 4;
+    r.nb = r.nbk * n_rec;
+    if (r.nb > (1ll << 34)) return fail(LPM_EINVAL, "too many grid tiles times records");
+    r.nscan = (r.nb + lpm::kScanChunk - 1) / lpm::kScanChunk;
+    r.cap = 0;
+    for (int k = 0; k < n_rec; ++k)
+        r.cap += (unsigned long long)first_local_born_at_or_after(
+            sch, (long long)rec_step0 + (long long)k * rec_every + 1);
+    r.o_off = 0;
+    r.o_cur = r.o_off + align256(8 * (size_t)r.nb);
+    r.o_bsum = r.o_cur + align256(8 * (size_t)r.nb);
+    r.o_idx = r.o_bsum + align256(8 * (size_t)r.nscan);
+    r.bytes = r.o_idx + align256(4 * (size_t)r.cap);
+    r.tile_lds = column * r.tx * r.ty;
+    *rp = r;
+    return LPM_OK;
+}
+
+}  // namespace lpm_host
+
+int lpm_grid_records_workspace(const lpm_schedule* sch, const lpm_physics* ph,
+                               const lpm_grid* grid, int32_t rec_step0, int32_t rec_every,
+                               int32_t n_rec, int64_t* bytes)
+{
+    g_msg[0] = 0;
+    if (!bytes) return fail(LPM_EINVAL, "null output");
+    RecordPlan rp;
+    const int rc = plan_records(sch, ph, grid, rec_step0, rec_every, n_rec, &rp);
+    if (rc) return rc;
+    *bytes = n_rec == 0 ? 0 : (int64_t)rp.bytes;
+    return LPM_OK;
+}
+
+int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, int32_t rec_every,
+                     int32_t n_rec, const lpm_source* src, const lpm_schedule* sch,
+                     const lpm_physics* ph, const lpm_grid* grid, void* work, int64_t work_bytes,
+                     float* out, lpm_stream stream)
+{
+    g_msg[0] = 0;
+    if (!src) return fail(LPM_EINVAL, "null source");
+    RecordPlan rp;
+    int rc = plan_records(sch, ph, grid, rec_step0, rec_every, n_rec, &rp);
+    if (rc) return rc;
     if (n_rec == 0) return LPM_OK;
     if (!rec || ((uintptr_t)rec & 15u)) return fail(LPM_EINVAL, "null or misaligned record buffer");
     if (rec_stride < sch->n_local) return fail(LPM_EINVAL, "rec_stride below n_local");
-    if (!acc_scratch || !out || ((uintptr_t)acc_scratch & 7u) || !aligned4(out))
-        return fail(LPM_EINVAL, "null or misaligned grid buffers");
-    if ((long long)rec_step0 + (long long)(n_rec - 1) * rec_every > 0x7FFFFFFFll)
-        return fail(LPM_EINVAL, "record steps overflow");
-    if (n_rec > 65535) return fail(LPM_EINVAL, "at most 65535 records per call");
+    if (!out || !aligned4(out)) return fail(LPM_EINVAL, "null or misaligned output");
+    if (!work || ((uintptr_t)work & 255u)) return fail(LPM_EINVAL, "null or misaligned workspace");
+    if (work_bytes < (int64_t)rp.bytes) return fail(LPM_EINVAL, "workspace below lpm_grid_records_workspace");
     lpm::GridConst g;
     memset(&g, 0, sizeof g);
     g.n_total = sch->n_total; g.id_base = sch->id_base; g.id_stride = sch->id_stride;
@@ -1731,28 +2054,50 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     g.x0 = grid->x0; g.y0 = grid->y0; g.z0 = grid->z0;
     g.inv_dx = 1.0 / grid->dx; g.inv_dy = 1.0 / grid->dy; g.inv_dz = 1.0 / grid->dz;
     g.cells = (long long)grid->nx * grid->ny * grid->nz;
-    g.acc = acc_scratch;
     // every particle that can be born by the last recorded step
     g.i_hi = first_local_born_at_or_after(sch, (long long)rec_step0 + (long long)(n_rec - 1) * rec_every + 1);
-    const long long total = g.cells * ph->n_nuc * n_rec;
-    const double vol = grid->density ? grid->dx * grid->dy * grid->dz : 1.0;
+    char* w = (char*)work;
+    lpm::TileConst t;
+    t.tx = rp.tx; t.ty = rp.ty; t.ntx = rp.ntx; t.nty = rp.nty; t.nbx = rp.nbx; t.nby = rp.nby;
+    t.nbk = rp.nbk;
+    t.off = (unsigned long long*)(w + rp.o_off);
+    t.cur = (unsigned long long*)(w + rp.o_cur);
+    t.bsum = (unsigned long long*)(w + rp.o_bsum);
+    t.idx = (uint32_t*)(w + rp.o_idx);
+    t.cap = rp.cap;
+    t.out = out;
+    t.inv_vol = 1.0 / (grid->density ? grid->dx * grid->dy * grid->dz : 1.0);
     hipStream_t s = (hipStream_t)stream;
-    const unsigned fb = blocks_for(total) < 16384 ? blocks_for(total) : 16384;
-    hipLaunchKernelGGL(lpm::fill_f64, dim3(fb), dim3(lpm::kBlock), 0, s, acc_scratch, total);
+    const dim3 bs(lpm::kBlock);
+    // counts start at zero (a fill kernel: the call may be captured in a graph)
+    hipLaunchKernelGGL(lpm::fill_u32, dim3(blocks_for(2 * rp.nb)), bs, 0, s, (uint32_t*)t.cur,
+                       2 * rp.nb);
+    const float4* r4 = reinterpret_cast<const float4*>(rec);
+    const int* last = reinterpret_cast<const int*>(rec + 4ll * n_rec * rec_stride);
     if (g.i_hi > 0) {
-        const float4* r4 = reinterpret_cast<const float4*>(rec);
-        const int* last = reinterpret_cast<const int*>(rec + 4ll * n_rec * rec_stride);
-        const dim3 nb((unsigned)((g.i_hi + lpm::kRecChunk - 1) / lpm::kRecChunk), (unsigned)n_rec),
-            bs(lpm::kBlock);
-        switch (ph->n_nuc) {
-        case 1: hipLaunchKernelGGL(lpm::rec_conc_kernel<1>, nb, bs, 0, s, g, r4, last, rec_stride, rec_step0, rec_every); break;
-        case 2: hipLaunchKernelGGL(lpm::rec_conc_kernel<2>, nb, bs, 0, s, g, r4, last, rec_stride, rec_step0, rec_every); break;
-        case 3: hipLaunchKernelGGL(lpm::rec_conc_kernel<3>, nb, bs, 0, s, g, r4, last, rec_stride, rec_step0, rec_every); break;
-        default: hipLaunchKernelGGL(lpm::rec_conc_kernel<4>, nb, bs, 0, s, g, r4, last, rec_stride, rec_step0, rec_every); break;
-        }
+        const dim3 nb((unsigned)((g.i_hi + lpm::kRecChunk - 1) / lpm::kRecChunk), (unsigned)n_rec);
+        const bool lds = rp.nbk <= lpm::kBinLds;
+        hipLaunchKernelGGL(lpm::bin_count_kernel, nb, bs, lds ? 4 * rp.nbk : 0, s, g, t, r4, last,
+                           rec_stride, rec_step0, rec_every);
+        hipLaunchKernelGGL(lpm::scan_sums_kernel, dim3((unsigned)rp.nscan), bs, 0, s, t.cur, rp.nb,
+                           t.bsum);
+        hipLaunchKernelGGL(lpm::scan_bsum_kernel, dim3(1), bs, 0, s, t.bsum, rp.nscan);
+        hipLaunchKernelGGL(lpm::scan_apply_kernel, dim3((unsigned)rp.nscan), bs, 0, s, t.cur, t.off,
+                           rp.nb, (const unsigned long long*)t.bsum);
+        hipLaunchKernelGGL(lpm::bin_scatter_kernel, nb, bs, lds ? 12 * rp.nbk : 0, s, g, t, r4,
+                           last, rec_stride, rec_step0, rec_every);
+    } else {
+        // nothing is born: every bin is empty (off = cur = 0)
+        hipLaunchKernelGGL(lpm::fill_u32, dim3(blocks_for(2 * rp.nb)), bs, 0, s, (uint32_t*)t.off,
+                           2 * rp.nb);
     }
-    hipLaunchKernelGGL(lpm::to_f32, dim3(fb), dim3(lpm::kBlock), 0, s, acc_scratch, out, total,
-                       1.0 / vol);
+    const dim3 tg((unsigned)((long long)rp.ntx * rp.nty), (unsigned)n_rec);
+    switch (ph->n_nuc) {
+    case 1: hipLaunchKernelGGL(lpm::tile_conc_kernel<1>, tg, bs, rp.tile_lds, s, g, t, r4, rec_stride, rec_step0, rec_every); break;
+    case 2: hipLaunchKernelGGL(lpm::tile_conc_kernel<2>, tg, bs, rp.tile_lds, s, g, t, r4, rec_stride, rec_step0, rec_every); break;
+    case 3: hipLaunchKernelGGL(lpm::tile_conc_kernel<3>, tg, bs, rp.tile_lds, s, g, t, r4, rec_stride, rec_step0, rec_every); break;
+    default: hipLaunchKernelGGL(lpm::tile_conc_kernel<4>, tg, bs, rp.tile_lds, s, g, t, r4, rec_stride, rec_step0, rec_every); break;
+    }
     return hip_status("lpm_grid_records");
 }
 

@@ -14,7 +14,7 @@ import torch
 from . import (Accum, Field, Grid, Physics, Receptors, Schedule, Scenario, Source, State,
                CTRL_WORDS, LEDGER_SLOTS, LEDGER_STRIDE, SCENARIO_BYTES, accum_reset,
                adjoint_workspace, autotune_ensemble, ensemble_prepare, grid_concentration,
-               grid_deposition, grid_records, read_ledger, receptor_adjoint,
+               grid_deposition, grid_records, grid_records_workspace, read_ledger, receptor_adjoint,
                receptor_concentration, release_ensemble, release_particles, step_ensemble,
                step_particles, step_particles_record, check)
 
@@ -134,17 +134,19 @@ class DeviceRun:
         return torch.empty((4 * n_rec + 1) * self.rec_stride, dtype=torch.float32,
                            device=self.device)
 
-    def grid_buffers(self, n_rec: int):
+    def grid_buffers(self, rec_step0: int, every: int, n_rec: int):
+        """Workspace and output of grid_records for these output steps."""
         cg, nn = self.case.conc_grid, self.case.physics.n_nuc
-        shape = (n_rec, nn, cg.nz, cg.ny, cg.nx)
-        return (torch.empty(shape, dtype=torch.float64, device=self.device),
-                torch.empty(shape, dtype=torch.float32, device=self.device))
+        nbytes = grid_records_workspace(self.sch, self.ph, self.cgrid, rec_step0, every, n_rec)
+        return (torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device),
+                torch.empty((n_rec, nn, cg.nz, cg.ny, cg.nx), dtype=torch.float32,
+                            device=self.device))
 
     def grid_records(self, rec: torch.Tensor, rec_step0: int, every: int, n_rec: int,
                      bufs=None):
-        scratch, out = bufs if bufs is not None else self.grid_buffers(n_rec)
+        work, out = bufs if bufs is not None else self.grid_buffers(rec_step0, every, n_rec)
         grid_records(rec, self.rec_stride, rec_step0, every, n_rec, self.src, self.sch, self.ph,
-                     self.cgrid, scratch, out)
+                     self.cgrid, work, out)
         return out
 
     # -- the host main loop -------------------------------------------------

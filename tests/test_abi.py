@@ -188,3 +188,36 @@ def test_receptor_entry_points_reject_bad_arguments(args):
     assert adj(1 << 40, q0) == L.LPM_EINVAL
     n = C.c_int64(0)
     assert code(L, "lpm_adjoint_workspace", fld, sch, 0, C.byref(n)) == L.LPM_EINVAL
+
+
+def test_record_gridding_workspace_and_rejections(args):
+    """lpm_grid_records_workspace: sizes from the tile plan and the births;
+    too-tall grids and bad buffers are rejected on the host."""
+    L, st, src, sch, ph, fld, acc, grid = args
+    n = C.c_int64(-1)
+    q = lambda g, s0, every, n_rec: code(L, "lpm_grid_records_workspace", sch, ph, g, s0, every,
+                                         n_rec, C.byref(n))
+    assert q(grid, 0, 1, 0) == L.LPM_OK and n.value == 0
+    # 200 x 200 x 30, 2 nuclides: 16 x 4 column tiles, bins (200/16+1)(200/4+1)4 per record
+    # step, two 64-bit words each; a 1000-particle run over 10 steps is fully born by
+    # step 9, so records at steps 4 and 9 hold at most 500 + 1000 particles
+    assert q(grid, 4, 5, 2) == L.LPM_OK
+    nb = 2 * 13 * 51 * 4
+    a256 = lambda b: (b + 255) // 256 * 256
+    assert n.value == 2 * a256(8 * nb) + a256(8 * ((nb + 2047) // 2048)) + a256(4 * 1500)
+    tall = L.Grid.from_buffer_copy(grid)
+    tall.nz = 3073  # 2 nuclides x 3073 levels x 8 B: one column exceeds the block's LDS
+    assert q(tall, 0, 1, 1) == L.LPM_EINVAL
+    tall.nz = 3072
+    assert q(tall, 0, 1, 1) == L.LPM_OK
+    assert q(grid, 0, 0, 1) == L.LPM_EINVAL
+    assert q(grid, 0, 1, 65536) == L.LPM_EINVAL
+    fake = C.c_void_p(0x10000)
+    rec = C.c_void_p(0x10000)
+    call = lambda work, nbytes, out: code(L, "lpm_grid_records", rec, 1000, 4, 5, 2, src, sch, ph,
+                                          grid, work, nbytes, out, None)
+    assert q(grid, 4, 5, 2) == L.LPM_OK
+    assert call(fake, n.value - 1, fake) == L.LPM_EINVAL          # workspace too small
+    assert call(C.c_void_p(0x10010), n.value, fake) == L.LPM_EINVAL  # not 256-byte aligned
+    assert call(None, n.value, fake) == L.LPM_EINVAL
+    assert call(fake, n.value, None) == L.LPM_EINVAL
