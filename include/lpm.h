@@ -295,15 +295,16 @@ int lpm_check(const lpm_accum* acc, lpm_stream stream);
 const char* lpm_last_error(void);
 
 /* Launch tuning of the step kernels (process-wide): a wave refills idle
- * lanes from the work queue every `refill_every` steps (default 16), and at
+ * lanes from the work queue every `refill_every` steps (default 24), and at
  * most `blocks_per_cu` blocks per compute unit are launched (0 = as many as
  * fit).  Results do not depend on either. */
 int lpm_set_launch(int32_t refill_every, int32_t blocks_per_cu);
 
 /* lpm_set_launch, and a wave refills only once at least `refill_min` of its
- * 64 lanes are idle (or all of them; default 64: a wave takes new particles
- * only once all its lanes are idle, which keeps particles released together
- * in one wave). */
+ * 64 lanes are idle (or all of them; default 56: a wave takes new particles
+ * only once nearly all its lanes are idle, which keeps particles released
+ * together in one wave; lanes that mix particles of different ages take
+ * different branches). */
 int lpm_set_launch_ex(int32_t refill_every, int32_t blocks_per_cu, int32_t refill_min);
 
 /* ---------------------------------------------------------------------------

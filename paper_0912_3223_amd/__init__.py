@@ -327,7 +327,7 @@ def surface_layer(U: float, z_ref: float, z0: float, dtheta: float, T0: float):
     return us.value, il.value
 
 
-def set_launch(refill_every: int = 16, blocks_per_cu: int = 0, refill_min: int = 64):
+def set_launch(refill_every: int = 24, blocks_per_cu: int = 0, refill_min: int = 56):
     _rc(_lib.lpm_set_launch_ex(refill_every, blocks_per_cu, refill_min))
 
 

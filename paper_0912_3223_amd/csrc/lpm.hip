@@ -1159,8 +1159,8 @@ thread_local char g_msg[kMsgLen] = "";
 
 // Launch tuning of the persistent step kernel (process-wide; set by the
 // autotuner or lpm_set_launch).
-int g_refill_every = 16;
-int g_refill_min = 64;
+int g_refill_every = 24;
+int g_refill_min = 56;
 int g_blocks_per_cu = 0;  // 0: as many as the device holds
 
 int fail(int code, const char* fmt, ...)
@@ -1845,7 +1845,7 @@ int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lp
     hipStream_t s = (hipStream_t)stream;
     // queue schedules (refill interval, idle lanes before a refill) x blocks
     // per compute unit
-    const int refills[][2] = {{1, 1}, {4, 1}, {16, 32}, {16, 64}};
+    const int refills[][2] = {{1, 1}, {4, 1}, {16, 32}, {16, 64}, {24, 56}};
     const int occupancy[] = {0, 3, 2};
     lpm_ensemble trial;
     int rc = lpm_ensemble_prepare(scen, ens->n_scen, st, ph, ens->step0, trial_steps, ens->table,

@@ -83,7 +83,7 @@ def test_autotuner_changes_no_result():
     t = e.autotune(trial_steps=60)
     log("autotune: refill %d blocks/cu %d best %.3f ms worst %.3f ms (%d tried)"
         % (t.refill_every, t.blocks_per_cu, t.best_ms, t.worst_ms, t.n_tried))
-    assert t.n_tried == 12 and t.best_ms <= t.worst_ms
+    assert t.n_tried == 15 and t.best_ms <= t.worst_ms  # 5 queue schedules x 3 occupancies
     e.run()
     for c in range(6):
         for k in "xyzm":
