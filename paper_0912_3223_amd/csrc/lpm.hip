@@ -6,20 +6,22 @@
 // Kernels
 //  - release_kernel: writes the initial state of the particles born in a
 //    window of steps (one thread per particle, coalesced float stores).
-//  - step_kernel: one thread per particle; the particle's state is loaded
-//    once, advanced through every step of the window in registers, and stored
-//    once.  Random numbers come from Philox in registers and the wind is
-//    gathered from the L2/MALL-resident field.  Deposition is aggregated in
-//    three levels before it reaches HBM: per thread while the particle stays
-//    in one grid cell (registers), per block in an LDS hash table of cells
-//    (FP64 LDS atomics), and once per block and cell into the FP64 grid.  The
-//    ledger is reduced per block before one atomic per entry into one of
+//  - step_kernel: persistent; each lane takes particles from a work queue,
+//    loads a particle's state once, advances it through the window in
+//    registers and stores it once.  Random numbers come from Philox in
+//    registers and the wind is gathered from the L2/MALL-resident field.
+//    Deposition is aggregated in four levels before it reaches HBM: per lane
+//    while the particle stays in one cell quad (registers), a per-wave
+//    staging list of quads, a per-wave LDS hash table of cells (FP64 LDS
+//    atomics), and once per table entry into the FP64 grid.  The ledger is
+//    reduced per block before one atomic per entry into one of
 //    LPM_LEDGER_SLOTS spread-out slots.
-//  - conc_kernel + finalize: scatter of activity to an FP64 grid, then
-//    conversion to float.
-//  Blocks keep the hardware's round-robin dealing to the 8 XCDs: live
-//  particles concentrate in the most recently released (highest) ids, and
-//  interleaving consecutive blocks over the XCDs spreads them evenly.
+//  - bin_count_kernel, scan_*, bin_scatter_kernel, tile_conc_kernel: the
+//    concentration of recorded output steps, binned by column tile and
+//    summed per tile in LDS (owner computes: each output cell written once).
+//  - conc_kernel + to_f32: single-step gridding of the live state (scatter
+//    of activity to an FP64 grid through an LDS hash, then conversion).
+//  The shared queue spreads live particles evenly over the 8 XCDs.
 #include <hip/hip_runtime.h>
 
 #include <limits.h>
@@ -821,14 +823,15 @@ constexpr int kRecChunk = 8 * kBlock;
 constexpr int kBinLds = 4096;  // bins per output step held in LDS by the binning kernels
 
 struct TileConst {
-    int tx, ty;        // tile width and depth in cells
+    int tx, ty;        // tile width and depth in cells (powers of two)
+    int lx, ly;        // their base-2 logarithms
     int ntx, nty;      // owner tiles
     int nbx, nby;      // bin tiles (nx / tx + 1, ny / ty + 1)
     long long nbk;     // bins per output step: nbx nby 4
     unsigned long long* off;  // [n_rec nbk] first index of each bin
     unsigned long long* cur;  // [n_rec nbk] counts, then end of each bin
     unsigned long long* bsum; // per-block sums of the scan
-    uint32_t* idx;            // particle index of each binned record
+    int2* idx;                // particle index and birth step of each binned record
     unsigned long long cap;   // entries of idx
     float* out;
     double inv_vol;
@@ -848,27 +851,27 @@ __device__ __forceinline__ int record_bin(const GridConst& g, const TileConst& t
         if (!(ix >= 0.0 && iy >= 0.0 && iz >= 0.0 && ix < (double)g.nx && iy < (double)g.ny &&
               iz < (double)g.nz))
             return -1;
-        return (((int)iy / t.ty) * t.nbx + (int)ix / t.tx) * 4;
+        return ((((int)iy >> t.ly) * t.nbx) + ((int)ix >> t.lx)) * 4;
     }
     const double ix = floor(fx - 0.5), iy = floor(fy - 0.5), iz = floor(fz - 0.5);
     if (!(ix >= -1.0 && iy >= -1.0 && iz >= -1.0 && ix < (double)g.nx && iy < (double)g.ny &&
           iz < (double)g.nz))
         return -1;
     const int ax = (int)ix + 1, ay = (int)iy + 1;
-    const bool ex = ax > 0 && ax % t.tx == 0, ey = ay > 0 && ay % t.ty == 0;
+    const bool ex = ax > 0 && (ax & (t.tx - 1)) == 0, ey = ay > 0 && (ay & (t.ty - 1)) == 0;
     const int cls = ex ? (ey ? 2 : 1) : (ey ? 3 : 0);
-    return ((ay / t.ty) * t.nbx + ax / t.tx) * 4 + cls;
+    return ((ay >> t.ly) * t.nbx + (ax >> t.lx)) * 4 + cls;
 }
 
 // Shared by the two binning kernels: the record of local particle i at output
 // step `step`, and its bin (-1 if it does not count).
 __device__ __forceinline__ int binned_record(const GridConst& g, const TileConst& t,
                                              const float4* rec_k, const int* last, long long i,
-                                             int step)
+                                             int step, int& b)
 {
     if (i >= g.i_hi) return -1;
-    if (birth(g.id_base + i * g.id_stride, g.s_release, g.n_total) > step || step >= last[i])
-        return -1;
+    b = (int)birth(g.id_base + i * g.id_stride, g.s_release, g.n_total);
+    if (b > step || step >= last[i]) return -1;
     const float4 r = rec_k[i];
     if (!(r.w > 0.0f)) return -1;
     return record_bin(g, t, r.x, r.y, r.z);
@@ -899,7 +902,8 @@ __global__ __launch_bounds__(kBlock) void bin_count_kernel(const GridConst g, co
     bool any = false;
 #pragma unroll
     for (int u = 0; u < kRecChunk / kBlock; ++u) {
-        bin[u] = binned_record(g, t, rec_k, last, i0 + u * kBlock + threadIdx.x, step);
+        int b;
+        bin[u] = binned_record(g, t, rec_k, last, i0 + u * kBlock + threadIdx.x, step, b);
         any |= bin[u] >= 0;
     }
     const bool lds = t.nbk <= kBinLds;
@@ -935,11 +939,11 @@ __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(const GridConst g, 
     if (chunk_unborn(g, i0, step)) return;
     const float4* rec_k = rec + (long long)k * rec_stride;
     unsigned long long* cur = t.cur + (long long)k * t.nbk;
-    int bin[kRecChunk / kBlock];
+    int bin[kRecChunk / kBlock], born[kRecChunk / kBlock];
     bool any = false;
 #pragma unroll
     for (int u = 0; u < kRecChunk / kBlock; ++u) {
-        bin[u] = binned_record(g, t, rec_k, last, i0 + u * kBlock + threadIdx.x, step);
+        bin[u] = binned_record(g, t, rec_k, last, i0 + u * kBlock + threadIdx.x, step, born[u]);
         any |= bin[u] >= 0;
     }
     const bool lds = t.nbk <= kBinLds;
@@ -948,7 +952,7 @@ __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(const GridConst g, 
         for (int u = 0; u < kRecChunk / kBlock; ++u)
             if (bin[u] >= 0) {
                 const unsigned long long pos = atomicAdd(cur + bin[u], 1ull);
-                if (pos < t.cap) t.idx[pos] = (uint32_t)(i0 + u * kBlock + threadIdx.x);
+                if (pos < t.cap) t.idx[pos] = make_int2((int)(i0 + u * kBlock + threadIdx.x), born[u]);
             }
         return;
     }
@@ -969,7 +973,7 @@ __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(const GridConst g, 
     for (int u = 0; u < kRecChunk / kBlock; ++u)
         if (bin[u] >= 0) {
             const unsigned long long pos = base[bin[u]] + r[u];
-            if (pos < t.cap) t.idx[pos] = (uint32_t)(i0 + u * kBlock + threadIdx.x);
+            if (pos < t.cap) t.idx[pos] = make_int2((int)(i0 + u * kBlock + threadIdx.x), born[u]);
         }
 }
 
@@ -1050,6 +1054,7 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(unsigned long long* 
 
 // Pass 4: one block per (owner tile, output step).  LDS: the tile's cells,
 // double [NNUC][nz][ty][tx].
+constexpr int kTileBatch = 4;
 template <int NNUC>
 __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, const TileConst t,
                                                            const float4* rec, long long rec_stride,
@@ -1074,24 +1079,14 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
     const long long lo3 = has_x && has_y ? (long long)t.off[bxy + 2] : 0;
     const long long total = e2 + (has_x && has_y ? (long long)t.cur[bxy + 2] - lo3 : 0);
     float* out = t.out + (long long)k * NNUC * g.cells;
-    if (total == 0) {
-        for (int c = threadIdx.x; c < NNUC * ncell; c += kBlock) {
-            const int xx = c % t.tx, yy = (c / t.tx) % t.ty, zn = c / (t.tx * t.ty);
-            if (xx < wx_n && yy < wy_n)
-                out[((long long)zn * g.ny + ya + yy) * g.nx + xa + xx] = 0.0f;
-        }
-        return;
-    }
+    // most tiles hold no record (the plume covers a few per output step):
+    // their cells were cleared by one coalesced fill before this pass
+    if (total == 0) return;
     for (int c = threadIdx.x; c < NNUC * ncell; c += kBlock) tile[c] = 0.0;
     __syncthreads();
-    for (long long j = threadIdx.x; j < total; j += kBlock) {
-        const long long pos = j < e0 ? lo0 + j
-                              : j < e1 ? lo1 + (j - e0)
-                              : j < e2 ? lo2 + (j - e1) : lo3 + (j - e2);
-        const long long i = t.idx[pos];
-        const float4 r = rec[(long long)k * rec_stride + i];
-        const long long b = birth(g.id_base + i * g.id_stride, g.s_release, g.n_total);
-        const float age = (float)(step + 1 - (int)b) * g.dt;
+    // one record's contributions to the tile's cells
+    auto add_record = [&](const float4 r, int b) {
+        const float age = (float)(step + 1 - b) * g.dt;
         float A[NNUC];
         activities<NNUC>(g, age, g.a0 * r.w * g.scale, A);
         const double fx = ((double)r.x - g.x0) * g.inv_dx;
@@ -1104,7 +1099,7 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
                 for (int n = 0; n < NNUC; ++n)
                     atomicAdd(&tile[((n * g.nz + cz) * t.ty + cy) * t.tx + cx], (double)A[n]);
             }
-            continue;
+            return;
         }
         const double ix = floor(fx - 0.5), iy = floor(fy - 0.5), iz = floor(fz - 0.5);
         const float wx = (float)(fx - 0.5 - ix), wy = (float)(fy - 0.5 - iy);
@@ -1119,10 +1114,35 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
             for (int n = 0; n < NNUC; ++n)
                 atomicAdd(&tile[((n * g.nz + cz) * t.ty + cy) * t.tx + cx], (double)(A[n] * w));
         }
+    };
+    // A crowded tile (the one holding the source) gets tens of thousands of
+    // records: each thread takes kTileBatch of them at a time and issues
+    // their index and record loads before using any, so that the dependent
+    // gathers of one record overlap those of the others.
+    const float4* rec_k = rec + (long long)k * rec_stride;
+    for (long long j0 = threadIdx.x; j0 < total; j0 += (long long)kTileBatch * kBlock) {
+        int2 ib[kTileBatch];
+        bool ok[kTileBatch];
+#pragma unroll
+        for (int u = 0; u < kTileBatch; ++u) {
+            const long long j = j0 + (long long)u * kBlock;
+            ok[u] = j < total;
+            ib[u] = ok[u] ? t.idx[j < e0 ? lo0 + j
+                                  : j < e1 ? lo1 + (j - e0)
+                                  : j < e2 ? lo2 + (j - e1) : lo3 + (j - e2)]
+                          : make_int2(0, 0);
+        }
+        float4 rr[kTileBatch];
+#pragma unroll
+        for (int u = 0; u < kTileBatch; ++u)
+            rr[u] = ok[u] ? rec_k[(uint32_t)ib[u].x] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+        for (int u = 0; u < kTileBatch; ++u)
+            if (ok[u]) add_record(rr[u], ib[u].y);
     }
     __syncthreads();
     for (int c = threadIdx.x; c < NNUC * ncell; c += kBlock) {
-        const int xx = c % t.tx, yy = (c / t.tx) % t.ty, zn = c / (t.tx * t.ty);
+        const int xx = c & (t.tx - 1), yy = (c >> t.lx) & (t.ty - 1), zn = c >> (t.lx + t.ly);
         if (xx < wx_n && yy < wy_n)
             out[((long long)zn * g.ny + ya + yy) * g.nx + xa + xx] = (float)(tile[c] * t.inv_vol);
     }
@@ -1136,8 +1156,8 @@ __global__ __launch_bounds__(kBlock) void fill_f64(double* p, long long n)
 
 __global__ __launch_bounds__(kBlock) void fill_u32(uint32_t* p, long long n)
 {
-    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) p[i] = 0u;
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) p[i] = 0u;
 }
 
 __global__ __launch_bounds__(kBlock) void to_f32(const double* __restrict__ src, float* dst,
@@ -2002,7 +2022,7 @@ int plan_records(const lpm_schedule* sch, const lpm_physics* ph, const lpm_grid*
     r.o_cur = r.o_off + align256(8 * (size_t)r.nb);
     r.o_bsum = r.o_cur + align256(8 * (size_t)r.nb);
     r.o_idx = r.o_bsum + align256(8 * (size_t)r.nscan);
-    r.bytes = r.o_idx + align256(4 * (size_t)r.cap);
+    r.bytes = r.o_idx + align256(8 * (size_t)r.cap);
     r.tile_lds = column * r.tx * r.ty;
     *rp = r;
     return LPM_OK;
@@ -2058,20 +2078,26 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     g.i_hi = first_local_born_at_or_after(sch, (long long)rec_step0 + (long long)(n_rec - 1) * rec_every + 1);
     char* w = (char*)work;
     lpm::TileConst t;
-    t.tx = rp.tx; t.ty = rp.ty; t.ntx = rp.ntx; t.nty = rp.nty; t.nbx = rp.nbx; t.nby = rp.nby;
+    t.tx = rp.tx; t.ty = rp.ty;
+    t.lx = __builtin_ctz((unsigned)rp.tx); t.ly = __builtin_ctz((unsigned)rp.ty);
+    t.ntx = rp.ntx; t.nty = rp.nty; t.nbx = rp.nbx; t.nby = rp.nby;
     t.nbk = rp.nbk;
     t.off = (unsigned long long*)(w + rp.o_off);
     t.cur = (unsigned long long*)(w + rp.o_cur);
     t.bsum = (unsigned long long*)(w + rp.o_bsum);
-    t.idx = (uint32_t*)(w + rp.o_idx);
+    t.idx = (int2*)(w + rp.o_idx);
     t.cap = rp.cap;
     t.out = out;
     t.inv_vol = 1.0 / (grid->density ? grid->dx * grid->dy * grid->dz : 1.0);
     hipStream_t s = (hipStream_t)stream;
     const dim3 bs(lpm::kBlock);
-    // counts start at zero (a fill kernel: the call may be captured in a graph)
-    hipLaunchKernelGGL(lpm::fill_u32, dim3(blocks_for(2 * rp.nb)), bs, 0, s, (uint32_t*)t.cur,
-                       2 * rp.nb);
+    // the output and the counts start at zero (fill kernels: the call may be
+    // captured in a graph)
+    const long long n_out = (long long)n_rec * ph->n_nuc * g.cells;
+    hipLaunchKernelGGL(lpm::fill_u32, dim3(std::min(blocks_for(n_out), 16384u)), bs, 0, s,
+                       (uint32_t*)out, n_out);
+    hipLaunchKernelGGL(lpm::fill_u32, dim3(std::min(blocks_for(2 * rp.nb), 16384u)), bs, 0, s,
+                       (uint32_t*)t.cur, 2 * rp.nb);
     const float4* r4 = reinterpret_cast<const float4*>(rec);
     const int* last = reinterpret_cast<const int*>(rec + 4ll * n_rec * rec_stride);
     if (g.i_hi > 0) {
@@ -2088,8 +2114,8 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
                            last, rec_stride, rec_step0, rec_every);
     } else {
         // nothing is born: every bin is empty (off = cur = 0)
-        hipLaunchKernelGGL(lpm::fill_u32, dim3(blocks_for(2 * rp.nb)), bs, 0, s, (uint32_t*)t.off,
-                           2 * rp.nb);
+        hipLaunchKernelGGL(lpm::fill_u32, dim3(std::min(blocks_for(2 * rp.nb), 16384u)), bs, 0, s,
+                           (uint32_t*)t.off, 2 * rp.nb);
     }
     const dim3 tg((unsigned)((long long)rp.ntx * rp.nty), (unsigned)n_rec);
     switch (ph->n_nuc) {
