@@ -2,7 +2,7 @@
 
 The oracle grids the GPU's own recorded float32 positions and masses, so the
 comparison isolates the gridding: binning of records by column tile, the
-per-tile FP64 sums and the conversion.  Grids are chosen to reach every path:
+per-tile FP64 sums and the conversion.  Grids and nuclide sets are chosen to reach every path:
 bins per output step held in LDS and not, tiles of 16 x 4 and of 8 x 2
 columns (tall grids), grids that the tiles do not divide, cloud-in-cell and
 nearest-cell.  Tolerances as in the other parity tests: cloud-in-cell
@@ -40,7 +40,14 @@ GRIDS = [
     ("c1 grid, nearest cell", dict(mode=0)),
     ("37x23x7 small, every tile ragged", dict(nx=37, ny=23, nz=7, dx=700.0, dy=900.0,
                                              dz=150.0, x0=-4000.0, y0=-10000.0)),
+    ("5x3x1 flat, narrower than one tile", dict(nx=5, ny=3, nz=1, dx=3000.0, dy=4000.0,
+                                               dz=2000.0, x0=-2000.0, y0=-6000.0)),
 ]
+
+# nuclide sets (the tile pass is compiled per nuclide count); the last is a
+# parent -> daughter chain (Bateman activities)
+NUCLIDES = [dict(lambdas=(3e-5,)), dict(lambdas=(1e-6, 1e-5, 1e-4)),
+            dict(lambdas=(1e-3, 2.5e-4, 4e-3, 7e-4), chain=1)]
 
 
 def _records(case, every, n_rec):
@@ -59,12 +66,8 @@ def _records(case, every, n_rec):
     return run, rec.cpu().numpy(), out.double().cpu().numpy()
 
 
-@pytest.mark.parametrize("label,kw", GRIDS, ids=[g[0].split(",")[0] + "-" + str(i)
-                                                 for i, g in enumerate(GRIDS)])
-def test_records_gridded_like_oracle(label, kw):
+def _check_against_oracle(c, label):
     import oracle
-    c = synth.c1(n_total=40_000, n_steps=360, s_release=360)
-    c = c.with_(conc_grid=_grid(c.conc_grid, **kw))
     every, n_rec = 60, 6
     run, recs, out = _records(c, every, n_rec)
     assert not np.isnan(out).any()
@@ -96,6 +99,20 @@ def test_records_gridded_like_oracle(label, kw):
             unexplained, nnear = ngp_unexplained(got, ref, (x, y, z), act, c.conc_grid, 1e-3)
             log(label, "step", s, "NGP unexplained %.3e near-face %d" % (unexplained, nnear))
             assert unexplained == 0.0
+
+
+@pytest.mark.parametrize("label,kw", GRIDS, ids=[g[0].split(",")[0] + "-" + str(i)
+                                                 for i, g in enumerate(GRIDS)])
+def test_records_gridded_like_oracle(label, kw):
+    c = synth.c1(n_total=40_000, n_steps=360, s_release=360)
+    _check_against_oracle(c.with_(conc_grid=_grid(c.conc_grid, **kw)), label)
+
+
+@pytest.mark.parametrize("kw", NUCLIDES, ids=["1", "3", "4-chain"])
+def test_records_gridded_like_oracle_nuclides(kw):
+    c = synth.c1(n_total=40_000, n_steps=360, s_release=360)
+    _check_against_oracle(c.with_(physics=synth.replace(c.physics, **kw)),
+                          "nuclides %d" % len(kw["lambdas"]))
 
 
 def test_records_grid_twice_same_buffers():
