@@ -2,10 +2,11 @@
 
 The oracle grids the GPU's own recorded float32 positions and masses, so the
 comparison isolates the gridding: binning of records by column tile, the
-per-tile FP64 sums and the conversion.  Grids and nuclide sets are chosen to reach every path:
-bins per output step held in LDS and not, tiles of 16 x 4 and of 8 x 2
-columns (tall grids), grids that the tiles do not divide, cloud-in-cell and
-nearest-cell.  Tolerances as in the other parity tests: cloud-in-cell
+per-tile FP64 sums and the conversion.  Grids and nuclide sets are chosen
+to reach every path: bins per output step held in LDS and not, tiles of
+16 x 4, 8 x 4 and 8 x 2 columns, grids that the tiles do not divide or that
+are narrower than one tile, one to four nuclides (a decay chain among
+them), cloud-in-cell and nearest-cell.  Tolerances as in the other parity tests: cloud-in-cell
 relative L2 <= 1e-6 (float32 contributions summed in FP64), nearest-cell
 differences only from particles within 1e-3 m of a cell face.
 """
