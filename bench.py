@@ -222,7 +222,7 @@ def adjoint_bench(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
     import torch
     import synth
