@@ -130,3 +130,19 @@ def test_records_grid_twice_same_buffers():
     torch.cuda.synchronize()
     # FP64 sums in another order may round to the neighbouring float
     np.testing.assert_allclose(out.double().cpu().numpy(), out1, rtol=2e-7, atol=0.0)
+
+
+def test_records_of_particles_all_gone_grid_to_zero():
+    """Degenerate: every particle leaves the (1 m wide, bounded) field in its
+    first step, so no record counts; every cell of every output step must
+    still be written, with zero."""
+    c = synth.c0(n_total=5_000, n_steps=180)
+    c = c.with_(field=synth.uniform_field(5.0, 0.0, bounded=True))
+    run, recs, out = _records(c, 60, 3)
+    assert not np.isnan(out).any()
+    assert np.all(out == 0.0)
+    led = run.ledger()[0]
+    # nothing stays airborne: what did not decay in the first step left
+    released, deposited, decayed, exited = led
+    assert deposited == 0.0 and exited > 0.999 * released
+    np.testing.assert_allclose(decayed + exited, released, rtol=1e-6)  # float per-particle terms
