@@ -832,6 +832,7 @@ struct TileConst {
     unsigned long long* cur;  // [n_rec nbk] counts, then end of each bin
     unsigned long long* bsum; // per-block sums of the scan
     int2* idx;                // particle index and birth step of each binned record
+    const int* chunk_end;     // per chunk of kRecChunk ids: the largest `last` in it
     unsigned long long cap;   // entries of idx
     float* out;
     double inv_vol;
@@ -877,11 +878,38 @@ __device__ __forceinline__ int binned_record(const GridConst& g, const TileConst
     return record_bin(g, t, r.x, r.y, r.z);
 }
 
-// Local ids are born in increasing order: a chunk whose first id is born
-// after the output step holds no record of it.
-__device__ __forceinline__ bool chunk_unborn(const GridConst& g, long long i0, int step)
+// A chunk holds no record of an output step when its first id is born after
+// the step (local ids are born in increasing order) or when all of its
+// particles stopped by then.
+__device__ __forceinline__ bool chunk_idle(const GridConst& g, const TileConst& t, long long i0,
+                                           int step)
 {
-    return i0 >= g.i_hi || birth(g.id_base + i0 * g.id_stride, g.s_release, g.n_total) > step;
+    return i0 >= g.i_hi || step >= t.chunk_end[blockIdx.x] ||
+           birth(g.id_base + i0 * g.id_stride, g.s_release, g.n_total) > step;
+}
+
+// Pass 0: the largest `last` of each chunk (one block per chunk).
+__global__ __launch_bounds__(kBlock) void chunk_end_kernel(const int* last, long long i_hi,
+                                                           int* chunk_end)
+{
+    __shared__ int wmax[kBlock / 64];
+    const long long i0 = (long long)blockIdx.x * kRecChunk;
+    int v = INT_MIN;
+#pragma unroll
+    for (int u = 0; u < kRecChunk / kBlock; ++u) {
+        const long long i = i0 + u * kBlock + threadIdx.x;
+        if (i < i_hi) v = max(v, last[i]);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = wmax[0];
+#pragma unroll
+        for (int w = 1; w < kBlock / 64; ++w) m = max(m, wmax[w]);
+        chunk_end[blockIdx.x] = m;
+    }
 }
 
 // Pass 1: records per bin.  LDS: nbk counters when nbk <= kBinLds.
@@ -895,7 +923,7 @@ __global__ __launch_bounds__(kBlock) void bin_count_kernel(const GridConst g, co
     const int k = blockIdx.y;
     const int step = rec_step0 + k * rec_every;
     const long long i0 = (long long)blockIdx.x * kRecChunk;
-    if (chunk_unborn(g, i0, step)) return;
+    if (chunk_idle(g, t, i0, step)) return;
     const float4* rec_k = rec + (long long)k * rec_stride;
     unsigned long long* cnt = t.cur + (long long)k * t.nbk;
     int bin[kRecChunk / kBlock];
@@ -936,7 +964,7 @@ __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(const GridConst g, 
     const int k = blockIdx.y;
     const int step = rec_step0 + k * rec_every;
     const long long i0 = (long long)blockIdx.x * kRecChunk;
-    if (chunk_unborn(g, i0, step)) return;
+    if (chunk_idle(g, t, i0, step)) return;
     const float4* rec_k = rec + (long long)k * rec_stride;
     unsigned long long* cur = t.cur + (long long)k * t.nbk;
     int bin[kRecChunk / kBlock], born[kRecChunk / kBlock];
@@ -1979,7 +2007,8 @@ struct RecordPlan {
     int tx, ty, ntx, nty, nbx, nby;
     long long nbk, nb, nscan;
     unsigned long long cap;        // binned records at most
-    size_t o_off, o_cur, o_bsum, o_idx, bytes;
+    long long nchunk;              // chunks of kRecChunk ids that can hold records
+    size_t o_off, o_cur, o_bsum, o_cend, o_idx, bytes;
     size_t tile_lds;
 };
 
@@ -2021,7 +2050,11 @@ int plan_records(const lpm_schedule* sch, const lpm_physics* ph, const lpm_grid*
     r.o_off = 0;
     r.o_cur = r.o_off + align256(8 * (size_t)r.nb);
     r.o_bsum = r.o_cur + align256(8 * (size_t)r.nb);
-    r.o_idx = r.o_bsum + align256(8 * (size_t)r.nscan);
+    r.nchunk = (first_local_born_at_or_after(
+                    sch, (long long)rec_step0 + (long long)(n_rec > 0 ? n_rec - 1 : 0) * rec_every + 1) +
+                lpm::kRecChunk - 1) / lpm::kRecChunk;
+    r.o_cend = r.o_bsum + align256(8 * (size_t)r.nscan);
+    r.o_idx = r.o_cend + align256(4 * (size_t)r.nchunk);
     r.bytes = r.o_idx + align256(8 * (size_t)r.cap);
     r.tile_lds = column * r.tx * r.ty;
     *rp = r;
@@ -2086,6 +2119,7 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     t.cur = (unsigned long long*)(w + rp.o_cur);
     t.bsum = (unsigned long long*)(w + rp.o_bsum);
     t.idx = (int2*)(w + rp.o_idx);
+    t.chunk_end = (const int*)(w + rp.o_cend);
     t.cap = rp.cap;
     t.out = out;
     t.inv_vol = 1.0 / (grid->density ? grid->dx * grid->dy * grid->dz : 1.0);
@@ -2103,6 +2137,8 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     if (g.i_hi > 0) {
         const dim3 nb((unsigned)((g.i_hi + lpm::kRecChunk - 1) / lpm::kRecChunk), (unsigned)n_rec);
         const bool lds = rp.nbk <= lpm::kBinLds;
+        hipLaunchKernelGGL(lpm::chunk_end_kernel, dim3((unsigned)rp.nchunk), bs, 0, s, last,
+                           g.i_hi, (int*)(w + rp.o_cend));
         hipLaunchKernelGGL(lpm::bin_count_kernel, nb, bs, lds ? 4 * rp.nbk : 0, s, g, t, r4, last,
                            rec_stride, rec_step0, rec_every);
         hipLaunchKernelGGL(lpm::scan_sums_kernel, dim3((unsigned)rp.nscan), bs, 0, s, t.cur, rp.nb,

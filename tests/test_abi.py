@@ -205,7 +205,9 @@ def test_record_gridding_workspace_and_rejections(args):
     assert q(grid, 4, 5, 2) == L.LPM_OK
     nb = 2 * 13 * 51 * 4
     a256 = lambda b: (b + 255) // 256 * 256
-    assert n.value == 2 * a256(8 * nb) + a256(8 * ((nb + 2047) // 2048)) + a256(8 * 1500)
+    # (plus one int per chunk of 2048 particle ids: 1 chunk)
+    assert n.value == (2 * a256(8 * nb) + a256(8 * ((nb + 2047) // 2048)) + a256(4 * 1)
+                       + a256(8 * 1500))
     tall = L.Grid.from_buffer_copy(grid)
     tall.nz = 3073  # 2 nuclides x 3073 levels x 8 B: one column exceeds the block's LDS
     assert q(tall, 0, 1, 1) == L.LPM_EINVAL
