@@ -825,6 +825,9 @@ constexpr int kBinLds = 4096;  // bins per output step held in LDS by the binnin
 struct TileConst {
     int tx, ty;        // tile width and depth in cells (powers of two)
     int lx, ly;        // their base-2 logarithms
+    int ps;            // doubles per level of the LDS tile: tx ty, plus one of padding
+                       // when tx ty > 1 (the same corner of records on different levels
+                       // then falls in different LDS banks)
     int ntx, nty;      // owner tiles
     int nbx, nby;      // bin tiles (nx / tx + 1, ny / ty + 1)
     long long nbk;     // bins per output step: nbx nby 4
@@ -1081,7 +1084,7 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(unsigned long long* 
 }
 
 // Pass 4: one block per (owner tile, output step).  LDS: the tile's cells,
-// double [NNUC][nz][ty][tx].
+// double [NNUC][nz][ps] (ty tx cells per level, padded).
 constexpr int kTileBatch = 4;
 template <int NNUC>
 __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, const TileConst t,
@@ -1110,7 +1113,8 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
     // most tiles hold no record (the plume covers a few per output step):
     // their cells were cleared by one coalesced fill before this pass
     if (total == 0) return;
-    for (int c = threadIdx.x; c < NNUC * ncell; c += kBlock) tile[c] = 0.0;
+    const int ps = t.ps;
+    for (int c = threadIdx.x; c < NNUC * g.nz * ps; c += kBlock) tile[c] = 0.0;
     __syncthreads();
     // one record's contributions to the tile's cells
     auto add_record = [&](const float4 r, int b) {
@@ -1125,7 +1129,7 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
             if (cx >= 0 && cx < wx_n && cy >= 0 && cy < wy_n && cz >= 0 && cz < g.nz) {
 #pragma unroll
                 for (int n = 0; n < NNUC; ++n)
-                    atomicAdd(&tile[((n * g.nz + cz) * t.ty + cy) * t.tx + cx], (double)A[n]);
+                    atomicAdd(&tile[(n * g.nz + cz) * ps + cy * t.tx + cx], (double)A[n]);
             }
             return;
         }
@@ -1140,7 +1144,7 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
                             ((c >> 2) ? wz : 1.0f - wz);
 #pragma unroll
             for (int n = 0; n < NNUC; ++n)
-                atomicAdd(&tile[((n * g.nz + cz) * t.ty + cy) * t.tx + cx], (double)(A[n] * w));
+                atomicAdd(&tile[(n * g.nz + cz) * ps + cy * t.tx + cx], (double)(A[n] * w));
         }
     };
     // A crowded tile (the one holding the source) gets tens of thousands of
@@ -1172,7 +1176,8 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
     for (int c = threadIdx.x; c < NNUC * ncell; c += kBlock) {
         const int xx = c & (t.tx - 1), yy = (c >> t.lx) & (t.ty - 1), zn = c >> (t.lx + t.ly);
         if (xx < wx_n && yy < wy_n)
-            out[((long long)zn * g.ny + ya + yy) * g.nx + xa + xx] = (float)(tile[c] * t.inv_vol);
+            out[((long long)zn * g.ny + ya + yy) * g.nx + xa + xx] =
+                (float)(tile[zn * ps + (c & (t.tx * t.ty - 1))] * t.inv_vol);
     }
 }
 
@@ -2004,7 +2009,7 @@ namespace lpm_host {
 // tile of full height whose cells (double, n_nuc of them each) fit the LDS
 // budget of one block.
 struct RecordPlan {
-    int tx, ty, ntx, nty, nbx, nby;
+    int tx, ty, ps, ntx, nty, nbx, nby;
     long long nbk, nb, nscan;
     unsigned long long cap;        // binned records at most
     long long nchunk;              // chunks of kRecChunk ids that can hold records
@@ -2033,7 +2038,8 @@ int plan_records(const lpm_schedule* sch, const lpm_physics* ph, const lpm_grid*
     static const int shapes[][2] = {{16, 4}, {8, 4}, {8, 2}, {4, 2}, {2, 2}, {2, 1}, {1, 1}};
     int pick = -1;
     for (int j = 0; j < 7 && pick < 0; ++j)
-        if (column * shapes[j][0] * shapes[j][1] <= kTileLds) pick = j;
+        if (column * (shapes[j][0] * shapes[j][1] + (shapes[j][0] * shapes[j][1] > 1 ? 1 : 0)) <= kTileLds)
+            pick = j;
     if (pick < 0) return fail(LPM_EINVAL, "n_nuc * nz must be at most 6144 to grid records");
     RecordPlan r;
     r.tx = shapes[pick][0]; r.ty = shapes[pick][1];
@@ -2056,7 +2062,8 @@ int plan_records(const lpm_schedule* sch, const lpm_physics* ph, const lpm_grid*
     r.o_cend = r.o_bsum + align256(8 * (size_t)r.nscan);
     r.o_idx = r.o_cend + align256(4 * (size_t)r.nchunk);
     r.bytes = r.o_idx + align256(8 * (size_t)r.cap);
-    r.tile_lds = column * r.tx * r.ty;
+    r.ps = r.tx * r.ty + (r.tx * r.ty > 1 ? 1 : 0);
+    r.tile_lds = column * r.ps;
     *rp = r;
     return LPM_OK;
 }
@@ -2113,6 +2120,7 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     lpm::TileConst t;
     t.tx = rp.tx; t.ty = rp.ty;
     t.lx = __builtin_ctz((unsigned)rp.tx); t.ly = __builtin_ctz((unsigned)rp.ty);
+    t.ps = rp.ps;
     t.ntx = rp.ntx; t.nty = rp.nty; t.nbx = rp.nbx; t.nby = rp.nby;
     t.nbk = rp.nbk;
     t.off = (unsigned long long*)(w + rp.o_off);
