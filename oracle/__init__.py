@@ -18,6 +18,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lpm_oracle.c")
 _LIB = os.path.join(_HERE, "liblpm_oracle.so")
+# The test suite's planted-mistake check loads a deliberately broken build of
+# the oracle from this path; it is never set otherwise.
+_LIB_OVERRIDE = os.environ.get("LPM_ORACLE_LIB")
 
 
 def build(force: bool = True) -> str:
@@ -73,9 +76,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = C.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            L = C.CDLL(_LIB)
         P = C.POINTER(Problem)
         dp = C.POINTER(C.c_double)
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),

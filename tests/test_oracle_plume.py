@@ -33,13 +33,21 @@ def chi2_check(M, E, var, count, min_count=20):
     return p, rel, pred, k
 
 
-@pytest.mark.parametrize("n_total,min_count", [(10_000, 5), (200_000, 20)])
-def test_c0_grid_matches_exact_expectation(n_total, min_count):
+# (particles, cells): at 1e4 particles no cell of the 100 x 100 x 50 m grid
+# expects 20 of them, so that case is binned on 400 x 400 x 100 m cells of the
+# same 10 x 10 x 1 km domain (83 cells expect >= 20)
+@pytest.mark.parametrize("n_total,cells", [(10_000, (25, 25, 10, 400.0, 400.0, 100.0)),
+                                           (200_000, None)])
+def test_c0_grid_matches_exact_expectation(n_total, cells):
     case = ngp(synth.c0(n_total=n_total))
+    if cells is not None:
+        nx, ny, nz, dx, dy, dz = cells
+        case = case.with_(conc_grid=synth.replace(case.conc_grid, nx=nx, ny=ny, nz=nz, dx=dx,
+                                                  dy=dy, dz=dz))
     r = oracle.Oracle(case).simulate(snap_steps=[case.n_steps - 1])
     M = r["snaps"][0, 0]
     E, var, count = expected_ngp(case)
-    p, rel, pred, k = chi2_check(M, E, var, count, min_count)
+    p, rel, pred, k = chi2_check(M, E, var, count, min_count=20)
     assert p > 1e-3, (p, k)
     assert rel < 3 * pred, (rel, pred)
 
