@@ -1,47 +1,63 @@
 """Benchmark: forward particle-steps/s of the particle-dispersion hot path on
-one MI355X.
+one MI355X, beside adjoint gradient evaluations/s, the batched ensemble
+against sequential plain runs, and the FP64 oracle on the host cores.
 
-Workload (one benchmark step = one full forward run): 1e6 particles released
-continuously from (0, 0, 50 m) over 6 h at dt = 5 s (4320 time steps), steady
-200 x 200 x 30 wind field (250/250/40 m nodes, power-law profile with four
-seeded Fourier modes of direction), parabolic K_z over a 1000 m mixed layer,
-dry deposition (v_d = 0.002 m/s), wet scavenging (1e-5 1/s) in a seeded
-elliptical rain region, two nuclides (lambda = 1e-6, 1e-5 1/s).  Every step of
-a run: release, particle step (advection, turbulent random walk, reflection,
-decay, dry/wet deposition with the deposition scatter), concentration gridding
-on the 200 x 200 x 30 x 2 cloud-in-cell grid every 60 steps, and the final
-deposition grid.  `value` = active particle-steps per second over the timed
+Headline workload (one benchmark step = one full forward run): 1.6e7
+particles released continuously from (0, 0, 50 m) over the first 6 h of a
+24 h run at dt = 5 s (17280 time steps), 25 hourly 400 x 400 x 40 wind
+fields (250/250/40 m nodes; power-law profile, four seeded Fourier modes of
+direction per hour) interpolated linearly in time, parabolic K_z over a
+1000 m mixed layer, dry deposition (v_d = 0.002 m/s), wet scavenging
+(1e-5 1/s) in a seeded elliptical rain region, two nuclides (lambda = 1e-6,
+1e-5 1/s).  Every step of a run: release, particle step (advection,
+turbulent random walk, reflection, decay, dry/wet deposition with the
+deposition scatter), cloud-in-cell concentration on the 400 x 400 x 40 x 2
+grid every 60 steps (288 output steps), and the final 400 x 400 x 2
+deposition grid.  `value` = particle-steps advanced per second over the timed
 runs (inputs resident in HBM).
 
-Also reported on the same line: gradient evaluations per second of a
-receptor log-misfit with respect to (source height, release rate, wind
-scale, deposition velocity) on the same workload (forward + adjoint), the
-64-scenario batched ensemble against 64 sequential plain runs, and the FP64
-oracle's rate on the host cores.
+Also on the same line: the 1e6-particle 6 h run on one 200 x 200 x 30 field
+("c1"), gradient evaluations per second of a receptor log-misfit on that
+workload ("adjoint"), the 64-scenario ensemble against 64 sequential plain
+runs ("ensemble"), and the oracle's rate on all host cores and on one core
+("cpu_baseline").
 
-    python bench.py [--steps K] [--warmup W] [--spl STEPS_PER_LAUNCH]
+    python bench.py [--steps K] [--warmup W] [--workload c2|c1]
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU issue peak with packed FP32 disabled: 256 CUs x 4 SIMDs x 16 lanes x
-# 2.4 GHz lane-operations per second (the 157.3 TFLOP/s FP32 figure counts a
-# packed two-lane FMA as four flops).
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
-# Lane-cycles of VALU work one particle-step of the method needs (Philox
-# 10 rounds, Box-Muller, trilinear wind, K_z at two heights, move and fold,
-# deposition rates, decay of two nuclides, FP64 ledger sums); derived in the
-# design notes.  Quarter-rate transcendentals and 32-bit multiplies count 4.
-ALG_OPS_PER_PSTEP = 290
-HBM_PEAK = 8.0e12
+HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+# Algorithmic HBM bytes per particle-step: one read and one write of the FP32
+# state x, y, z, m (random numbers come from Philox keys, the birth from the
+# index, the wind from the cache-resident field).
+B_FWD = 32
+# A gradient evaluation: the forward's 32 B, plus storing the recomputed
+# state of each step (16 B) and reading it back in the reverse sweep (16 B).
+B_GRAD = 64
+# VALU issue peak with packed FP32 disabled: 256 CUs x 4 SIMDs, one wave64
+# instruction per SIMD every 4 cycles at 2.4 GHz.
+VALU_WAVE_INSTS_PEAK = 256 * 4 * 2.4e9 / 4
+# Lane operations one particle-step of the method needs, counted by hand
+# (a model, not a measurement; the measured instruction count is in `valu`).
+MODEL_LANE_OPS_PER_PSTEP = 290
+
+WORKLOADS = {
+    "c2": "1.6e7-particle 24 h run, release over the first 6 h, 25 hourly 400x400x40 wind "
+          "fields interpolated in time, dt=5 s, 17280 steps, CIC concentration 400x400x40x2 "
+          "every 60 steps (288 output steps), deposition 400x400x2",
+    "c1": "1e6-particle 6 h continuous point release, 200x200x30 steady gridded wind, "
+          "dt=5 s, 4320 steps, CIC gridding every 60 steps (72 output steps)",
+}
 
 
 def kernel_source_hash() -> str:
@@ -58,36 +74,47 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per step-kernel launch from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy of known size),
-    or None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "c1_1e6_step_kernel_hbm_traffic.md")
+def profile_values(name):
+    """The machine-readable `key: value` lines of a committed profile summary,
+    or None when it is missing or the kernel sources changed since it was
+    taken (its kernel_source_sha256 no longer matches)."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        k, _, v = line.strip().partition(": ")
-        if k in ("step_kernel_hbm_bytes_per_launch", "kernel_source_sha256"):
+        k, sep, v = line.strip().partition(": ")
+        if sep and k and " " not in k:
             vals[k] = v.strip()
     if vals.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    return float(vals["step_kernel_hbm_bytes_per_launch"])
+    return vals
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--spl", type=int, default=0,
-                    help="time steps per step-kernel launch; 0 = the whole run in one launch "
-                         "with the output-step states recorded and gridded afterwards")
-    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--workload", choices=["c2", "c1"], default="c2",
+                    help="headline workload (c2: the 1.6e7-particle 24 h run)")
+    ap.add_argument("--n", type=int, default=0, help="particles (0 = the workload's)")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 1e6-particle 6 h line")
+    ap.add_argument("--c1-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=8,
-                    help="oracle sample: every k-th particle id of the same workload")
-    ap.add_argument("--ensemble-steps", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="target seconds of each oracle leg (all cores, one core)")
+    ap.add_argument("--ensemble-steps", type=int, default=3)
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the 64-scenario batched-vs-sequential comparison")
     ap.add_argument("--adjoint-steps", type=int, default=3,
@@ -100,32 +127,149 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(case, stride):
+def make_case(name, n):
+    import synth
+    if name == "c2":
+        return synth.c2(n_total=n or 16_000_000)
+    return synth.c1(n_total=n or 1_000_000)
+
+
+def forward(case, steps, warmup, copy_mb=0):
+    """Whole forward runs of `case`: release, one step launch over the run
+    with the states after the output steps recorded, the gridding of every
+    output step from the records, the deposition grid.  The step kernel is
+    timed with HIP events on the stream it is launched on."""
+    import torch
+    import paper_0912_3223_amd as L
+    snaps = case.output_steps()
+    assert snaps == list(range(case.out_every - 1, case.n_steps, case.out_every))
+    run = L.DeviceRun(case)
+    stream = torch.cuda.current_stream()
+    rec = run.record_buffer(len(snaps))
+    gbufs = run.grid_buffers(snaps[0], case.out_every, len(snaps))
+    ev = []
+
+    def one_run(timed):
+        run.reset()
+        run.release(0, case.n_steps)
+        if timed:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        run.step_record(0, case.n_steps, snaps[0], case.out_every, len(snaps), rec)
+        if timed:
+            e1.record(stream)
+            ev.append((e0, e1))
+        run.grid_records(rec, snaps[0], case.out_every, len(snaps), gbufs)
+        run.grid_deposition()
+
+    for _ in range(warmup):
+        one_run(False)
+    torch.cuda.synchronize()
+    if copy_mb:
+        n = copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    psteps = run.particle_steps()
+    run.check()
+    ledger = run.ledger()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_run(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert run.particle_steps() == psteps, "runs are not deterministic in their step count"
+    step_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    res = {"psteps": psteps, "ms": (t1 - t0) * 1e3 / steps, "value": psteps * steps / (t1 - t0),
+           "step_ms": statistics.mean(step_ms), "ledger": ledger}
+    del rec, gbufs, run
+    torch.cuda.empty_cache()
+    return res
+
+
+def roofline(fw, profile):
+    """HBM roofline of the step kernel: B_FWD bytes per particle-step over
+    its average launch time (one launch per run)."""
+    achieved = B_FWD * fw["psteps"] / (fw["step_ms"] / 1e3)
+    vals = profile_values(profile)
+    traffic = float(vals["step_kernel_hbm_bytes_per_launch"]) if vals and \
+        "step_kernel_hbm_bytes_per_launch" in vals else None
+    return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK, "traffic": traffic, "kernel": "step_kernel",
+            "bytes_per_particle_step": B_FWD, "particle_steps_per_launch": fw["psteps"],
+            "avg_launch_ms": fw["step_ms"], "launches_per_run": 1,
+            "step_kernel_share": fw["step_ms"] / fw["ms"]}
+
+
+def valu(fw, profile):
+    """VALU figures of the step kernel from a committed counter summary
+    (None while the summary is missing or stale): instructions per
+    particle-step and the share of the VALU issue peak they occupy at the
+    event-timed launch duration."""
+    vals = profile_values(profile)
+    model = {"model_lane_ops_per_particle_step": MODEL_LANE_OPS_PER_PSTEP,
+             "model_frac": MODEL_LANE_OPS_PER_PSTEP * fw["psteps"] / (fw["step_ms"] / 1e3)
+             / (VALU_WAVE_INSTS_PEAK * 64)}
+    if not vals or "sq_insts_valu_per_launch" not in vals:
+        return dict(model, counters=None)
+    insts = float(vals["sq_insts_valu_per_launch"])
+    out = dict(model, counters=profile,
+               wave_insts_per_launch=insts,
+               wave_insts_per_particle_step=insts / fw["psteps"],
+               lane_insts_per_particle_step=64 * insts / fw["psteps"],
+               issue_frac=insts / (fw["step_ms"] / 1e3) / VALU_WAVE_INSTS_PEAK)
+    if "valu_busy_frac" in vals:
+        out["busy_frac_counters"] = float(vals["valu_busy_frac"])
+    return out
+
+
+def cpu_baseline(case, seconds):
+    """The oracle (as it stands) on a bounded sample of the same workload --
+    every k-th particle id, k chosen so that each leg takes about `seconds` --
+    once on all host cores and once on one core."""
     import oracle
-    sub = case.with_(schedule=case.schedule.subset(stride))
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    o = oracle.Oracle(sub)
-    t = time.perf_counter()
-    r = o.simulate(nthreads=threads)
-    dt = time.perf_counter() - t
-    return {"value": r["psteps"] / dt, "unit": "particle-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"every {stride}th particle id of the same 1e6-particle 6 h run "
-                      f"({sub.schedule.local_count} particles, {r['psteps']} particle-steps, "
-                      f"{dt:.1f} s, FP64, {threads} OpenMP threads)"}
+    threads = len(os.sched_getaffinity(0))
+    # particle-steps per id of the full run, from the workload's own count
+    per_id = {"c2": 3800.0, "c1": 540.0}.get(case.name, 1000.0)
+    rate_guess = {1: 1.5e6}
+    legs = {}
+    for nth in (threads, 1):
+        guess = rate_guess.get(nth, 1.5e6 * nth)
+        want = seconds * guess / per_id
+        stride = max(1, int(case.schedule.n_total / max(want, 1.0)))
+        sub = case.with_(schedule=case.schedule.subset(stride))
+        o = oracle.Oracle(sub)
+        t = time.perf_counter()
+        r = o.simulate(nthreads=nth)
+        dt = time.perf_counter() - t
+        legs[nth] = (r["psteps"] / dt, stride, sub.schedule.local_count, r["psteps"], dt)
+    v, stride, n, ps, dt = legs[threads]
+    v1, stride1, n1, ps1, dt1 = legs[1]
+    return {"value": v, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th particle id of the same run ({n} particles, {ps} "
+                      f"particle-steps, {dt:.1f} s, FP64, {threads} OpenMP threads)",
+            "single_core": {"value": v1, "unit": "particle-steps/s", "cores": 1,
+                            "sample": f"every {stride1}th particle id ({n1} particles, {ps1} "
+                                      f"particle-steps, {dt1:.1f} s, one thread)"},
+            "cpu_model": cpu_model()}
 
 
 def ensemble_vs_plain(a):
-    """64 release scenarios of uneven size on the gridded 6 h workload:
-    one persistent ensemble launch per run against 64 sequential plain runs
-    (release + whole-window step each), same particle-steps."""
+    """64 release scenarios of uneven size on the 6 h 200 x 200 x 30 workload:
+    one persistent ensemble launch per run (eager and replayed from a captured
+    graph) against 64 sequential plain runs (release + whole-window step each),
+    same particle-steps."""
     import torch
     import synth
     import paper_0912_3223_amd as L
     base, sources, counts = synth.c3()
     e = L.EnsembleRun(base, sources, counts)
     e.prepare()
-    tune = e.autotune(trial_steps=240)
+    tune = e.autotune(trial_steps=240, reps=3)
     e.run()
     torch.cuda.synchronize()
     ps = e.particle_steps()
@@ -134,13 +278,25 @@ def ensemble_vs_plain(a):
         e.run()
     torch.cuda.synchronize()
     batched = (time.perf_counter() - t0) / a.ensemble_steps
-    tuned = (tune.refill_every, tune.blocks_per_cu, tune.refill_min)
-    L.set_launch()
+    # the same run captured once and replayed
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        e.run()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.ensemble_steps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph = (time.perf_counter() - t0) / a.ensemble_steps
+    assert e.particle_steps() == ps, "graph replay changed the particle-step count"
     runs = []
     for src, n in zip(sources, counts):
         case = base.with_(source=src, schedule=synth.Schedule(n_total=n, s_release=base.n_steps))
         runs.append(L.DeviceRun(case))
-    L.set_launch(*tuned)
+    # sequential plain runs with the same queue schedule (plain launches use 256 threads)
+    tl = tune.launch
+    L.set_launch(tl.refill_every, tl.blocks_per_cu if tl.block == 256 else 0, tl.refill_min)
 
     def sequential():
         for r in runs:
@@ -161,13 +317,16 @@ def ensemble_vs_plain(a):
                         "U(10,200) m, rates U(0.5,2), wind scale U(0.8,1.2), shared 200x200x30 "
                         "field, 4320 steps",
             "particles": int(sum(counts)), "particle_steps": ps, "plain_particle_steps": ps_plain,
-            "batched_ms": batched * 1e3, "sequential_ms": seq * 1e3,
+            "batched_ms": batched * 1e3, "graph_ms": graph * 1e3, "sequential_ms": seq * 1e3,
             "batched_particle_steps_per_s": ps / batched,
+            "graph_particle_steps_per_s": ps / graph,
             "sequential_particle_steps_per_s": ps_plain / seq,
             "speedup_batched_vs_sequential": seq / batched,
-            "autotuned": {"refill_every": tune.refill_every, "refill_min": tune.refill_min,
-                          "blocks_per_cu": tune.blocks_per_cu,
-                          "best_trial_ms": tune.best_ms, "worst_trial_ms": tune.worst_ms}}
+            "speedup_graph_vs_sequential": seq / graph,
+            "autotuned": {"refill_every": tl.refill_every, "refill_min": tl.refill_min,
+                          "blocks_per_cu": tl.blocks_per_cu, "block": tl.block,
+                          "median_trial_ms": tune.best_ms, "worst_trial_ms": tune.worst_ms,
+                          "settings_tried": tune.n_tried, "reps": tune.reps}}
 
 
 def adjoint_bench(a):
@@ -209,6 +368,7 @@ def adjoint_bench(a):
     dt = (time.perf_counter() - t0) / a.adjoint_steps
     back_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
     loss = float(((torch.log(c + eps) - torch.log(o + eps)) ** 2).sum())
+    achieved = B_GRAD * psteps / dt
     return {"workload": "receptor log-misfit gradient in (h, q, s_w, v_d) at theta0 = "
                         "(50 m, 1, 1, 0.002 m/s); 1e6 particles, 4320 steps, 50 ground "
                         "receptors (Gaussian kernel 250 m / 40 m), checkpoints every 60 steps",
@@ -216,122 +376,60 @@ def adjoint_bench(a):
             "adjoint_kernel_ms": back_ms, "forward_ms": dt * 1e3 - back_ms,
             "particle_steps_forward": psteps,
             "adjoint_particle_steps_per_s": psteps / (back_ms / 1e3),
+            "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                         "bytes_per_particle_step": B_GRAD,
+                         "what": "one gradient evaluation (forward + adjoint) per B_GRAD x "
+                                 "forward particle-steps"},
             "loss": loss, "grad": [float(v) for v in g[:4].cpu()]}
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only (no multi-GPU path); "
+                                   "run with --gpus 1"}))
         sys.exit(2)
-    import torch
-    import synth
-    import paper_0912_3223_amd as L
+    import torch  # noqa: F401
+    import paper_0912_3223_amd  # noqa: F401  (fails loudly without liblpm.so)
 
-    case = synth.c1(n_total=a.n)
-    snaps = case.output_steps()
-    assert snaps == list(range(case.out_every - 1, case.n_steps, case.out_every))
-    run = L.DeviceRun(case)
-    stream = torch.cuda.current_stream()
-
-    # step-kernel timing: HIP events on the stream the kernels are launched on
-    ev = []
-
-    rec = run.record_buffer(len(snaps)) if a.spl == 0 else None
-    gbufs = run.grid_buffers(snaps[0], case.out_every, len(snaps)) if a.spl == 0 else None
-
-    def one_run(timed):
-        run.reset()
-        if a.spl == 0:
-            run.release(0, case.n_steps)
-            if timed:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-            run.step_record(0, case.n_steps, snaps[0], case.out_every, len(snaps), rec)
-            if timed:
-                e1.record(stream)
-                ev.append((e0, e1))
-            run.grid_records(rec, snaps[0], case.out_every, len(snaps), gbufs)
-            run.grid_deposition()
-            return
-        for s0, s1 in run.windows(0, case.n_steps, a.spl, snaps):
-            run.release(s0, s1 - s0)
-            if timed:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                run.step(s0, s1 - s0)
-                e1.record(stream)
-                ev.append((e0, e1))
-            else:
-                run.step(s0, s1 - s0)
-            if (s1 - 1) in snaps:
-                run.grid_concentration(s1 - 1)
-        run.grid_deposition()
-
-    for _ in range(a.warmup):
-        one_run(False)
-    torch.cuda.synchronize()
-    if a.copy_calibration_mb:
-        n = a.copy_calibration_mb * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    psteps = run.particle_steps()
-    run.check()
-    ledger = run.ledger()
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        one_run(True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    assert run.particle_steps() == psteps, "runs are not deterministic in their step count"
-
-    ms = (t1 - t0) * 1e3 / a.steps
-    value = psteps * a.steps / (t1 - t0)
-    step_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
-    launches_per_run = len(step_ms) // a.steps
-    step_total_s = sum(step_ms) / 1e3 / a.steps
-    avg_launch_s = sum(step_ms) / 1e3 / len(step_ms)
-    ops_per_launch = ALG_OPS_PER_PSTEP * psteps / launches_per_run
-    achieved = ops_per_launch / avg_launch_s
+    case = make_case(a.workload, a.n)
+    fw = forward(case, a.steps, a.warmup, a.copy_calibration_mb)
+    prof = f"{a.workload}_step_kernel_counters.md"
     out = {
         "metric": "particle-steps/s (forward)",
-        "value": value,
+        "value": fw["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": fw["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "1e6-particle 6 h continuous point release, 200x200x30 steady "
-                               "gridded wind, dt=5 s, 4320 steps, CIC gridding every 60 steps",
+        "config": {"workload": WORKLOADS[a.workload],
                    "particles": case.schedule.n_total, "time_steps": case.n_steps,
-                   "steps_per_launch": a.spl or case.n_steps, "particle_steps_per_run": psteps},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12,
-                     "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
-                     "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": measured_traffic() if a.spl == 0 and a.n == 1_000_000 else None,
-                     "kernel": "step_kernel", "avg_launch_ms": avg_launch_s * 1e3,
-                     "launches_per_run": launches_per_run,
-                     "step_kernel_share": step_total_s / (ms / 1e3)},
-        "ledger_first_nuclide": list(map(float, ledger[0])),
+                   "output_steps": len(case.output_steps()),
+                   "particle_steps_per_run": fw["psteps"]},
+        "roofline": roofline(fw, prof),
+        "valu": valu(fw, prof),
+        "ledger_first_nuclide": list(map(float, fw["ledger"][0])),
     }
+    if a.workload == "c2" and not a.no_c1:
+        c1 = make_case("c1", 0)
+        f1 = forward(c1, a.c1_steps, 1)
+        out["c1"] = {"workload": WORKLOADS["c1"], "value": f1["value"], "unit": "particle-steps/s",
+                     "ms_per_step": f1["ms"], "particle_steps_per_run": f1["psteps"],
+                     "roofline": roofline(f1, "c1_step_kernel_counters.md"),
+                     "valu": valu(f1, "c1_step_kernel_counters.md")}
     if not a.no_adjoint:
         out["adjoint"] = adjoint_bench(a)
     if not a.no_ensemble:
         out["ensemble"] = ensemble_vs_plain(a)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, a.cpu_stride)
+        out["cpu_baseline"] = cpu_baseline(case, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -276,8 +276,10 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0,
                      const lpm_grid* grid, void* work, int64_t work_bytes,
                      float* out, lpm_stream stream);
 
-/* Deposited activity so far on the deposition grid, converted to float and
- * divided by the cell area when dep_grid.density != 0.
+/* Deposited activity so far on the deposition grid (Sec. 2: activity removed
+ * from the particles to the surface by dry and wet deposition; Sec. 3.2:
+ * summed on a rectangular grid), converted to float and divided by the cell
+ * area when dep_grid.density != 0.
  * out: device float [n_nuc][ny][nx], overwritten. */
 int lpm_grid_deposition(const lpm_accum* acc, float* out, lpm_stream stream);
 
@@ -294,17 +296,31 @@ int lpm_check(const lpm_accum* acc, lpm_stream stream);
 /* Message of the calling thread's last failed call ("" if none). */
 const char* lpm_last_error(void);
 
-/* Launch tuning of the step kernels (process-wide): a wave refills idle
- * lanes from the work queue every `refill_every` steps (default 24), and at
- * most `blocks_per_cu` blocks per compute unit are launched (0 = as many as
- * fit).  Results do not depend on either. */
+/* Launch settings of the persistent step kernel.  Results do not depend on
+ * them, only the time does.  A wave refills idle lanes from the work queue
+ * every `refill_every` steps (1 .. 4096), and only once at least
+ * `refill_min` of its 64 lanes are idle or all of them are (1 .. 64; a wave
+ * that waits for nearly all its lanes keeps particles released together in
+ * one wave, whose lanes then take the same branches).  At most
+ * `blocks_per_cu` blocks run per compute unit (0 = as many as fit).  `block`
+ * is the number of threads per block: 128, 256 or 512 for ensemble launches;
+ * plain launches always use 256. */
+typedef struct {
+    int32_t refill_every;
+    int32_t refill_min;
+    int32_t blocks_per_cu;
+    int32_t block;
+} lpm_launch;
+
+/* Launch settings of later plain step launches (lpm_step_particles[_record])
+ * in this process: refill interval, blocks per compute unit and idle lanes
+ * before a refill (defaults 24, 0 and 56).  This setting is the library's
+ * only mutable process-wide state; it is read atomically at each launch, so
+ * a call from another thread affects launches made after it returns.
+ * Ensemble launches carry their own settings in lpm_ensemble. */
 int lpm_set_launch(int32_t refill_every, int32_t blocks_per_cu);
 
-/* lpm_set_launch, and a wave refills only once at least `refill_min` of its
- * 64 lanes are idle (or all of them; default 56: a wave takes new particles
- * only once nearly all its lanes are idle, which keeps particles released
- * together in one wave; lanes that mix particles of different ages take
- * different branches). */
+/* lpm_set_launch with the number of idle lanes before a refill. */
 int lpm_set_launch_ex(int32_t refill_every, int32_t blocks_per_cu, int32_t refill_min);
 
 /* ---------------------------------------------------------------------------
@@ -336,6 +352,9 @@ typedef struct {
     int32_t n_steps;
     int64_t queue_len;   /* particles of all scenarios born before step0 + n_steps */
     int64_t max_release; /* most particles one scenario releases in the window */
+    lpm_launch launch;   /* settings of lpm_step_ensemble: the defaults (24, 56, 0,
+                            256) after lpm_ensemble_prepare, the autotuner's pick
+                            after lpm_autotune_ensemble; the caller may set them */
 } lpm_ensemble;
 
 /* Check the scenarios (n_scen <= LPM_MAX_SCENARIOS, disjoint state ranges
@@ -364,26 +383,28 @@ int lpm_step_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_fi
 
 /* Launch settings picked by lpm_autotune_ensemble. */
 typedef struct {
-    int32_t refill_every;
-    int32_t blocks_per_cu;
-    double best_ms;   /* trial time of the chosen setting */
-    double worst_ms;  /* trial time of the slowest setting */
-    int32_t n_tried;
-    int32_t refill_min;
+    lpm_launch launch; /* the chosen setting (also written to ens->launch) */
+    double best_ms;    /* median trial time of the chosen setting */
+    double worst_ms;   /* median trial time of the slowest setting */
+    int32_t n_tried;   /* settings timed */
+    int32_t reps;      /* timed trials per setting (the median is kept) */
 } lpm_tuning;
 
 /* Autotuner: time the ensemble step over the first `trial_steps` steps of
- * the prepared window for each candidate (queue schedule, i.e. refill
- * interval and idle lanes before a refill, x blocks per compute unit), keep
- * the fastest (installed with lpm_set_launch_ex) and report
- * it.  It runs release and step on the given buffers, so state, dep, ledgers
- * and ctrl must be reset and the particles released again afterwards.
- * Synchronises `stream`. */
-int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens,
+ * the prepared window for each candidate setting -- queue schedule (refill
+ * interval and idle lanes before a refill), threads per block and blocks per
+ * compute unit -- `reps` times each (1 .. 15, after one untimed warm-up), and
+ * keep in ens->launch the first candidate, in a fixed order, whose median
+ * time is within 3 % of the smallest median (settings that time alike are
+ * told apart by the order, so repeated calls pick the same setting; nothing
+ * process-wide changes).  It runs release and step on the given buffers, so
+ * state, dep, ledgers and ctrl must be reset and the particles released
+ * again afterwards.  Synchronises `stream`. */
+int lpm_autotune_ensemble(const lpm_state* st, lpm_ensemble* ens,
                           const lpm_scenario* scen, const lpm_field* fld,
                           const lpm_physics* ph, const lpm_grid* dep_grid, double* dep,
                           double* ledgers, uint32_t* ctrl, int32_t trial_steps,
-                          lpm_tuning* out, lpm_stream stream);
+                          int32_t reps, lpm_tuning* out, lpm_stream stream);
 
 /* Friction velocity and inverse Monin-Obukhov length of the surface layer
  * from the vertical stratification (Sec. 2: u* and L computed iteratively

@@ -79,16 +79,23 @@ class Scenario(C.Structure):
                 ("reserved", C.c_int32), ("offset", C.c_int64)]
 
 
+class Launch(C.Structure):
+    _fields_ = [("refill_every", C.c_int32), ("refill_min", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("block", C.c_int32)]
+
+    def as_tuple(self):
+        return (self.refill_every, self.refill_min, self.blocks_per_cu, self.block)
+
+
 class Ensemble(C.Structure):
     _fields_ = [("table", C.c_void_p), ("n_scen", C.c_int32), ("n_nuc", C.c_int32),
                 ("step0", C.c_int32), ("n_steps", C.c_int32), ("queue_len", C.c_int64),
-                ("max_release", C.c_int64)]
+                ("max_release", C.c_int64), ("launch", Launch)]
 
 
 class Tuning(C.Structure):
-    _fields_ = [("refill_every", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("best_ms", C.c_double), ("worst_ms", C.c_double), ("n_tried", C.c_int32),
-                ("refill_min", C.c_int32)]
+    _fields_ = [("launch", Launch), ("best_ms", C.c_double), ("worst_ms", C.c_double),
+                ("n_tried", C.c_int32), ("reps", C.c_int32)]
 
 
 class Receptors(C.Structure):
@@ -135,7 +142,7 @@ def _load():
                               C.c_void_p, C.c_void_p, C.c_void_p],
         "lpm_autotune_ensemble": [P(State), P(Ensemble), P(Scenario), P(Field), P(Physics),
                                   P(Grid), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
-                                  P(Tuning), C.c_void_p],
+                                  C.c_int32, P(Tuning), C.c_void_p],
         "lpm_receptor_concentration": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                        P(Source), P(Schedule), P(Physics), P(Receptors),
                                        C.c_void_p, C.c_void_p],
@@ -282,12 +289,14 @@ def step_ensemble(st: State, ens: Ensemble, fld: Field, ph: Physics, dep_grid: G
 
 def autotune_ensemble(st: State, ens: Ensemble, scen, fld: Field, ph: Physics, dep_grid: Grid,
                       dep: torch.Tensor, ledgers: torch.Tensor, ctrl: torch.Tensor,
-                      trial_steps: int, stream=None) -> Tuning:
+                      trial_steps: int, reps: int = 3, stream=None) -> Tuning:
+    """Times the candidate launch settings and stores the pick in
+    ``ens.launch`` (the Ensemble passed in is updated)."""
     t = Tuning()
     _rc(_lib.lpm_autotune_ensemble(C.byref(st), C.byref(ens), scen, C.byref(fld), C.byref(ph),
                                    C.byref(dep_grid), C.c_void_p(dep.data_ptr()),
                                    C.c_void_p(ledgers.data_ptr()), C.c_void_p(ctrl.data_ptr()),
-                                   trial_steps, C.byref(t), _stream(stream)))
+                                   trial_steps, reps, C.byref(t), _stream(stream)))
     return t
 
 

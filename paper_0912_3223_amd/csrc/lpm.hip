@@ -32,6 +32,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -40,24 +42,6 @@
 #include "lpm_host.h"
 
 namespace lpm {
-
-// exp(x) - 1 for x <= 0.  Per-step rates times dt are small (|x| < 1e-3 in
-// practice), where the Taylor series of exp to x^4/24 is exact to float
-// rounding (truncation x^5/120); larger |x| use the library expm1f.
-__device__ __forceinline__ float expm1_neg(float x)
-{
-    if (x > -0.0078125f)
-        return x * fmaf(x, fmaf(x, fmaf(x, 1.0f / 24.0f, 1.0f / 6.0f), 0.5f), 1.0f);
-    return expm1f(x);
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 // ---------------------------------------------------------------------------
 // Block-private histogram: an open-addressing hash table of grid cells in LDS
@@ -119,556 +103,6 @@ struct CellTable {
 // run independent particles and never meet at a block barrier, so each wave
 // owns a table; when half of its slots are taken, the wave (which executes in
 // lockstep) moves the table to the global grid and empties it.
-template <int NNUC, int LOG2_SLOTS>
-struct WaveTable {
-    static constexpr int kSlots = 1 << LOG2_SLOTS;
-    static constexpr int kShift = 32 - LOG2_SLOTS;
-    static constexpr int kProbes = 8;
-    int* key;      // [kSlots]: 0 = empty, else cell + 1
-    double* val;   // [NNUC][kSlots]
-    int* used;     // slots taken
-    // A key is scen * plane + cell; scenario scen's grid starts at
-    // scen * NNUC * plane (a plain launch has scen = 0).
-    __device__ static double* at(double* grid, long long plane, int key, int n)
-    {
-        const unsigned sc = (unsigned)key / (unsigned)plane;
-        return grid + (long long)sc * (NNUC - 1) * plane + (long long)n * plane + key;
-    }
-
-    __device__ void init(int lane)
-    {
-        for (int t = lane; t < kSlots; t += 64) {
-            key[t] = 0;
-#pragma unroll
-            for (int n = 0; n < NNUC; ++n) val[n * kSlots + t] = 0.0;
-        }
-        if (lane == 0) {
-            *used = 0;
-            *sn = 0;
-        }
-    }
-
-    __device__ void add(int cell, const float (&v)[NNUC], double* grid, long long plane)
-    {
-        unsigned h = ((unsigned)cell * 2654435761u) >> kShift;
-        for (int probe = 0; probe < kProbes; ++probe) {
-            const int old = atomicCAS(&key[h], 0, cell + 1);
-            if (old == 0 || old == cell + 1) {
-                if (old == 0) atomicAdd(used, 1);
-#pragma unroll
-                for (int n = 0; n < NNUC; ++n)
-                    if (v[n] != 0.0f) atomicAdd(&val[n * kSlots + h], (double)v[n]);
-                return;
-            }
-            h = (h + 1) & (kSlots - 1);
-        }
-#pragma unroll
-        for (int n = 0; n < NNUC; ++n)
-            if (v[n] != 0.0f) atomicAdd(at(grid, plane, cell, n), (double)v[n]);
-    }
-
-    // Called by all lanes of the wave at the same point.
-    __device__ void flush(int lane, double* grid, long long plane)
-    {
-        __builtin_amdgcn_wave_barrier();
-        for (int t = lane; t < kSlots; t += 64) {
-            const int k = atomicExch(&key[t], 0);
-            if (k == 0) continue;
-#pragma unroll
-            for (int n = 0; n < NNUC; ++n) {
-                const double v = atomicExch(&val[n * kSlots + t], 0.0);
-                if (v != 0.0) atomicAdd(at(grid, plane, k - 1, n), v);
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) atomicExch(used, 0);
-        __builtin_amdgcn_wave_barrier();
-    }
-
-    __device__ void flush_if_half_full(int lane, double* grid, long long plane)
-    {
-        // one broadcast LDS read (not 64 same-address atomics)
-        const int u = __hip_atomic_load(used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        if (__builtin_amdgcn_readfirstlane(u) > kSlots / 2) flush(lane, grid, plane);
-    }
-
-    // Staging list in front of the table.  A particle that moves to another
-    // cell quad hands over its quad (origin and the four corner sums) in
-    // whatever lanes happen to do so in that step, a few of the wave's 64:
-    // hashing its corners there would run the probe loops with most lanes
-    // masked off.  Instead the quad is appended to a per-wave list (one
-    // ballot and a prefix count for all of them), and the whole wave expands
-    // the quads into corners and inserts them when the list fills up.
-    static constexpr int kStage = 128;                // quads
-    static constexpr int kDrainAt = kStage - 64;      // room for every lane
-    int* sq;       // [3][kStage]: i0, j0, key base of each quad
-    float* sval;   // [4 NNUC][kStage]: corner sums, corner-major per nuclide
-    int* sn;       // quads staged
-
-    // Called by the active lanes together; lanes with has = false only take
-    // part in the count.  Returns false (nothing staged) when the list is
-    // full, and the caller inserts directly.
-    __device__ bool stage(bool has, int i0, int j0, int kb, const float (&acc)[NNUC][4])
-    {
-        const unsigned long long m = __ballot(has);
-        if (m == 0ull) return true;
-        const int lane = __lane_id();
-        const int cnt = __popcll(m);
-        const int base = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(sn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT));
-        if (base + cnt > kStage) return false;  // never: see the drain points
-        if (has) {
-            const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
-            sq[pos] = i0;
-            sq[kStage + pos] = j0;
-            sq[2 * kStage + pos] = kb;
-#pragma unroll
-            for (int n = 0; n < NNUC; ++n)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) sval[(4 * n + c) * kStage + pos] = acc[n][c];
-        }
-        if (lane == __ffsll((long long)m) - 1)
-            __hip_atomic_store(sn, base + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        return true;
-    }
-
-    // Called by all lanes of the wave at the same point: inserts the staged
-    // quads' corners (ncorner = 1 for nearest-cell deposition) when at least
-    // at_least quads are staged.
-    __device__ bool drain(int lane, double* grid, long long plane, int at_least, int ncorner,
-                          int dnx, int dny)
-    {
-        const int n = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(sn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT));
-        if (n < at_least || n == 0) return false;
-        __builtin_amdgcn_wave_barrier();
-        // lane -> (quad, corner): 64 / ncorner quads per pass
-        const int per = 64 / ncorner;
-        const int c = lane % ncorner;
-        for (int e = lane / ncorner; e < n; e += per) {
-            const int ii = sq[e] + (c & 1), jj = sq[kStage + e] + (c >> 1);
-            if (ii < 0 || jj < 0 || ii >= dnx || jj >= dny) continue;
-            float v[NNUC];
-#pragma unroll
-            for (int q = 0; q < NNUC; ++q) v[q] = sval[(4 * q + c) * kStage + e];
-            add(sq[2 * kStage + e] + jj * dnx + ii, v, grid, plane);
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) __hip_atomic_store(sn, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        __builtin_amdgcn_wave_barrier();
-        return true;
-    }
-};
-
-template <int NNUC>
-using DepTable = WaveTable<NNUC, 7>;
-
-// Per-thread deposition while the particle stays in one grid cell (nearest
-// cell) or above one cell quad (cloud-in-cell): partial sums of the corner
-// weights times the deposited activity, flushed to the wave's table when the
-// cell changes and when the particle stops.
-template <int NNUC>
-struct Dwell {
-    int i0 = INT_MIN, j0 = 0;
-    float acc[NNUC][4];
-
-    int key_base = 0;  // scenario * plane in an ensemble launch
-
-    __device__ void flush(const StepConst& p, DepTable<NNUC>& tab, long long plane)
-    {
-        // A lane stages at most one quad between two drain points of its wave
-        // (the kernel drains whenever 64 free entries are not left), so the
-        // list cannot overflow; if it ever did, the error word says so.
-        const bool any = i0 != INT_MIN;
-        if (!tab.stage(any, i0, j0, key_base, acc) && any)
-            atomicOr(p.ctrl + LPM_CTRL_ERR, 2u);
-        i0 = INT_MIN;
-    }
-
-    // Deposited activities d[n] (already scaled) at (x, y).  The cell index
-    // and weights are formed in double precision: 50 km from the grid origin a
-    // float coordinate difference alone would perturb them by ~1e-5.
-    __device__ void add(const StepConst& p, DepTable<NNUC>& tab, long long plane, float x,
-                        float y, const float (&d)[NNUC])
-    {
-        const double fx = ((double)x - p.dx0) * p.dinv_dx;
-        const double fy = ((double)y - p.dy0) * p.dinv_dy;
-        const double sh = p.dmode == 0 ? 0.0 : 0.5;
-        const double ix = floor(fx - sh), iy = floor(fy - sh);
-        // the cell (quad) must touch the grid; false for NaN
-        if (!(ix >= -1.0 && iy >= -1.0 && ix < (double)p.dnx && iy < (double)p.dny)) return;
-        const int ci = (int)ix, cj = (int)iy;
-        if (ci != i0 || cj != j0) {
-            flush(p, tab, plane);
-            i0 = ci;
-            j0 = cj;
-#pragma unroll
-            for (int n = 0; n < NNUC; ++n)
-                acc[n][0] = acc[n][1] = acc[n][2] = acc[n][3] = 0.0f;
-        }
-        if (p.dmode == 0) {
-#pragma unroll
-            for (int n = 0; n < NNUC; ++n) acc[n][0] += d[n];
-            return;
-        }
-        const float wx = (float)(fx - sh - ix), wy = (float)(fy - sh - iy);
-        const float w00 = (1.0f - wx) * (1.0f - wy), w10 = wx * (1.0f - wy);
-        const float w01 = (1.0f - wx) * wy, w11 = wx * wy;
-#pragma unroll
-        for (int n = 0; n < NNUC; ++n) {
-            acc[n][0] = fmaf(d[n], w00, acc[n][0]);
-            acc[n][1] = fmaf(d[n], w10, acc[n][1]);
-            acc[n][2] = fmaf(d[n], w01, acc[n][2]);
-            acc[n][3] = fmaf(d[n], w11, acc[n][3]);
-        }
-    }
-};
-
-// Per-lane ledger partials: deposited, decayed, exited per nuclide, the
-// particle-steps, and (general kernels, KZ == 4) the ingrowth of each nuclide
-// of a decay chain, booked into its "released" entry.
-template <int NNUC, int KZ>
-struct Ledger {
-    static constexpr int kSize = 3 * NNUC + 1 + (KZ == 4 ? NNUC : 0);
-    __device__ static constexpr int offset(int q)
-    {
-        return q < 3 * NNUC ? (q / 3) * 4 + 1 + q % 3
-                            : (q == 3 * NNUC ? LPM_LEDGER_PSTEPS : (q - 3 * NNUC - 1) * 4);
-    }
-};
-
-// ---------------------------------------------------------------------------
-// One time step of one particle (Sec. 3.2 main loop; Eqs. 1-3).  Returns 1
-// when the particle left the area, 2 when it became non-finite, 3 when it was
-// removed by stochastic deposition, else 0.  KZ == 4 is the general kernel:
-// K_z kind at run time (including Eq. 3 with stability), decay chains and
-// stochastic deposition.
-// ---------------------------------------------------------------------------
-template <int NCOMP, bool TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS>
-__device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
-                                       DepTable<NNUC>& tab, long long plane, uint32_t gid,
-                                       int b, int s, float& x, float& y, float& z, float& m,
-                                       double (&led)[(Ledger<NNUC, KZ>::kSize)], Dwell<NNUC>& dw)
-{
-    const float age = (float)(s - b) * p.dt;
-    // wind sample, random numbers, diffusivity, move and fold
-    float xn, yn, zn;
-    motion<NCOMP, TIME, LEVELS, KZ, !ENS>(p, sv.wscale, sv.key1, gid, s, x, y, z, xn, yn, zn);
-    // decay factors at the start of the step
-    float D[NNUC];
-#pragma unroll
-    for (int n = 0; n < NNUC; ++n) D[n] = __builtin_amdgcn_exp2f(-p.lam_l2e[n] * age);
-    // deposition rate at the new position (Sec. 2)
-    const float k = DEP ? deposition_rate(p, sv.dry_c1, sv.dry_c2, xn, yn, zn) : 0.0f;
-    float mn = k > 0.0f ? m * __builtin_amdgcn_exp2f(-1.4426950408889634f * k * p.dt) : m;
-    // decay and deposition of each nuclide's activity this step
-    float dsum[NNUC];
-    bool removed = false;
-    if constexpr (KZ == 4) {
-        // Over the step nuclide n spends S_n activity-seconds in the air
-        // (activity times surviving mass, integrated): k S_n deposits,
-        // lambda_n S_n decays and lambda_{n+1} S_n grows into the daughter of
-        // a chain.  With stochastic deposition the particle stays whole and is
-        // removed at the end of the step with probability 1 - exp(-k dt).
-        const float kk = p.dep_mode ? 0.0f : k;
-        if (p.dep_mode) {
-            mn = m;
-            if (k > 0.0f)
-                removed = removal_uniform<!ENS>(gid, (uint32_t)s, p.key0, sv.key1) <=
-                          -expm1_neg(-k * p.dt);
-        }
-        float DG[NNUC];
-#pragma unroll
-        for (int j = 0; j < NNUC; ++j) {
-            const float r = p.lam[j] + kk;
-            DG[j] = D[j] * (r > 0.0f ? -expm1_neg(-r * p.dt) * __builtin_amdgcn_rcpf(r) : p.dt);
-        }
-#pragma unroll
-        for (int n = 0; n < NNUC; ++n) {
-            float sa = 0.0f, se = 0.0f;
-#pragma unroll
-            for (int j = 0; j <= n; ++j) {
-                sa = fmaf(p.bc[n][j], DG[j], sa);
-                se = fmaf(p.bc[n][j], D[j] * p.edec[j], se);
-            }
-            const float S = sv.a0 * m * sa;
-            const float dep = removed ? sv.a0 * m * se : kk * S;
-            dsum[n] = dep * p.dscale;
-            led[3 * n + 0] += (double)dep;
-            led[3 * n + 1] += (double)(p.lam[n] * S);
-            if (n + 1 < NNUC && p.chain) led[3 * NNUC + 2 + n] += (double)(p.lam[n + 1] * S);
-        }
-        if (removed) mn = 0.0f;
-    } else {
-#pragma unroll
-    for (int n = 0; n < NNUC; ++n) {
-        const float A = sv.a0 * m * D[n];
-        if constexpr (DEP) {
-            // loss of activity this step, split by the rates (no branch on
-            // k: lanes with and without deposition share the wave)
-            const float r = p.lam[n] + k;
-            const float loss = -A * expm1_neg(-r * p.dt);
-            const float dep = k > 0.0f ? loss * (k * __builtin_amdgcn_rcpf(r)) : 0.0f;
-            dsum[n] = dep * p.dscale;
-            led[3 * n + 0] += (double)dep;
-            led[3 * n + 1] += (double)(loss - dep);
-        } else {
-            dsum[n] = 0.0f;
-            led[3 * n + 1] += (double)(A * p.cdec[n]);
-        }
-    }
-    }
-    if (DEP && k > 0.0f) dw.add(p, tab, plane, xn, yn, dsum);
-    x = xn;
-    y = yn;
-    z = zn;
-    m = mn;
-    led[3 * NNUC] += 1.0;
-    if (!(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z) &&
-          __builtin_isfinite(m)))
-        return 2;
-    if (removed) return 3;
-    // leaving the simulated area inactivates the particle
-    if (p.bounded && (x < p.X0 || x >= p.X1 || y < p.Y0 || y >= p.Y1)) {
-#pragma unroll
-        for (int n = 0; n < NNUC; ++n) {
-            float se = D[n] * p.edec[n];
-            if constexpr (KZ == 4) {
-                se = 0.0f;
-#pragma unroll
-                for (int j = 0; j <= n; ++j) se = fmaf(p.bc[n][j], D[j] * p.edec[j], se);
-            }
-            led[3 * n + 2] += (double)(sv.a0 * m * se);
-        }
-        m = 0.0f;
-        return 1;
-    }
-    return 0;
-}
-
-// Adds one lane's ledger partials into a ledger slot (ensemble launches,
-// where lanes may hold different scenarios).
-template <int NNUC, int KZ>
-__device__ __forceinline__ void lane_ledger(double (&led)[(Ledger<NNUC, KZ>::kSize)], double* slot)
-{
-#pragma unroll
-    for (int q = 0; q < Ledger<NNUC, KZ>::kSize; ++q) {
-        if (led[q] != 0.0) atomicAdd(slot + Ledger<NNUC, KZ>::offset(q), led[q]);
-        led[q] = 0.0;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Persistent step kernel.  The grid is sized to the resident capacity; every
-// lane takes particles from a queue of work indices (one atomic per wave and
-// refill) and carries each through the window, so a lane whose particle
-// leaves the area or stops picks up the next one.  Lanes of a wave therefore
-// hold particles at different steps; what they do per step is exactly one
-// call of advance().  In an ensemble launch (ENS) the queue runs over the
-// particles of all scenarios, each lane looks up its particle's scenario, and
-// deposition and ledger go to that scenario's accumulators.
-// ---------------------------------------------------------------------------
-// Blocks per CU the compiler must fit: the lighter variants are held to 128
-// VGPRs (4 waves per SIMD), which beats the 3 waves the register allocation
-// picks by itself even where it spills a few registers (1e6-particle run:
-// 7.3 vs 7.8 ms; 64-scenario ensemble: 94 vs 103 ms); heavier variants keep
-// the default.
-template <int NCOMP, bool TIME, int NNUC, int KZ, bool DEP, bool ENS>
-constexpr int step_min_blocks()
-{
-    return (NCOMP == 3) + TIME + DEP + (NNUC >= 3) + (KZ == 4) <= 1 ? 4 : 1;
-}
-
-template <int NCOMP, bool TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS>
-__global__ __launch_bounds__(kBlock, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP, ENS>())) void step_kernel(const StepConst pk)
-{
-    constexpr int kWaves = kBlock / 64;
-    // The launch constants live in LDS: kept in SGPRs across the persistent
-    // loop they outnumber the scalar registers and spill to VGPR lanes.
-    __shared__ StepConst pc;
-    __shared__ long long scen_qbase[ENS ? LPM_MAX_SCENARIOS + 1 : 1];
-    if (threadIdx.x < sizeof(StepConst) / 4)
-        reinterpret_cast<uint32_t*>(&pc)[threadIdx.x] = reinterpret_cast<const uint32_t*>(&pk)[threadIdx.x];
-    if constexpr (ENS) {
-        for (int c = threadIdx.x; c <= pk.n_scen; c += kBlock)
-            scen_qbase[c] = c < pk.n_scen ? pk.scen[c].qbase : pk.i_hi;
-    }
-    __syncthreads();
-    const StepConst& p = pc;
-    __shared__ int tab_key[kWaves][DepTable<NNUC>::kSlots];
-    __shared__ double tab_val[kWaves][NNUC * DepTable<NNUC>::kSlots];
-    __shared__ int tab_used[kWaves];
-    __shared__ int stage_key[kWaves][DEP ? 3 * DepTable<NNUC>::kStage : 1];
-    __shared__ float stage_val[kWaves][DEP ? 4 * NNUC * DepTable<NNUC>::kStage : 1];
-    __shared__ int stage_n[kWaves];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    DepTable<NNUC> tab{tab_key[wv], tab_val[wv], &tab_used[wv], stage_key[wv], stage_val[wv],
-                       &stage_n[wv]};
-    const long long plane = (long long)p.dnx * p.dny;
-    if constexpr (DEP) tab.init(lane);
-    __builtin_amdgcn_wave_barrier();
-
-    unsigned long long* queue = reinterpret_cast<unsigned long long*>(p.ctrl + LPM_CTRL_QUEUE);
-    float4* rec4 = reinterpret_cast<float4*>(p.rec);
-    int* rec_exit = reinterpret_cast<int*>(p.rec + 4ll * p.n_rec * p.rec_stride);
-    const int slot_index = blockIdx.x % LPM_LEDGER_SLOTS;
-
-    using LG = Ledger<NNUC, KZ>;
-    double led[LG::kSize];
-#pragma unroll
-    for (int q = 0; q < LG::kSize; ++q) led[q] = 0.0;
-
-    SrcVals sv{p.a0, p.wscale, p.dry_c1, p.dry_c2, p.key1, 0};
-    int led_scen = 0;  // scenario the ledger partials belong to
-    bool have = false, drained = false;
-    long long i = 0;
-    uint32_t gid = 0;
-    int b = 0, s = 0, krec = 0, next_rec = INT_MAX;
-    float x = 0.0f, y = 0.0f, z = 0.0f, m = 0.0f;
-    Dwell<NNUC> dw;
-
-    while (true) {
-        // hand the next queue entries to the lanes without a particle
-        while (!drained) {
-            const unsigned long long need = __ballot(!have);
-            // refill once enough lanes idle (keeps the lanes of a wave on
-            // particles released together, whose wind stencils overlap), or
-            // when the whole wave is idle
-            const int idle = __popcll(need);
-            if (need == 0ull || (idle < p.refill_min && need != __ballot(true))) break;
-            const int leader = __ffsll((long long)need) - 1;
-            const int cnt = __popcll(need);
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(queue, (unsigned long long)cnt);
-            base = __shfl(base, leader, 64);
-            if (base + (unsigned long long)cnt >= (unsigned long long)p.i_hi) drained = true;
-            if (!have) {
-                const int rank = __popcll(need & ((1ull << lane) - 1ull));
-                const long long q = (long long)(base + (unsigned long long)rank);
-                if (q < p.i_hi) {
-                    long long g;
-                    if constexpr (ENS) {
-                        // scenario of work index q: last c with qbase[c] <= q
-                        int lo = 0, hi = p.n_scen;
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (scen_qbase[mid] <= q) lo = mid; else hi = mid;
-                        }
-                        const DevScen& ds = p.scen[lo];
-                        if (lo != led_scen) {
-                            lane_ledger<NNUC, KZ>(led, p.ledger + ((long long)led_scen * LPM_LEDGER_SLOTS + slot_index) * LPM_LEDGER_STRIDE);
-                            led_scen = lo;
-                        }
-                        sv = SrcVals{ds.a0, ds.wscale, ds.dry_c1, ds.dry_c2, ds.key1, lo};
-                        // the lane's dwell outlives its particle; its sums go
-                        // to the scenario they were made in
-                        if constexpr (DEP)
-                            if ((int)(lo * plane) != dw.key_base) dw.flush(p, tab, plane);
-                        dw.key_base = (int)(lo * plane);
-                        g = q - ds.qbase;                  // local id of the scenario
-                        b = (int)birth(g, ds.s_release, ds.n_total);
-                        i = ds.offset + g;                 // element in the state arrays
-                    } else {
-                        i = q;
-                        g = p.id_base + q * p.id_stride;
-                        b = (int)birth(g, p.s_release, p.n_total);
-                    }
-                    gid = (uint32_t)g;
-                    m = as_global(p.M)[i];
-                    if (m > 0.0f) {
-                        x = as_global(p.X)[i];
-                        y = as_global(p.Y)[i];
-                        z = as_global(p.Z)[i];
-                        s = b > p.step0 ? b : p.step0;
-                        krec = s <= p.rec_step0 ? 0
-                                                : (s - p.rec_step0 + p.rec_every - 1) / p.rec_every;
-                        next_rec = krec < p.n_rec ? p.rec_step0 + krec * p.rec_every : INT_MAX;
-                        have = true;
-                    } else if (p.n_rec > 0) {
-                        as_global(rec_exit)[i] = INT_MIN;  // inactive before this window
-                    }
-                }
-            }
-        }
-        // refills may have staged a quad per lane (ensembles: scenario change)
-        if constexpr (DEP && ENS) {
-            if (tab.drain(lane, p.dep, plane, DepTable<NNUC>::kDrainAt, p.dmode == 0 ? 1 : 4,
-                          p.dnx, p.dny))
-                tab.flush_if_half_full(lane, p.dep, plane);
-        }
-        if (!__any(have)) break;
-        for (int j = 0; j < p.refill_every; ++j) {
-            if (have) {
-                const int st = advance<NCOMP, TIME, LEVELS, NNUC, KZ, DEP, ENS>(
-                    p, sv, tab, plane, gid, b, s, x, y, z, m, led, dw);
-                if (s == next_rec) {  // state after an output step, for gridding later
-                    typedef float quad __attribute__((ext_vector_type(4)));
-                    as_global(reinterpret_cast<quad*>(rec4))[(long long)krec * p.rec_stride + i] =
-                        quad{x, y, z, m};
-                    ++krec;
-                    next_rec = krec < p.n_rec ? p.rec_step0 + krec * p.rec_every : INT_MAX;
-                }
-                ++s;
-                if (st != 0 || s >= p.step_end) {
-                    // (the lane's dwell stays: deposits are keyed by cell, and
-                    // the lane's next particle or the kernel's end flushes it)
-                    as_global(p.X)[i] = x;
-                    as_global(p.Y)[i] = y;
-                    as_global(p.Z)[i] = z;
-                    as_global(p.M)[i] = m;
-                    if (p.n_rec > 0) as_global(rec_exit)[i] = st != 0 ? s - 1 : INT_MAX;
-                    if (st == 2) atomicOr(p.ctrl + LPM_CTRL_ERR, 1u);
-                    have = false;
-                }
-            }
-            if constexpr (DEP) {
-                // a drain fills the table: move it out before it overflows
-                if (tab.drain(lane, p.dep, plane, DepTable<NNUC>::kDrainAt,
-                              p.dmode == 0 ? 1 : 4, p.dnx, p.dny))
-                    tab.flush_if_half_full(lane, p.dep, plane);
-            }
-        }
-    }
-    if constexpr (DEP) {
-        dw.flush(p, tab, plane);  // every lane: its last particle's sums
-        tab.drain(lane, p.dep, plane, 1, p.dmode == 0 ? 1 : 4, p.dnx, p.dny);
-        tab.flush(lane, p.dep, plane);
-    }
-
-    // ledger slot: [nuclide][released, deposited, decayed, exited], steps
-    constexpr int NV = LG::kSize;
-    if constexpr (ENS) {
-        // lanes of a wave usually finish in one scenario: one atomic per entry
-        const int s0 = __shfl(led_scen, 0, 64);
-        double* slot = p.ledger + ((long long)led_scen * LPM_LEDGER_SLOTS + slot_index) * LPM_LEDGER_STRIDE;
-        if (__all(led_scen == s0)) {
-#pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                const double v = wave_sum(led[q]);
-                if (lane == 0 && v != 0.0) atomicAdd(slot + LG::offset(q), v);
-            }
-        } else {
-            lane_ledger<NNUC, KZ>(led, slot);
-        }
-        return;
-    }
-    double* slot = p.ledger + (long long)slot_index * LPM_LEDGER_STRIDE;
-    __shared__ double part[kWaves][NV];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        const double v = wave_sum(led[q]);
-        if (lane == 0) part[wv][q] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < NV) {
-        double v = 0.0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) v += part[w][threadIdx.x];
-        const int q = threadIdx.x;
-        if (v != 0.0) atomicAdd(slot + LG::offset(q), v);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Release (Sec. 2: particles released from the point source every step).
 // ---------------------------------------------------------------------------
@@ -686,26 +120,6 @@ __global__ __launch_bounds__(kBlock) void release_kernel(float* X, float* Y, flo
         M[i] = 1.0f;
     }
     if (blockIdx.x == 0 && threadIdx.x < n_nuc) atomicAdd(ledger + threadIdx.x * 4, released);
-}
-
-// Release of every scenario of an ensemble window: blockIdx.y = scenario.
-__global__ __launch_bounds__(kBlock) void release_ensemble_kernel(float* X, float* Y, float* Z,
-                                                                  float* M, const DevScen* scen,
-                                                                  double* ledgers, int n_nuc)
-{
-    const DevScen& d = scen[blockIdx.y];
-    const long long l = d.lo + (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (l < d.hi) {
-        const long long i = d.offset + l;
-        X[i] = d.xs;
-        Y[i] = d.ys;
-        Z[i] = d.h;
-        M[i] = 1.0f;
-    }
-    if (blockIdx.x == 0 && threadIdx.x < n_nuc && d.hi > d.lo)
-        atomicAdd(ledgers + (long long)blockIdx.y * LPM_LEDGER_SLOTS * LPM_LEDGER_STRIDE +
-                      threadIdx.x * 4,
-                  d.released);
 }
 
 // ---------------------------------------------------------------------------
@@ -820,7 +234,10 @@ __global__ __launch_bounds__(kBlock) void conc_kernel(const GridConst g)
 // A record counts if the particle was born by s_k and still active after it
 // and its mass is positive.
 constexpr int kRecChunk = 8 * kBlock;
-constexpr int kBinLds = 4096;  // bins per output step held in LDS by the binning kernels
+// LDS bytes per bin: the counting pass keeps a 32-bit count, the scatter pass
+// a 32-bit rank and a 64-bit base per bin of the output step.
+constexpr int kBinCountLds = 4;
+constexpr int kBinScatterLds = 12;
 
 struct TileConst {
     int tx, ty;        // tile width and depth in cells (powers of two)
@@ -831,6 +248,7 @@ struct TileConst {
     int ntx, nty;      // owner tiles
     int nbx, nby;      // bin tiles (nx / tx + 1, ny / ty + 1)
     long long nbk;     // bins per output step: nbx nby 4
+    int bins_lds;      // 1: the bins of an output step fit one block's LDS (else global atomics)
     unsigned long long* off;  // [n_rec nbk] first index of each bin
     unsigned long long* cur;  // [n_rec nbk] counts, then end of each bin
     unsigned long long* bsum; // per-block sums of the scan
@@ -915,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void chunk_end_kernel(const int* last, long
     }
 }
 
-// Pass 1: records per bin.  LDS: nbk counters when nbk <= kBinLds.
+// Pass 1: records per bin.  LDS: nbk counters when the bins fit (bins_lds).
 __global__ __launch_bounds__(kBlock) void bin_count_kernel(const GridConst g, const TileConst t,
                                                            const float4* rec, const int* last,
                                                            long long rec_stride, int rec_step0,
@@ -937,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void bin_count_kernel(const GridConst g, co
         bin[u] = binned_record(g, t, rec_k, last, i0 + u * kBlock + threadIdx.x, step, b);
         any |= bin[u] >= 0;
     }
-    const bool lds = t.nbk <= kBinLds;
+    const bool lds = t.bins_lds != 0;
     if (!lds) {
 #pragma unroll
         for (int u = 0; u < kRecChunk / kBlock; ++u)
@@ -977,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(const GridConst g, 
         bin[u] = binned_record(g, t, rec_k, last, i0 + u * kBlock + threadIdx.x, step, born[u]);
         any |= bin[u] >= 0;
     }
-    const bool lds = t.nbk <= kBinLds;
+    const bool lds = t.bins_lds != 0;
     if (!lds) {
 #pragma unroll
         for (int u = 0; u < kRecChunk / kBlock; ++u)
@@ -1210,11 +628,21 @@ namespace lpm_host {
 
 thread_local char g_msg[kMsgLen] = "";
 
-// Launch tuning of the persistent step kernel (process-wide; set by the
-// autotuner or lpm_set_launch).
-int g_refill_every = 24;
-int g_refill_min = 56;
-int g_blocks_per_cu = 0;  // 0: as many as the device holds
+// Launch settings of plain step launches: the library's only mutable
+// process-wide state (lpm_set_launch), read atomically at each launch.
+std::atomic<int> g_refill_every{24};
+std::atomic<int> g_refill_min{56};
+std::atomic<int> g_blocks_per_cu{0};  // 0: as many as the device holds
+
+lpm_launch plain_launch()
+{
+    lpm_launch l;
+    l.refill_every = g_refill_every.load(std::memory_order_relaxed);
+    l.refill_min = g_refill_min.load(std::memory_order_relaxed);
+    l.blocks_per_cu = g_blocks_per_cu.load(std::memory_order_relaxed);
+    l.block = lpm::kBlock;
+    return l;
+}
 
 int fail(int code, const char* fmt, ...)
 {
@@ -1381,7 +809,7 @@ int lpm_surface_layer(double U, double z_ref, double z0, double dtheta, double T
 
 int lpm_set_launch(int32_t refill_every, int32_t blocks_per_cu)
 {
-    return lpm_set_launch_ex(refill_every, blocks_per_cu, g_refill_min);
+    return lpm_set_launch_ex(refill_every, blocks_per_cu, g_refill_min.load());
 }
 
 int lpm_set_launch_ex(int32_t refill_every, int32_t blocks_per_cu, int32_t refill_min)
@@ -1470,11 +898,11 @@ int fill_field(lpm::StepConst& p, const lpm_field* f)
     p.tmaxi = f->nt >= 2 ? f->nt - 2 : 0;
     p.fxmax = (float)(f->nx - 1); p.fymax = (float)(f->ny - 1);
     p.fzmax = (float)(f->nz - 1); p.ftmax = (float)(f->nt - 1);
-    p.fx0 = (float)f->x0; p.fy0 = (float)f->y0;
+    p.fcx = (float)(-f->x0 / f->dx - 0.5); p.fcy = (float)(-f->y0 / f->dy - 0.5);
     p.inv_dx = (float)(1.0 / f->dx); p.inv_dy = (float)(1.0 / f->dy);
     p.inv_dz = f->z_levels ? 0.0f : (float)(1.0 / f->dz);
-    p.ft0 = (float)f->t0;
     p.inv_dtf = f->nt > 1 ? (float)(1.0 / f->dt_field) : 0.0f;
+    p.fct = f->nt > 1 ? (float)(-f->t0 / f->dt_field) : 0.0f;
     p.sj = f->nx * f->ncomp;
     p.sk = f->ny * p.sj;
     p.st = f->nz * p.sk;
@@ -1533,7 +961,6 @@ void fill_physics(lpm::StepConst& p, const lpm_physics* ph)
         const double lam = ph->lambda[n];
         p.lam[n] = (float)lam;
         p.lam_l2e[n] = (float)(lam * 1.4426950408889634);
-        p.cdec[n] = (float)(-expm1(-lam * dt));
         p.edec[n] = (float)exp(-lam * dt);
     }
     p.inv_L = ph->kz_kind == 3 ? (float)ph->inv_L : 0.0f;
@@ -1571,101 +998,87 @@ void activity_coefficients(const lpm_physics* ph, double bc[4][4])
 void fill_depgrid(lpm::StepConst& p, const lpm_grid& dg)
 {
     p.dnx = dg.nx; p.dny = dg.ny; p.dmode = dg.mode;
-    p.dx0 = dg.x0; p.dy0 = dg.y0;
-    p.dinv_dx = 1.0 / dg.dx; p.dinv_dy = 1.0 / dg.dy;
+    const double sh = dg.mode == 0 ? 0.0 : 0.5;
+    p.d_cx = (float)(-dg.x0 / dg.dx - sh); p.d_cy = (float)(-dg.y0 / dg.dy - sh);
+    p.d_inv_dx = (float)(1.0 / dg.dx); p.d_inv_dy = (float)(1.0 / dg.dy);
+    p.d_fnx = (float)dg.nx; p.d_fny = (float)dg.ny;
     p.dscale = dg.density ? (float)(1.0 / (dg.dx * dg.dy)) : 1.0f;
 }
 
-// Blocks of one persistent launch: at most what the device holds at once.
-template <typename K>
-unsigned resident_blocks(K kernel, unsigned wanted)
+// Device attributes, read once per device (the device a call runs on is the
+// current one).  A race between two first readers stores the same value.
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_dev_cus[kMaxDevices];
+std::atomic<int> g_dev_lds[kMaxDevices];
+
+int current_device()
 {
-    static int per_cu = -1;  // one cache per kernel instance
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    static int cus_dev = -1, cus = 0;
-    if (cus_dev != dev) {
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            cus = 0;  // one block per CU-less device: the launch still drains its queue
-        cus_dev = dev;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+    return dev;
+}
+
+int device_cus()
+{
+    const int dev = current_device();
+    int v = g_dev_cus[dev].load(std::memory_order_relaxed);
+    if (v <= 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1)
+            v = 1;  // one block per CU-less device: a persistent launch still drains its queue
+        g_dev_cus[dev].store(v, std::memory_order_relaxed);
     }
-    if (per_cu < 0) {
-        int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, lpm::kBlock, 0) != hipSuccess || n < 1)
-            n = 1;
-        per_cu = n;
+    return v;
+}
+
+int device_lds()
+{
+    const int dev = current_device();
+    int v = g_dev_lds[dev].load(std::memory_order_relaxed);
+    if (v <= 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+            v < 65536)
+            v = 65536;
+        g_dev_lds[dev].store(v, std::memory_order_relaxed);
     }
-    const int use = g_blocks_per_cu > 0 && g_blocks_per_cu < per_cu ? g_blocks_per_cu : per_cu;
-    const unsigned cap = (unsigned)(use * (cus > 0 ? cus : 1));
+    return v;
+}
+
+// Occupancy (blocks per CU) of each (kernel, block size, device), cached:
+// every variant has its own register and LDS footprint.
+struct OccEntry {
+    const void* kernel;
+    int block, dev, per_cu;
+};
+std::mutex g_occ_mutex;
+std::vector<OccEntry> g_occ;
+
+int occupancy(const void* kernel, int block)
+{
+    const int dev = current_device();
+    {
+        std::lock_guard<std::mutex> lock(g_occ_mutex);
+        for (const OccEntry& e : g_occ)
+            if (e.kernel == kernel && e.block == block && e.dev == dev) return e.per_cu;
+    }
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, 0) != hipSuccess || n < 1)
+        n = 1;
+    try {
+        std::lock_guard<std::mutex> lock(g_occ_mutex);
+        g_occ.push_back({kernel, block, dev, n});
+    } catch (...) {
+        // out of host memory: the value is still right, only not cached
+    }
+    return n;
+}
+
+unsigned resident_blocks(const void* kernel, int block, int blocks_per_cu, unsigned wanted)
+{
+    const int per_cu = occupancy(kernel, block);
+    const int use = blocks_per_cu > 0 && blocks_per_cu < per_cu ? blocks_per_cu : per_cu;
+    const unsigned cap = (unsigned)use * (unsigned)device_cus();
     return wanted < cap ? wanted : cap;
 }
-
-template <int NCOMP, bool TIME, bool LEV, int NNUC, int KZ, bool ENS = false>
-void launch_step_dep(bool dep, unsigned nb, hipStream_t s, const lpm::StepConst& p)
-{
-    if (dep) {
-        auto k = lpm::step_kernel<NCOMP, TIME, LEV, NNUC, KZ, true, ENS>;
-        hipLaunchKernelGGL(k, dim3(resident_blocks(k, nb)), dim3(lpm::kBlock), 0, s, p);
-    } else {
-        auto k = lpm::step_kernel<NCOMP, TIME, LEV, NNUC, KZ, false, ENS>;
-        hipLaunchKernelGGL(k, dim3(resident_blocks(k, nb)), dim3(lpm::kBlock), 0, s, p);
-    }
-}
-
-// Ensemble variants: two or three wind components, steady or hourly fields,
-// uniform levels, one or two nuclides.
-template <int NCOMP, bool TIME>
-void launch_ensemble(int nnuc, int kz, bool dep, unsigned nb, hipStream_t s, const lpm::StepConst& p)
-{
-    if (nnuc == 1) {
-        switch (kz) {
-        case 0: launch_step_dep<NCOMP, TIME, false, 1, 0, true>(dep, nb, s, p); break;
-        case 1: launch_step_dep<NCOMP, TIME, false, 1, 1, true>(dep, nb, s, p); break;
-        default: launch_step_dep<NCOMP, TIME, false, 1, 2, true>(dep, nb, s, p); break;
-        }
-    } else {
-        switch (kz) {
-        case 0: launch_step_dep<NCOMP, TIME, false, 2, 0, true>(dep, nb, s, p); break;
-        case 1: launch_step_dep<NCOMP, TIME, false, 2, 1, true>(dep, nb, s, p); break;
-        default: launch_step_dep<NCOMP, TIME, false, 2, 2, true>(dep, nb, s, p); break;
-        }
-    }
-}
-
-template <int NCOMP, bool TIME, bool LEV, int NNUC>
-void launch_step_kz(int kz, bool dep, unsigned nb, hipStream_t s, const lpm::StepConst& p)
-{
-    switch (kz) {
-    case 0: launch_step_dep<NCOMP, TIME, LEV, NNUC, 0>(dep, nb, s, p); break;
-    case 1: launch_step_dep<NCOMP, TIME, LEV, NNUC, 1>(dep, nb, s, p); break;
-    case 2: launch_step_dep<NCOMP, TIME, LEV, NNUC, 2>(dep, nb, s, p); break;
-    default: {  // general kernel (Eq. 3 stability, chains, stochastic deposition)
-        auto k = lpm::step_kernel<NCOMP, TIME, LEV, NNUC, 4, true, false>;
-        hipLaunchKernelGGL(k, dim3(resident_blocks(k, nb)), dim3(lpm::kBlock), 0, s, p);
-        break;
-    }
-    }
-}
-
-template <int NCOMP, bool TIME, bool LEV>
-void launch_step_n(int nnuc, int kz, bool dep, unsigned nb, hipStream_t s, const lpm::StepConst& p)
-{
-    switch (nnuc) {
-    case 1: launch_step_kz<NCOMP, TIME, LEV, 1>(kz, dep, nb, s, p); break;
-    case 2: launch_step_kz<NCOMP, TIME, LEV, 2>(kz, dep, nb, s, p); break;
-    case 3: launch_step_kz<NCOMP, TIME, LEV, 3>(kz, dep, nb, s, p); break;
-    default: launch_step_kz<NCOMP, TIME, LEV, 4>(kz, dep, nb, s, p); break;
-    }
-}
-
-template <int NCOMP, bool TIME>
-void launch_step_lev(bool lev, int nnuc, int kz, bool dep, unsigned nb, hipStream_t s,
-                     const lpm::StepConst& p)
-{
-    if (lev) launch_step_n<NCOMP, TIME, true>(nnuc, kz, dep, nb, s, p);
-    else launch_step_n<NCOMP, TIME, false>(nnuc, kz, dep, nb, s, p);
-}
-
 }  // namespace lpm_host
 using namespace lpm_host;
 
@@ -1696,8 +1109,9 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
     lpm::StepConst p;
     memset(&p, 0, sizeof p);
     if ((rc = fill_field(p, fld))) return rc;
-    p.refill_every = g_refill_every;
-    p.refill_min = g_refill_min;
+    const lpm_launch lc = plain_launch();
+    p.refill_every = lc.refill_every;
+    p.refill_min = lc.refill_min;
     p.rec = n_rec > 0 ? rec : nullptr;
     p.rec_stride = rec_stride;
     p.rec_step0 = rec_step0;
@@ -1726,12 +1140,13 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
     // the general kernel (K_z kind at run time) serves the paper-literal variants
     const int kz = (ph->chain || ph->dep_mode || ph->kz_kind == 3) ? 4 : ph->kz_kind;
     const bool lev = fld->z_levels != nullptr;
+    const int bpc = lc.blocks_per_cu;
     if (fld->ncomp == 2) {
-        if (time) launch_step_lev<2, true>(lev, ph->n_nuc, kz, dep, nb, s, p);
-        else launch_step_lev<2, false>(lev, ph->n_nuc, kz, dep, nb, s, p);
+        if (time) launch_plain<2, true>(lev, ph->n_nuc, kz, dep, nb, s, p, bpc);
+        else launch_plain<2, false>(lev, ph->n_nuc, kz, dep, nb, s, p, bpc);
     } else {
-        if (time) launch_step_lev<3, true>(lev, ph->n_nuc, kz, dep, nb, s, p);
-        else launch_step_lev<3, false>(lev, ph->n_nuc, kz, dep, nb, s, p);
+        if (time) launch_plain<3, true>(lev, ph->n_nuc, kz, dep, nb, s, p, bpc);
+        else launch_plain<3, false>(lev, ph->n_nuc, kz, dep, nb, s, p, bpc);
     }
     return hip_status("lpm_step_particles");
 }
@@ -1753,218 +1168,17 @@ int lpm_step_particles_record(const lpm_state* st, const lpm_source* src,
                      rec_stride, stream);
 }
 
-static_assert(sizeof(lpm::DevScen) <= LPM_SCENARIO_BYTES, "scenario table entry too large");
+}  // extern "C"
 
-int lpm_ensemble_prepare(const lpm_scenario* scen, int32_t n_scen, const lpm_state* st,
-                         const lpm_physics* ph, int32_t step0, int32_t n_steps, void* table,
-                         int64_t table_bytes, lpm_ensemble* out, lpm_stream stream)
-{
-    g_msg[0] = 0;
-    int rc;
-    if (!scen || !st || !out) return fail(LPM_EINVAL, "null argument");
-    if ((rc = check_physics(ph))) return rc;
-    if (ph->chain || ph->dep_mode || ph->kz_kind == 3)
-        return fail(LPM_EINVAL, "ensemble launches do not take chains, stochastic deposition or kz_kind 3");
-    if (n_scen < 1 || n_scen > LPM_MAX_SCENARIOS)
-        return fail(LPM_EINVAL, "n_scen must be in [1, %d]", LPM_MAX_SCENARIOS);
-    if (!table || ((uintptr_t)table & 15u) || table_bytes < (int64_t)n_scen * LPM_SCENARIO_BYTES)
-        return fail(LPM_EINVAL, "null, misaligned or small scenario table");
-    if (step0 < 0 || n_steps < 1 || (long long)step0 + n_steps > 0x7FFFFFFFll)
-        return fail(LPM_EINVAL, "bad step window");
-    if (!st->x || !st->y || !st->z || !st->m) return fail(LPM_EINVAL, "null state array");
-    std::vector<lpm::DevScen> t(n_scen);
-    std::vector<std::pair<long long, long long>> ranges;
-    long long q = 0, max_rel = 0;
-    for (int c = 0; c < n_scen; ++c) {
-        const lpm_scenario& e = scen[c];
-        if (e.n_total <= 0 || e.n_total > 0xFFFFFFFFll || e.s_release <= 0 || e.offset < 0 ||
-            e.offset + e.n_total > st->capacity)
-            return fail(LPM_EINVAL, "scenario %d: bad size, release steps or state range", c);
-        ranges.push_back({e.offset, e.offset + e.n_total});
-        lpm_schedule sch{e.n_total, e.n_total, 0, 1, e.s_release, 0};
-        lpm::DevScen& d = t[c];
-        memset(&d, 0, sizeof d);
-        d.qbase = q;
-        d.offset = e.offset;
-        d.n_total = e.n_total;
-        d.s_release = e.s_release;
-        d.i_hi = first_local_born_at_or_after(&sch, (long long)step0 + n_steps);
-        d.lo = first_local_born_at_or_after(&sch, step0);
-        d.hi = d.i_hi;
-        const double a0 = a0_of(&e.src, &sch, ph);
-        d.released = a0 * (double)(d.hi - d.lo);
-        d.a0 = (float)a0;
-        d.wscale = (float)e.src.wind_scale;
-        if (e.src.v_d > 0.0 && ph->h_s > 0.0) {
-            d.dry_c1 = (float)(2.0 * e.src.v_d / ph->h_s);
-            d.dry_c2 = (float)(2.0 * e.src.v_d / (ph->h_s * ph->h_s));
-        }
-        d.xs = (float)e.src.xs; d.ys = (float)e.src.ys; d.h = (float)e.src.h;
-        d.key1 = e.src.scenario;
-        q += d.i_hi;
-        if (d.hi - d.lo > max_rel) max_rel = d.hi - d.lo;
-    }
-    std::sort(ranges.begin(), ranges.end());
-    for (size_t k = 1; k < ranges.size(); ++k)
-        if (ranges[k].first < ranges[k - 1].second)
-            return fail(LPM_EINVAL, "scenario state ranges overlap");
-    if (hipMemcpyAsync(table, t.data(), sizeof(lpm::DevScen) * n_scen, hipMemcpyHostToDevice,
-                       (hipStream_t)stream) != hipSuccess ||
-        hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
-        return hip_status("lpm_ensemble_prepare");
-    out->table = table;
-    out->n_scen = n_scen;
-    out->n_nuc = ph->n_nuc;
-    out->step0 = step0;
-    out->n_steps = n_steps;
-    out->queue_len = q;
-    out->max_release = max_rel;
-    return LPM_OK;
-}
+namespace lpm_host {
 
-int lpm_release_ensemble(const lpm_state* st, const lpm_ensemble* ens, double* ledgers,
-                         lpm_stream stream)
+// Shared by lpm_grid_concentration and its no-allocation variant: checks the
+// arguments (except the scratch) and launches clear, scatter and conversion
+// on acc_scratch, which must hold n_nuc * nx * ny * nz doubles.
+int grid_concentration_impl(const lpm_state* st, const lpm_source* src, const lpm_schedule* sch,
+                            const lpm_physics* ph, const lpm_grid* grid, int32_t step,
+                            double* acc_scratch, float* out, lpm_stream stream, const char* what)
 {
-    g_msg[0] = 0;
-    if (!st || !ens || !ens->table || !ledgers) return fail(LPM_EINVAL, "null argument");
-    if (ens->n_scen < 1 || ens->n_scen > LPM_MAX_SCENARIOS || ens->n_nuc < 1 || ens->n_nuc > 4)
-        return fail(LPM_EINVAL, "ensemble not prepared");
-    if (ens->max_release <= 0) return LPM_OK;
-    hipLaunchKernelGGL(lpm::release_ensemble_kernel,
-                       dim3(blocks_for(ens->max_release), (unsigned)ens->n_scen), dim3(lpm::kBlock),
-                       0, (hipStream_t)stream, st->x, st->y, st->z, st->m,
-                       (const lpm::DevScen*)ens->table, ledgers, ens->n_nuc);
-    return hip_status("lpm_release_ensemble");
-}
-
-int lpm_step_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_field* fld,
-                      const lpm_physics* ph, const lpm_grid* dep_grid, double* dep,
-                      double* ledgers, uint32_t* ctrl, lpm_stream stream)
-{
-    g_msg[0] = 0;
-    int rc;
-    if (!st || !ens || !ens->table || !dep || !ledgers || !ctrl) return fail(LPM_EINVAL, "null argument");
-    if (((uintptr_t)dep & 7u) || ((uintptr_t)ledgers & 7u) || ((uintptr_t)ctrl & 7u))
-        return fail(LPM_EINVAL, "misaligned accumulator");
-    if ((rc = check_physics(ph)) || (rc = check_grid(dep_grid, true))) return rc;
-    if (ph->n_nuc != ens->n_nuc) return fail(LPM_EINVAL, "physics and ensemble n_nuc differ");
-    if (ph->n_nuc > 2) return fail(LPM_EINVAL, "ensemble launches support one or two nuclides");
-    if (ph->chain || ph->dep_mode || ph->kz_kind == 3)
-        return fail(LPM_EINVAL, "ensemble launches do not take chains, stochastic deposition or kz_kind 3");
-    if ((double)dep_grid->nx * dep_grid->ny * ens->n_scen >= 2147483647.0)
-        return fail(LPM_EINVAL, "scenarios x deposition cells must stay below 2^31 - 1");
-    if (fld && fld->z_levels) return fail(LPM_EINVAL, "ensemble launches need uniform levels");
-    lpm::StepConst p;
-    memset(&p, 0, sizeof p);
-    if ((rc = fill_field(p, fld))) return rc;
-    fill_physics(p, ph);
-    fill_depgrid(p, *dep_grid);
-    p.refill_every = g_refill_every;
-    p.refill_min = g_refill_min;
-    p.rec_every = 1;
-    p.X = st->x; p.Y = st->y; p.Z = st->z; p.M = st->m;
-    p.step0 = ens->step0;
-    p.step_end = ens->step0 + ens->n_steps;
-    p.i_hi = ens->queue_len;
-    p.scen = (const lpm::DevScen*)ens->table;
-    p.n_scen = ens->n_scen;
-    p.dep = dep; p.ledger = ledgers; p.ctrl = ctrl;
-    if (p.i_hi <= 0) return LPM_OK;
-    // wet deposition, or dry deposition of any scenario (v_d is per scenario
-    // and only known to the device table here), selects the depositing variant
-    const bool dep_any = p.L0 > 0.0f || ph->h_s > 0.0;
-    hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(lpm::fill_u32, dim3(1), dim3(lpm::kBlock), 0, s, ctrl + LPM_CTRL_QUEUE, 2ll);
-    const unsigned nb = blocks_for(p.i_hi);
-    const int kz = ph->kz_kind;
-    if (fld->ncomp == 2) {
-        if (fld->nt > 1) launch_ensemble<2, true>(ph->n_nuc, kz, dep_any, nb, s, p);
-        else launch_ensemble<2, false>(ph->n_nuc, kz, dep_any, nb, s, p);
-    } else {
-        if (fld->nt > 1) launch_ensemble<3, true>(ph->n_nuc, kz, dep_any, nb, s, p);
-        else launch_ensemble<3, false>(ph->n_nuc, kz, dep_any, nb, s, p);
-    }
-    return hip_status("lpm_step_ensemble");
-}
-
-int lpm_autotune_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_scenario* scen,
-                          const lpm_field* fld, const lpm_physics* ph, const lpm_grid* dep_grid,
-                          double* dep, double* ledgers, uint32_t* ctrl, int32_t trial_steps,
-                          lpm_tuning* out, lpm_stream stream)
-{
-    g_msg[0] = 0;
-    if (!st || !ens || !scen || !out) return fail(LPM_EINVAL, "null argument");
-    if (trial_steps < 1 || trial_steps > ens->n_steps) return fail(LPM_EINVAL, "bad trial_steps");
-    hipStream_t s = (hipStream_t)stream;
-    // queue schedules (refill interval, idle lanes before a refill) x blocks
-    // per compute unit
-    const int refills[][2] = {{1, 1}, {4, 1}, {16, 32}, {16, 64}, {24, 56}};
-    const int occupancy[] = {0, 3, 2};
-    lpm_ensemble trial;
-    int rc = lpm_ensemble_prepare(scen, ens->n_scen, st, ph, ens->step0, trial_steps, ens->table,
-                                  (int64_t)ens->n_scen * LPM_SCENARIO_BYTES, &trial, stream);
-    if (rc) return rc;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return hip_status("lpm_autotune_ensemble");
-    const int keep_refill = g_refill_every, keep_min = g_refill_min, keep_bpc = g_blocks_per_cu;
-    double best = 1e300, worst = 0.0;
-    int best_r = keep_refill, best_m = keep_min, best_o = keep_bpc, tried = 0;
-    for (const auto& r : refills) {
-        for (int o : occupancy) {
-            g_refill_every = r[0];
-            g_refill_min = r[1];
-            g_blocks_per_cu = o;
-            for (int rep = 0; rep < 2; ++rep) {  // first repetition warms up
-                if ((rc = lpm_release_ensemble(st, &trial, ledgers, stream))) break;
-                if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(LPM_EHIP, "lpm_autotune_ensemble: hipEventRecord failed"); break; }
-                if ((rc = lpm_step_ensemble(st, &trial, fld, ph, dep_grid, dep, ledgers, ctrl, stream))) break;
-                if (hipEventRecord(e1, s) != hipSuccess) { rc = fail(LPM_EHIP, "lpm_autotune_ensemble: hipEventRecord failed"); break; }
-            }
-            if (rc) break;
-            float ms = 0.0f;
-            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                rc = hip_status("lpm_autotune_ensemble");
-                break;
-            }
-            ++tried;
-            if (ms < best) { best = ms; best_r = r[0]; best_m = r[1]; best_o = o; }
-            if (ms > worst) worst = ms;
-        }
-        if (rc) break;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    g_refill_every = rc ? keep_refill : best_r;
-    g_refill_min = rc ? keep_min : best_m;
-    g_blocks_per_cu = rc ? keep_bpc : best_o;
-    if (rc) return rc;
-    // restore the caller's window in the table
-    lpm_ensemble again;
-    if ((rc = lpm_ensemble_prepare(scen, ens->n_scen, st, ph, ens->step0, ens->n_steps, ens->table,
-                                   (int64_t)ens->n_scen * LPM_SCENARIO_BYTES, &again, stream)))
-        return rc;
-    out->refill_every = best_r;
-    out->blocks_per_cu = best_o;
-    out->refill_min = best_m;
-    out->best_ms = best;
-    out->worst_ms = worst;
-    out->n_tried = tried;
-    return LPM_OK;
-}
-
-int lpm_grid_concentration(const lpm_state* st, const lpm_source* src, const lpm_schedule* sch,
-                           const lpm_physics* ph, const lpm_grid* grid, int32_t step,
-                           double* acc_scratch, float* out, lpm_stream stream)
-{
-    g_msg[0] = 0;
-    int rc = check_state(st, sch);
-    if (rc) return rc;
-    if (!src) return fail(LPM_EINVAL, "null source");
-    if ((rc = check_physics(ph)) || (rc = check_grid(grid, false))) return rc;
-    if (!acc_scratch || !out || ((uintptr_t)acc_scratch & 7u) || !aligned4(out))
-        return fail(LPM_EINVAL, "null or misaligned grid buffers");
-    if (step < 0) return fail(LPM_EINVAL, "step must be >= 0");
     lpm::GridConst g;
     memset(&g, 0, sizeof g);
     g.X = st->x; g.Y = st->y; g.Z = st->z; g.M = st->m;
@@ -2000,7 +1214,36 @@ int lpm_grid_concentration(const lpm_state* st, const lpm_source* src, const lpm
     }
     hipLaunchKernelGGL(lpm::to_f32, dim3(fb), dim3(lpm::kBlock), 0, s, acc_scratch, out, total,
                        1.0 / vol);
-    return hip_status("lpm_grid_concentration");
+    return hip_status(what);
+}
+
+int check_grid_concentration(const lpm_state* st, const lpm_source* src, const lpm_schedule* sch,
+                             const lpm_physics* ph, const lpm_grid* grid, int32_t step, float* out)
+{
+    int rc = check_state(st, sch);
+    if (rc) return rc;
+    if (!src) return fail(LPM_EINVAL, "null source");
+    if ((rc = check_physics(ph)) || (rc = check_grid(grid, false))) return rc;
+    if (!out || !aligned4(out)) return fail(LPM_EINVAL, "null or misaligned output grid");
+    if (step < 0) return fail(LPM_EINVAL, "step must be >= 0");
+    return LPM_OK;
+}
+
+}  // namespace lpm_host
+
+extern "C" {
+
+int lpm_grid_concentration(const lpm_state* st, const lpm_source* src, const lpm_schedule* sch,
+                           const lpm_physics* ph, const lpm_grid* grid, int32_t step,
+                           double* acc_scratch, float* out, lpm_stream stream)
+{
+    g_msg[0] = 0;
+    int rc = check_grid_concentration(st, src, sch, ph, grid, step, out);
+    if (rc) return rc;
+    if (!acc_scratch || ((uintptr_t)acc_scratch & 7u))
+        return fail(LPM_EINVAL, "null or misaligned grid scratch");
+    return grid_concentration_impl(st, src, sch, ph, grid, step, acc_scratch, out, stream,
+                                   "lpm_grid_concentration");
 }
 
 namespace lpm_host {
@@ -2123,6 +1366,22 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     t.ps = rp.ps;
     t.ntx = rp.ntx; t.nty = rp.nty; t.nbx = rp.nbx; t.nby = rp.nby;
     t.nbk = rp.nbk;
+    // The bins of an output step go to LDS when the scatter pass's rank and
+    // base per bin fit one block's LDS (160 KB on gfx950: up to 13653 bins,
+    // e.g. the 10504 of a 400 x 400 grid in 16 x 4 tiles); beyond that, the
+    // passes count and place records with global atomics.
+    t.bins_lds = rp.nbk * lpm::kBinScatterLds <= (long long)device_lds() ? 1 : 0;
+    if (t.bins_lds && rp.nbk * lpm::kBinScatterLds > 65536) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(lpm::bin_scatter_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(rp.nbk * lpm::kBinScatterLds)) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void*>(lpm::bin_count_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(rp.nbk * lpm::kBinScatterLds)) != hipSuccess) {
+            (void)hipGetLastError();
+            t.bins_lds = 0;
+        }
+    }
     t.off = (unsigned long long*)(w + rp.o_off);
     t.cur = (unsigned long long*)(w + rp.o_cur);
     t.bsum = (unsigned long long*)(w + rp.o_bsum);
@@ -2144,18 +1403,18 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     const int* last = reinterpret_cast<const int*>(rec + 4ll * n_rec * rec_stride);
     if (g.i_hi > 0) {
         const dim3 nb((unsigned)((g.i_hi + lpm::kRecChunk - 1) / lpm::kRecChunk), (unsigned)n_rec);
-        const bool lds = rp.nbk <= lpm::kBinLds;
+        const bool lds = t.bins_lds != 0;
         hipLaunchKernelGGL(lpm::chunk_end_kernel, dim3((unsigned)rp.nchunk), bs, 0, s, last,
                            g.i_hi, (int*)(w + rp.o_cend));
-        hipLaunchKernelGGL(lpm::bin_count_kernel, nb, bs, lds ? 4 * rp.nbk : 0, s, g, t, r4, last,
-                           rec_stride, rec_step0, rec_every);
+        hipLaunchKernelGGL(lpm::bin_count_kernel, nb, bs, lds ? lpm::kBinCountLds * rp.nbk : 0, s,
+                           g, t, r4, last, rec_stride, rec_step0, rec_every);
         hipLaunchKernelGGL(lpm::scan_sums_kernel, dim3((unsigned)rp.nscan), bs, 0, s, t.cur, rp.nb,
                            t.bsum);
         hipLaunchKernelGGL(lpm::scan_bsum_kernel, dim3(1), bs, 0, s, t.bsum, rp.nscan);
         hipLaunchKernelGGL(lpm::scan_apply_kernel, dim3((unsigned)rp.nscan), bs, 0, s, t.cur, t.off,
                            rp.nb, (const unsigned long long*)t.bsum);
-        hipLaunchKernelGGL(lpm::bin_scatter_kernel, nb, bs, lds ? 12 * rp.nbk : 0, s, g, t, r4,
-                           last, rec_stride, rec_step0, rec_every);
+        hipLaunchKernelGGL(lpm::bin_scatter_kernel, nb, bs, lds ? lpm::kBinScatterLds * rp.nbk : 0,
+                           s, g, t, r4, last, rec_stride, rec_step0, rec_every);
     } else {
         // nothing is born: every bin is empty (off = cur = 0)
         hipLaunchKernelGGL(lpm::fill_u32, dim3(std::min(blocks_for(2 * rp.nb), 16384u)), bs, 0, s,

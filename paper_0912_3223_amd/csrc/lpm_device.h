@@ -54,7 +54,9 @@ struct StepConst {
     int nx, ny, nz, nt;
     int imax, jmax, kmax, tmaxi;          // largest lower node index
     float fxmax, fymax, fzmax, ftmax;     // largest fractional node index
-    float fx0, fy0, inv_dx, inv_dy, inv_dz, ft0, inv_dtf;
+    // fractional node index of x: x inv_dx + fcx (fcx = -x0/dx - 1/2, cell-centred
+    // nodes), the same in y; of z: z inv_dz - 1/2; of t: t inv_dtf + fct
+    float fcx, fcy, inv_dx, inv_dy, inv_dz, fct, inv_dtf;
     int di, dj, dk, dt_off;               // float offsets of the upper neighbours
     int sj, sk, st, pad1;                 // float strides of j, k, t
     int bounded;
@@ -67,7 +69,6 @@ struct StepConst {
     float L0, rcx, rcy, r_ca_a, r_sa_a, r_ca_b, r_sa_b, inv_edge;
     float lam[4];                         // decay constants
     float lam_l2e[4];                     // lambda log2(e)
-    float cdec[4];                        // 1 - exp(-lambda dt)
     float edec[4];                        // exp(-lambda dt)
     // recorded states: plane q (x, y, z, m) of record k at rec + (4 k + q) rec_stride
     float* rec;
@@ -87,7 +88,9 @@ struct StepConst {
     double* ledger;
     uint32_t* ctrl;
     int dnx, dny, dmode, pad2;
-    double dx0, dy0, dinv_dx, dinv_dy;
+    // deposition cell (quad) coordinate of x: x d_inv_dx + d_cx, d_cx =
+    // -x0/dx (nearest cell) or -x0/dx - 1/2 (cloud in cell); the same in y
+    float d_cx, d_cy, d_inv_dx, d_inv_dy, d_fnx, d_fny;
     float dscale;
 };
 
@@ -191,9 +194,10 @@ __device__ __forceinline__ float removal_uniform(uint32_t id, uint32_t step, uin
     return lattice_uniform(r[0]);
 }
 
+// v clamped to [lo, hi] (lo <= hi) in one v_med3_f32.
 __device__ __forceinline__ float clampf(float v, float lo, float hi)
 {
-    return fminf(fmaxf(v, lo), hi);
+    return __builtin_amdgcn_fmed3f(v, lo, hi);
 }
 
 __device__ __forceinline__ float lerpf(float a, float b, float w)
@@ -201,11 +205,12 @@ __device__ __forceinline__ float lerpf(float a, float b, float w)
     return fmaf(w, b - a, a);
 }
 
-// Lower node and weight of a coordinate on cell-centred nodes, clamped.
-__device__ __forceinline__ void axis(float pos, float origin, float inv_d, float fmax,
+// Lower node and weight of a coordinate on cell-centred nodes, clamped:
+// fractional index pos inv_d + c (c folds the origin and the half cell).
+__device__ __forceinline__ void axis(float pos, float c, float inv_d, float fmax,
                                      int imax, int& i0, float& w)
 {
-    const float fi = clampf((pos - origin) * inv_d - 0.5f, 0.0f, fmax);
+    const float fi = clampf(fmaf(pos, inv_d, c), 0.0f, fmax);
     i0 = min((int)fi, imax);
     w = fi - (float)i0;
 }
@@ -299,14 +304,14 @@ __device__ __forceinline__ void wind_gather(const StepConst& p, float x, float y
                                             float t, WindTap<NCOMP, TIME>& w)
 {
     int i0, j0, k0;
-    axis(x, p.fx0, p.inv_dx, p.fxmax, p.imax, i0, w.wx);
-    axis(y, p.fy0, p.inv_dy, p.fymax, p.jmax, j0, w.wy);
+    axis(x, p.fcx, p.inv_dx, p.fxmax, p.imax, i0, w.wx);
+    axis(y, p.fcy, p.inv_dy, p.fymax, p.jmax, j0, w.wy);
     if constexpr (LEVELS) levels(p.lev, p.nz, z, k0, w.wz);
-    else axis(z, 0.0f, p.inv_dz, p.fzmax, p.kmax, k0, w.wz);
+    else axis(z, -0.5f, p.inv_dz, p.fzmax, p.kmax, k0, w.wz);
     int base = k0 * p.sk + j0 * p.sj + i0 * NCOMP;
     if constexpr (TIME) {
         // time nodes sit at ft0 + k dt_field (not cell-centred)
-        const float ft = clampf((t - p.ft0) * p.inv_dtf, 0.0f, p.ftmax);
+        const float ft = clampf(fmaf(t, p.inv_dtf, p.fct), 0.0f, p.ftmax);
         const int t0 = min((int)ft, p.tmaxi);
         w.wt = ft - (float)t0;
         base += t0 * p.st;

@@ -170,9 +170,9 @@ __device__ __forceinline__ float wet_rate_grad(const StepConst& p, float x, floa
 }
 
 // Slope of a clamped cell-centred axis: inv_d inside the node range, else 0.
-__device__ __forceinline__ float axis_slope(float pos, float origin, float inv_d, float fmax)
+__device__ __forceinline__ float axis_slope(float pos, float c, float inv_d, float fmax)
 {
-    const float f = fmaf(pos - origin, inv_d, -0.5f);
+    const float f = fmaf(pos, inv_d, c);
     return (f > 0.0f && f < fmax) ? inv_d : 0.0f;
 }
 
@@ -201,8 +201,8 @@ __device__ __forceinline__ void wind_and_grad(const StepConst& p, float x, float
 {
     WindTap<NCOMP, TIME> tap;
     wind_gather<NCOMP, TIME, LEVELS>(p, x, y, z, t, tap);
-    const float sx = axis_slope(x, p.fx0, p.inv_dx, p.fxmax);
-    const float sy = axis_slope(y, p.fy0, p.inv_dy, p.fymax);
+    const float sx = axis_slope(x, p.fcx, p.inv_dx, p.fxmax);
+    const float sy = axis_slope(y, p.fcy, p.inv_dy, p.fymax);
     float sz;
     if constexpr (LEVELS) {
         const gfloat* lev = as_global(p.lev);
@@ -211,7 +211,7 @@ __device__ __forceinline__ void wind_and_grad(const StepConst& p, float x, float
         levels(p.lev, p.nz, z, k0, w);
         sz = (p.nz > 1 && z > lev[0] && z < lev[p.nz - 1]) ? 1.0f / (lev[k0 + 1] - lev[k0]) : 0.0f;
     } else {
-        sz = axis_slope(z, 0.0f, p.inv_dz, p.fzmax);
+        sz = axis_slope(z, -0.5f, p.inv_dz, p.fzmax);
     }
     wind_interp<NCOMP, TIME>(tap, uvw);
     float d[3][3];
@@ -472,15 +472,6 @@ int check_schedule(const lpm_schedule* sch)
     return LPM_OK;
 }
 
-int device_cus()
-{
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 1;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 1;
-    return cus > 0 ? cus : 1;
-}
-
 unsigned adjoint_capacity_blocks(long long n_local)
 {
     const long long cap = (long long)kAdjBlocksPerCu * device_cus();
@@ -491,18 +482,10 @@ unsigned adjoint_capacity_blocks(long long n_local)
 template <int NCOMP, bool TIME, bool LEV, int KZ>
 void launch_adjoint(unsigned nb_cap, hipStream_t s, const lpm::StepConst& p, const lpm::AdjConst& a)
 {
-    static int per_cu = -1;
-    if (per_cu < 0) {
-        int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lpm::adjoint_kernel<NCOMP, TIME, LEV, KZ>,
-                                                         lpm::kBlock, 0) != hipSuccess || n < 1)
-            n = 1;
-        per_cu = n;
-    }
-    const long long fit = (long long)per_cu * device_cus();
-    const unsigned nb = (unsigned)(nb_cap < fit ? nb_cap : fit);
+    auto k = lpm::adjoint_kernel<NCOMP, TIME, LEV, KZ>;
+    const unsigned nb = resident_blocks(reinterpret_cast<const void*>(k), lpm::kBlock, 0, nb_cap);
     lpm::AdjConst aa = a;
-    hipLaunchKernelGGL((lpm::adjoint_kernel<NCOMP, TIME, LEV, KZ>), dim3(nb), dim3(lpm::kBlock), 0, s, p, aa);
+    hipLaunchKernelGGL(k, dim3(nb), dim3(lpm::kBlock), 0, s, p, aa);
 }
 
 template <int NCOMP, bool TIME, bool LEV>

@@ -276,11 +276,18 @@ class EnsembleRun:
         step_ensemble(self.st, self.ens, self.fld, self.ph, self.dgrid, self.dep, self.ledgers,
                       self.ctrl)
 
-    def autotune(self, trial_steps: int):
+    def autotune(self, trial_steps: int, reps: int = 3):
+        """Pick the launch settings of this ensemble (kept in ``self.ens``)."""
         t = autotune_ensemble(self.st, self.ens, self.scen, self.fld, self.ph, self.dgrid,
-                              self.dep, self.ledgers, self.ctrl, trial_steps)
+                              self.dep, self.ledgers, self.ctrl, trial_steps, reps)
         self.reset()
         return t
+
+    def set_launch(self, refill_every=24, refill_min=56, blocks_per_cu=0, block=256):
+        """Launch settings of later ``step`` calls of this ensemble."""
+        L = self.ens.launch
+        L.refill_every, L.refill_min, L.blocks_per_cu, L.block = (refill_every, refill_min,
+                                                                  blocks_per_cu, block)
 
     def run(self):
         self.reset()

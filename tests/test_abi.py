@@ -35,7 +35,7 @@ def test_struct_layout_matches_header(tmp_path):
     structs = {"lpm_state": L.State, "lpm_source": L.Source, "lpm_schedule": L.Schedule,
                "lpm_field": L.Field, "lpm_physics": L.Physics, "lpm_grid": L.Grid,
                "lpm_accum": L.Accum, "lpm_scenario": L.Scenario, "lpm_ensemble": L.Ensemble,
-               "lpm_tuning": L.Tuning, "lpm_receptors": L.Receptors}
+               "lpm_tuning": L.Tuning, "lpm_receptors": L.Receptors, "lpm_launch": L.Launch}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lpm.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

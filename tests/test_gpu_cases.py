@@ -1,8 +1,9 @@
-"""More parity cases of liblpm against the oracle: the full-size 1e6-particle
-workload on sampled particle ids, time-varying 400 x 400 x 40 fields, the
-field/physics variants (three wind components, nonuniform levels, Eq. 3
-exponent, 1-4 nuclides, nearest-cell deposition), and edge cases (empty,
-single and ragged particle counts, non-finite input, determinism, resume)."""
+"""More parity cases of liblpm against the oracle: time-varying 400 x 400 x 40
+fields, the field/physics variants (three wind components, nonuniform levels,
+Eq. 3 exponent, 1-4 nuclides, nearest-cell deposition), and edge cases
+(empty, single and ragged particle counts, non-finite input, determinism,
+resume).  The full-size workloads are in test_gpu_c1_full.py and
+test_gpu_c2_full.py."""
 import numpy as np
 import pytest
 
@@ -18,49 +19,6 @@ def _gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_0912_3223_amd  # noqa: F401
-
-
-def airborne(case, st, step):
-    sch, ph, src = case.schedule, case.physics, case.source
-    g = sch.id_base + np.arange(sch.local_count, dtype=np.int64) * sch.id_stride
-    b = (g * sch.s_release) // sch.n_total
-    a0 = src.q * sch.s_release * ph.dt / sch.n_total
-    alive = (b <= step) & (st["m"] > 0)
-    return np.array([(a0 * st["m"] * np.exp(-lam * (step + 1 - b) * ph.dt))[alive].sum()
-                     for lam in ph.lambdas])
-
-
-def test_full_size_workload_sampled():
-    """The benchmark's workload (1e6 particles, 4320 steps, 60 steps per
-    launch); the oracle recomputes every 997th particle id from its own
-    counters and the GPU ledger closes against the GPU state."""
-    c = synth.c1()
-    g = run_gpu(c, steps_per_launch=60)
-    sub = c.with_(schedule=c.schedule.subset(997, 5))
-    o = run_oracle(sub)
-    gs = {k: v[5::997] for k, v in g["state"].items()}
-    act = (o["state"]["m"] > 0) | (gs["m"] > 0)
-    d = distances(gs, o["state"], act)
-    same_status = np.mean((o["state"]["m"] > 0) == (gs["m"] > 0))
-    log("full-size sampled: %d particles, %d active, mean %.3e p99 %.3e max %.3e, same status %.4f"
-        % (len(act), act.sum(), d.mean(), np.quantile(d, 0.99), d.max(), same_status))
-    assert same_status >= 0.995
-    both = (o["state"]["m"] > 0) & (gs["m"] > 0)
-    db = distances(gs, o["state"], both)
-    assert db.mean() <= 0.05 and np.quantile(db, 0.99) <= 1.0
-    np.testing.assert_allclose(gs["m"][both], o["state"]["m"][both], rtol=1e-4)
-    # conservation at full size: released = airborne + deposited + decayed + exited
-    S = c.n_steps
-    air = airborne(c, g["state"], S - 1)
-    led = g["ledger"]
-    for n in range(2):
-        rel = led[n][0]
-        assert rel == pytest.approx(c.source.q * 4320 * 5.0, rel=1e-12)
-        assert abs(rel - air[n] - led[n][1] - led[n][2] - led[n][3]) <= 1e-6 * rel
-    # the deposition grid holds the deposited activity that landed on it
-    area = c.dep_grid.dx * c.dep_grid.dy
-    on_grid = g["dep"].sum(axis=(1, 2)) * area
-    assert np.all(on_grid <= led[:, 1] * (1 + 1e-5)) and np.all(on_grid >= 0.9 * led[:, 1])
 
 
 def test_time_varying_fields():

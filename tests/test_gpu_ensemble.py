@@ -81,14 +81,38 @@ def test_autotuner_changes_no_result():
     e.run()
     ref = [e.state(c) for c in range(6)]
     t = e.autotune(trial_steps=60)
-    log("autotune: refill %d blocks/cu %d best %.3f ms worst %.3f ms (%d tried)"
-        % (t.refill_every, t.blocks_per_cu, t.best_ms, t.worst_ms, t.n_tried))
-    assert t.n_tried == 15 and t.best_ms <= t.worst_ms  # 5 queue schedules x 3 occupancies
+    log("autotune: refill %d/%d lanes, block %d, blocks/cu %d, median %.3f ms, worst %.3f ms "
+        "(%d tried, %d reps)" % (t.launch.refill_every, t.launch.refill_min, t.launch.block,
+                                 t.launch.blocks_per_cu, t.best_ms, t.worst_ms, t.n_tried, t.reps))
+    # 5 queue schedules x (128: 3, 256: 3, 512: 2 distinct occupancies)
+    assert t.n_tried == 40 and t.reps == 3 and t.best_ms <= t.worst_ms
+    assert e.ens.launch.as_tuple() == t.launch.as_tuple()
+    assert t.launch.block in (128, 256, 512)
     e.run()
     for c in range(6):
         for k in "xyzm":
             np.testing.assert_array_equal(e.state(c)[k], ref[c][k])
-    L.set_launch()
+    # every block size gives the same trajectories
+    for block in (128, 512):
+        e.set_launch(refill_every=16, refill_min=32, blocks_per_cu=0, block=block)
+        e.run()
+        for c in range(6):
+            for k in "xyzm":
+                np.testing.assert_array_equal(e.state(c)[k], ref[c][k], err_msg=f"block {block}")
+
+
+def test_autotuner_pick_repeats():
+    """Two autotuner calls on the same ensemble pick the same setting (near
+    ties are broken by the candidates' fixed order)."""
+    import paper_0912_3223_amd as L
+    base, sources, counts = small_ensemble(n_scen=8, steps=600)
+    e = L.EnsembleRun(base, sources, counts)
+    e.prepare()
+    a = e.autotune(trial_steps=240, reps=5)
+    b = e.autotune(trial_steps=240, reps=5)
+    log("autotune picks %s (%.3f ms) and %s (%.3f ms)"
+        % (a.launch.as_tuple(), a.best_ms, b.launch.as_tuple(), b.best_ms))
+    assert a.launch.as_tuple() == b.launch.as_tuple()
 
 
 def test_graph_capture_replays():
