@@ -126,7 +126,8 @@ typedef struct {
  *     (inv_L >= 0) and (1 - 16 s)^(-1/2) for unstable stratification
  *     (Businger-Dyer forms; inv_L = 1/L, the inverse Monin-Obukhov length,
  *     0 = neutral, which is kind 2; see lpm_surface_layer).
- *  K_z = 0 above H_mix.  The vertical step adds the drift dK_z/dz dt and
+ *  K_z = 0 above H_mix (z > H_mix; at z = H_mix the profile, whose value is
+ *  0 and whose slope is taken from below).  The vertical step adds the drift dK_z/dz dt and
  *  evaluates K_z at z + dK_z/dz dt / 2 clamped to [0, H_mix]; with constant
  *  K_z this is Eq. (2) as printed.
  *  H_lid > 0: z is folded into [0, H_lid]; H_lid <= 0: ground reflection only.

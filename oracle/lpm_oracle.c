@@ -236,7 +236,9 @@ void orc_kz(const orc_problem* P, double z, double* K, double* dK)
     if (P->kz_kind == 0) { *K = P->Kz_const; *dK = 0.0; return; }
     double H = P->H_mix, ku = P->kappa_ustar;
     if (z < 0.0) z = 0.0;
-    if (z >= H) { *K = 0.0; *dK = 0.0; return; }
+    /* zero above the mixed layer; at z = H the profile itself (K = 0, its
+     * slope from below), so that the drift takes a particle at the top down */
+    if (z > H) { *K = 0.0; *dK = 0.0; return; }
     double g = 1.0 - z / H;
     if (P->kz_kind == 1) {
         *K = ku * (z + P->z0) * g;
@@ -700,7 +702,7 @@ static void wind_gradient(const orc_problem* P, double x, double y, double z, do
 /* Second derivative of K_z(z) (zero where K_z is constant or zero). */
 static double kz_second(const orc_problem* P, double z)
 {
-    if (P->kz_kind == 0 || z < 0.0 || z >= P->H_mix) return 0.0;
+    if (P->kz_kind == 0 || z < 0.0 || z > P->H_mix) return 0.0;
     double H = P->H_mix, ku = P->kappa_ustar, g = 1.0 - z / H;
     if (P->kz_kind == 1) return -2.0 * ku / H;
     return ku * (-4.0 * g / H + 2.0 * (z + P->z0) / (H * H));

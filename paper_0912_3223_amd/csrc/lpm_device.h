@@ -347,7 +347,7 @@ __device__ __forceinline__ void kz_stability(const StepConst& p, float z, float&
     const float zc = fmaxf(z, 0.0f);
     const float g = fmaf(-zc, p.inv_Hmix, 1.0f);
     const float zz = zc + p.z0;
-    const bool inside = zc < p.H_mix;
+    const bool inside = zc <= p.H_mix;  // at H_mix: K = 0 and the slope from below
     const float f = p.ku * zz * g * g;                        // Phi = 1 profile
     const float df = p.ku * g * fmaf(-2.0f * zz, p.inv_Hmix, g);
     float rphi, drphi;  // 1/Phi and its slope in z
@@ -384,7 +384,9 @@ __device__ __forceinline__ void kz_profile(const StepConst& p, float z, float& K
         const float zc = fmaxf(z, 0.0f);
         const float g = fmaf(-zc, p.inv_Hmix, 1.0f);
         const float zz = zc + p.z0;
-        const bool inside = zc < p.H_mix;
+        // at H_mix itself the profile (K = 0, slope from below): the drift
+        // takes a particle at the top of the mixed layer back down
+        const bool inside = zc <= p.H_mix;
         if constexpr (KZ == 1) {
             K = inside ? p.ku * zz * g : 0.0f;
             dK = inside ? p.ku * fmaf(-zz, p.inv_Hmix, g) : 0.0f;

@@ -140,7 +140,7 @@ __device__ __forceinline__ float kz_second(const StepConst& p, float z)
         return 0.0f;
     } else {
         const float zc = fmaxf(z, 0.0f);
-        if (!(zc < p.H_mix)) return 0.0f;
+        if (!(zc <= p.H_mix)) return 0.0f;
         if constexpr (KZ == 1) {
             return -2.0f * p.ku * p.inv_Hmix;
         } else {

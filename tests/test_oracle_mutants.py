@@ -50,6 +50,9 @@ MUTANTS = [
      [I + "test_well_mixed_stays_well_mixed"]),
     ("wrong slope sign", "*dK = ku * (g - (z + P->z0) / H);", "*dK = ku * (g + (z + P->z0) / H);",
      [P + "test_kz_profile"]),
+    ("no drift at the top of the mixed layer", "if (z > H) { *K = 0.0; *dK = 0.0; return; }",
+     "if (z >= H) { *K = 0.0; *dK = 0.0; return; }",
+     [P + "test_particles_at_the_top_of_the_mixed_layer_leave_it"]),
     ("drift sign", "double zn = z + w * dt + dKz * dt + xi[2]", "double zn = z + w * dt - dKz * dt + xi[2]",
      [I + "test_well_mixed_stays_well_mixed"]),
     ("deposit and decay shares swapped", "led[n * 4 + 1] += d;\n        led[n * 4 + 2] += P->lambda[n] * S;",

@@ -95,6 +95,11 @@ def test_kz_profile(kind):
         h = 1e-3
         fd = (o.kz(z + h)[0] - o.kz(z - h)[0]) / (2 * h)
         assert o.kz(z)[1] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+    # at the top itself: K = 0 and the profile's slope from below (a zero
+    # slope there would hold a particle at the top with neither drift nor
+    # diffusion)
+    h = 1e-4
+    assert o.kz(H)[1] == pytest.approx((o.kz(H)[0] - o.kz(H - h)[0]) / h, rel=1e-3, abs=1e-6)
     # maximum of the exponent-1 profile at z = (H - z0)/2
     if kind == 1:
         zs = np.linspace(0, H, 100001)
@@ -102,6 +107,21 @@ def test_kz_profile(kind):
         assert K.max() == pytest.approx(ku * (H + z0) ** 2 / (4 * H), rel=1e-4)
     else:
         assert o.kz(H / 3)[0] == pytest.approx(ku * (H / 3 + z0) * (2 / 3) ** 2, rel=1e-14)
+
+
+def test_particles_at_the_top_of_the_mixed_layer_leave_it():
+    """Particles placed exactly at z = H_mix (= the lid) under the parabolic
+    profile drift down (slope -kappa u* (1 + z0/H) there) instead of
+    staying at the top."""
+    c = synth.c1(n_total=200, n_steps=21)
+    ph = synth.replace(c.physics, Kh=0.0, kz_kind=1, Lambda0=0.0)
+    case = c.with_(physics=ph, field=synth.uniform_field(0.0, 0.0),
+                   source=synth.replace(c.source, v_d=0.0),
+                   schedule=synth.replace(c.schedule, s_release=1))
+    n = 200
+    st = {"x": np.zeros(n), "y": np.zeros(n), "z": np.full(n, ph.H_mix), "m": np.ones(n)}
+    r = oracle.Oracle(case).simulate(s_begin=1, s_end=21, state=st)
+    assert np.all(r["state"]["z"] < ph.H_mix - 1e-3)
 
 
 def test_kz_constant():
