@@ -134,33 +134,34 @@ def make_case(name, n):
     return synth.c1(n_total=n or 1_000_000)
 
 
+def window_of(case):
+    """Steps per step launch: the whole run on a steady field; one field
+    interval (an hour, 720 steps) on hourly fields, so that every particle of
+    a launch samples the same two fields and they stay cache-resident."""
+    if case.field.nt > 1:
+        return int(round(case.field.dt_field / case.physics.dt))
+    return case.n_steps
+
+
 def forward(case, steps, warmup, copy_mb=0):
-    """Whole forward runs of `case`: release, one step launch over the run
-    with the states after the output steps recorded, the gridding of every
-    output step from the records, the deposition grid.  The step kernel is
-    timed with HIP events on the stream it is launched on."""
+    """Whole forward runs of `case` as DeviceRun.run_recorded runs them:
+    release, step launches (one per window) that record the states after the
+    output steps, the gridding of those output steps from the records, the
+    deposition grid.  Every step launch is timed with HIP events on the
+    stream it is launched on."""
     import torch
     import paper_0912_3223_amd as L
     snaps = case.output_steps()
     assert snaps == list(range(case.out_every - 1, case.n_steps, case.out_every))
+    window = window_of(case)
     run = L.DeviceRun(case)
-    stream = torch.cuda.current_stream()
-    rec = run.record_buffer(len(snaps))
-    gbufs = run.grid_buffers(snaps[0], case.out_every, len(snaps))
+    cg, nn = case.conc_grid, case.physics.n_nuc
+    out = torch.empty((len(snaps), nn, cg.nz, cg.ny, cg.nx), dtype=torch.float32, device="cuda")
     ev = []
 
     def one_run(timed):
         run.reset()
-        run.release(0, case.n_steps)
-        if timed:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-        run.step_record(0, case.n_steps, snaps[0], case.out_every, len(snaps), rec)
-        if timed:
-            e1.record(stream)
-            ev.append((e0, e1))
-        run.grid_records(rec, snaps[0], case.out_every, len(snaps), gbufs)
+        run.run_recorded(case.out_every, window, out, step_events=ev if timed else None)
         run.grid_deposition()
 
     for _ in range(warmup):
@@ -173,36 +174,42 @@ def forward(case, steps, warmup, copy_mb=0):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    psteps = run.particle_steps()
-    run.check()
-    ledger = run.ledger()
+    psteps = run.particle_steps() if warmup else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         one_run(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    assert run.particle_steps() == psteps, "runs are not deterministic in their step count"
+    run.check()
+    ledger = run.ledger()
+    last = run.particle_steps()
+    assert psteps is None or last == psteps, "runs are not deterministic in their step count"
+    psteps = last
     step_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    launches = len(step_ms) // steps
     res = {"psteps": psteps, "ms": (t1 - t0) * 1e3 / steps, "value": psteps * steps / (t1 - t0),
-           "step_ms": statistics.mean(step_ms), "ledger": ledger}
-    del rec, gbufs, run
+           "step_ms_run": sum(step_ms) / steps, "launches": launches,
+           "launch_ms": statistics.mean(step_ms), "window": window, "ledger": ledger}
+    del out, run
     torch.cuda.empty_cache()
     return res
 
 
 def roofline(fw, profile):
-    """HBM roofline of the step kernel: B_FWD bytes per particle-step over
-    its average launch time (one launch per run)."""
-    achieved = B_FWD * fw["psteps"] / (fw["step_ms"] / 1e3)
+    """HBM roofline of the step kernel: B_FWD bytes per particle-step times
+    the particle-steps of an average launch, over its average duration."""
+    achieved = B_FWD * (fw["psteps"] / fw["launches"]) / (fw["launch_ms"] / 1e3)
     vals = profile_values(profile)
     traffic = float(vals["step_kernel_hbm_bytes_per_launch"]) if vals and \
         "step_kernel_hbm_bytes_per_launch" in vals else None
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK, "traffic": traffic, "kernel": "step_kernel",
-            "bytes_per_particle_step": B_FWD, "particle_steps_per_launch": fw["psteps"],
-            "avg_launch_ms": fw["step_ms"], "launches_per_run": 1,
-            "step_kernel_share": fw["step_ms"] / fw["ms"]}
+            "bytes_per_particle_step": B_FWD,
+            "particle_steps_per_launch": fw["psteps"] / fw["launches"],
+            "avg_launch_ms": fw["launch_ms"], "launches_per_run": fw["launches"],
+            "steps_per_launch": fw["window"],
+            "step_kernel_share": fw["step_ms_run"] / fw["ms"]}
 
 
 def valu(fw, profile):
@@ -211,17 +218,18 @@ def valu(fw, profile):
     particle-step and the share of the VALU issue peak they occupy at the
     event-timed launch duration."""
     vals = profile_values(profile)
+    per_launch = fw["psteps"] / fw["launches"]
     model = {"model_lane_ops_per_particle_step": MODEL_LANE_OPS_PER_PSTEP,
-             "model_frac": MODEL_LANE_OPS_PER_PSTEP * fw["psteps"] / (fw["step_ms"] / 1e3)
+             "model_frac": MODEL_LANE_OPS_PER_PSTEP * per_launch / (fw["launch_ms"] / 1e3)
              / (VALU_WAVE_INSTS_PEAK * 64)}
     if not vals or "sq_insts_valu_per_launch" not in vals:
         return dict(model, counters=None)
     insts = float(vals["sq_insts_valu_per_launch"])
     out = dict(model, counters=profile,
                wave_insts_per_launch=insts,
-               wave_insts_per_particle_step=insts / fw["psteps"],
-               lane_insts_per_particle_step=64 * insts / fw["psteps"],
-               issue_frac=insts / (fw["step_ms"] / 1e3) / VALU_WAVE_INSTS_PEAK)
+               wave_insts_per_particle_step=insts / per_launch,
+               lane_insts_per_particle_step=64 * insts / per_launch,
+               issue_frac=insts / (fw["launch_ms"] / 1e3) / VALU_WAVE_INSTS_PEAK)
     if "valu_busy_frac" in vals:
         out["busy_frac_counters"] = float(vals["valu_busy_frac"])
     return out

