@@ -71,13 +71,23 @@ extern "C" {
 
 typedef void* lpm_stream; /* hipStream_t */
 
-/* Particle state (Sec. 3.2: position and state information per particle). */
+/* Particle state (Sec. 3.2: position and state information per particle).
+ * x_lo, y_lo (optional, both or neither): the rounding residuals of x and y.
+ * Within a step launch each horizontal coordinate is a float plus the
+ * float residual of its running sum (compensated summation), so that
+ * thousands of steps on positions of tens of kilometres do not accumulate
+ * float roundings; with these arrays the residuals also survive between
+ * calls and any split of a run into calls gives the same trajectories.
+ * Without them the residuals are dropped at the end of each call (x and y
+ * stay the correctly rounded positions). */
 typedef struct {
     float* x;
     float* y;
     float* z;
     float* m;
     int64_t capacity; /* elements of each array */
+    float* x_lo;
+    float* y_lo;
 } lpm_state;
 
 /* Point source of one release scenario (Sec. 2).  q: release rate in
@@ -215,8 +225,8 @@ int lpm_release_particles(const lpm_state* st, const lpm_source* src,
  * decayed (share lambda/(lambda + k)) in the ledger; a particle leaving a
  * bounded field books its remaining activity as exited and gets m = 0.
  * A non-finite coordinate or mass sets err and stops that particle.
- * Any n_steps >= 1 is allowed; the same trajectories result for any split
- * of the run into calls. */
+ * Any n_steps >= 1 is allowed; with st->x_lo and st->y_lo the same
+ * trajectories result for any split of the run into calls. */
 int lpm_step_particles(const lpm_state* st, const lpm_source* src,
                        const lpm_schedule* sch, const lpm_field* fld,
                        const lpm_physics* ph, int32_t step0, int32_t n_steps,

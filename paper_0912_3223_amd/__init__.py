@@ -34,7 +34,7 @@ class LpmError(RuntimeError):
 
 class State(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("m", C.c_void_p),
-                ("capacity", C.c_int64)]
+                ("capacity", C.c_int64), ("x_lo", C.c_void_p), ("y_lo", C.c_void_p)]
 
 
 class Source(C.Structure):

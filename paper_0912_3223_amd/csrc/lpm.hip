@@ -107,7 +107,8 @@ struct CellTable {
 // Release (Sec. 2: particles released from the point source every step).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void release_kernel(float* X, float* Y, float* Z,
-                                                         float* M, long long i_lo,
+                                                         float* M, float* XL, float* YL,
+                                                         long long i_lo,
                                                          long long i_hi, float xs, float ys,
                                                          float h, double* ledger,
                                                          int n_nuc, double released)
@@ -118,6 +119,10 @@ __global__ __launch_bounds__(kBlock) void release_kernel(float* X, float* Y, flo
         Y[i] = ys;
         Z[i] = h;
         M[i] = 1.0f;
+        if (XL) {
+            XL[i] = 0.0f;
+            YL[i] = 0.0f;
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x < n_nuc) atomicAdd(ledger + threadIdx.x * 4, released);
 }
@@ -681,6 +686,10 @@ int check_state(const lpm_state* st, const lpm_schedule* sch)
     if (!st->x || !st->y || !st->z || !st->m) return fail(LPM_EINVAL, "null state array");
     if (!aligned4(st->x) || !aligned4(st->y) || !aligned4(st->z) || !aligned4(st->m))
         return fail(LPM_EINVAL, "state arrays must be 4-byte aligned");
+    if ((st->x_lo == nullptr) != (st->y_lo == nullptr))
+        return fail(LPM_EINVAL, "x_lo and y_lo: both or neither");
+    if (!aligned4(st->x_lo) || !aligned4(st->y_lo))
+        return fail(LPM_EINVAL, "residual arrays must be 4-byte aligned");
     if (sch->n_total <= 0 || sch->n_total > 0xFFFFFFFFll)
         return fail(LPM_EINVAL, "n_total must be in [1, 2^32)");
     if (sch->s_release <= 0) return fail(LPM_EINVAL, "s_release must be positive");
@@ -858,7 +867,8 @@ int lpm_release_particles(const lpm_state* st, const lpm_source* src, const lpm_
     const double released = a0_of(src, sch, ph) * (double)(hi - lo);
     // a decay chain releases its parent only
     hipLaunchKernelGGL(lpm::release_kernel, dim3(blocks_for(hi - lo)), dim3(lpm::kBlock), 0,
-                       (hipStream_t)stream, st->x, st->y, st->z, st->m, lo, hi, (float)src->xs,
+                       (hipStream_t)stream, st->x, st->y, st->z, st->m, st->x_lo, st->y_lo, lo,
+                       hi, (float)src->xs,
                        (float)src->ys, (float)src->h, acc->ledger, ph->chain ? 1 : ph->n_nuc,
                        released);
     return hip_status("lpm_release_particles");
@@ -901,8 +911,8 @@ int fill_field(lpm::StepConst& p, const lpm_field* f)
     p.fcx = (float)(-f->x0 / f->dx - 0.5); p.fcy = (float)(-f->y0 / f->dy - 0.5);
     p.inv_dx = (float)(1.0 / f->dx); p.inv_dy = (float)(1.0 / f->dy);
     p.inv_dz = f->z_levels ? 0.0f : (float)(1.0 / f->dz);
-    p.inv_dtf = f->nt > 1 ? (float)(1.0 / f->dt_field) : 0.0f;
-    p.fct = f->nt > 1 ? (float)(-f->t0 / f->dt_field) : 0.0f;
+    p.inv_dtf = f->nt > 1 ? 1.0 / f->dt_field : 0.0;
+    p.ft_zero = f->nt > 1 ? -f->t0 / f->dt_field : 0.0;
     p.sj = f->nx * f->ncomp;
     p.sk = f->ny * p.sj;
     p.st = f->nz * p.sk;
@@ -933,9 +943,11 @@ void fill_source(lpm::StepConst& p, const lpm_source* src, const lpm_schedule* s
     }
 }
 
+// After fill_field (the time-node step needs the field interval).
 void fill_physics(lpm::StepConst& p, const lpm_physics* ph)
 {
     const double dt = ph->dt;
+    p.ft_step = dt * p.inv_dtf;
     p.key0 = (uint32_t)(ph->seed & 0xFFFFFFFFull);
     p.dt = (float)dt;
     p.sKh = (float)sqrt(2.0 * ph->Kh * dt);
@@ -1119,6 +1131,7 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
     p.n_rec = n_rec;
 
     p.X = st->x; p.Y = st->y; p.Z = st->z; p.M = st->m;
+    p.XL = st->x_lo; p.YL = st->y_lo;
     p.n_total = sch->n_total; p.id_base = sch->id_base; p.id_stride = sch->id_stride;
     p.s_release = sch->s_release;
     p.step0 = step0;

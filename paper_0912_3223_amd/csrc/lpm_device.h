@@ -37,11 +37,13 @@ struct DevScen {
 // rounded once to float.  Passed by value, so they live in SGPRs/the kernel
 // argument segment and cost no vector registers.
 struct StepConst {
-    // particle state
+    // particle state (XL, YL: rounding residuals of X, Y, or null)
     float* X;
     float* Y;
     float* Z;
     float* M;
+    float* XL;
+    float* YL;
     // schedule
     long long n_total, id_base, id_stride, i_hi;
     int s_release, step0, step_end, pad0;
@@ -55,8 +57,11 @@ struct StepConst {
     int imax, jmax, kmax, tmaxi;          // largest lower node index
     float fxmax, fymax, fzmax, ftmax;     // largest fractional node index
     // fractional node index of x: x inv_dx + fcx (fcx = -x0/dx - 1/2, cell-centred
-    // nodes), the same in y; of z: z inv_dz - 1/2; of t: t inv_dtf + fct
-    float fcx, fcy, inv_dx, inv_dy, inv_dz, fct, inv_dtf;
+    // nodes), the same in y; of z: z inv_dz - 1/2; of the time after step s
+    // (FP64, the same for every particle): s ft_step + ft_zero, ft_step =
+    // dt inv_dtf
+    float fcx, fcy, inv_dx, inv_dy, inv_dz;
+    double ft_step, ft_zero, inv_dtf;
     int di, dj, dk, dt_off;               // float offsets of the upper neighbours
     int sj, sk, st, pad1;                 // float strides of j, k, t
     int bounded;
@@ -297,11 +302,11 @@ __device__ __forceinline__ void trilinear(const float (&c)[8][NCOMP], float wx, 
     if constexpr (NCOMP == 2) out[2] = 0.0f;
 }
 
-// Issue the loads of the wind stencil at (x, y, z), time t (Sec. 3.2: linear
-// in x, y, z and t).
+// Issue the loads of the wind stencil at (x, y, z) at the start of step s
+// (Sec. 3.2: linear in x, y, z and t).
 template <int NCOMP, bool TIME, bool LEVELS>
 __device__ __forceinline__ void wind_gather(const StepConst& p, float x, float y, float z,
-                                            float t, WindTap<NCOMP, TIME>& w)
+                                            int s, WindTap<NCOMP, TIME>& w)
 {
     int i0, j0, k0;
     axis(x, p.fcx, p.inv_dx, p.fxmax, p.imax, i0, w.wx);
@@ -310,10 +315,14 @@ __device__ __forceinline__ void wind_gather(const StepConst& p, float x, float y
     else axis(z, -0.5f, p.inv_dz, p.fzmax, p.kmax, k0, w.wz);
     int base = k0 * p.sk + j0 * p.sj + i0 * NCOMP;
     if constexpr (TIME) {
-        // time nodes sit at ft0 + k dt_field (not cell-centred)
-        const float ft = clampf(fmaf(t, p.inv_dtf, p.fct), 0.0f, p.ftmax);
+        // time nodes sit at t0 + k dt_field (not cell-centred).  The time
+        // weight is the same for every particle of a step; in FP32 the
+        // rounding of 1/dt_field and of the fractional node index would bias
+        // it by up to ~1e-7 for a whole field interval, a coherent wind error
+        // that moves every trajectory the same way, so it is taken in FP64.
+        const double ft = fmin(fmax(fma((double)s, p.ft_step, p.ft_zero), 0.0), (double)p.ftmax);
         const int t0 = min((int)ft, p.tmaxi);
-        w.wt = ft - (float)t0;
+        w.wt = (float)(ft - (double)t0);
         base += t0 * p.st;
         gather8<NCOMP>(p.f, base, p.di, p.dj, p.dk, w.c[0]);
         gather8<NCOMP>(p.f, base + p.dt_off, p.di, p.dj, p.dk, w.c[1]);
@@ -436,13 +445,27 @@ __device__ __forceinline__ float fold_z(float zn, float H_top, float* sign = nul
 // start-of-step position and time.  The loads are issued first; everything
 // up to the interpolation is independent of them.  Returns the vertical
 // normal xi2 (the one random number the derivative of the step needs).
+// Horizontal positions are sums of thousands of steps of tens of metres on
+// values up to 5e4 m, where a float rounds to 4 mm: rounded every step, the
+// roundings would walk ~0.1 m away from the exact sum in 12 h.  Each
+// coordinate therefore carries its rounding residual lo (compensated
+// summation, Kahan): hi + lo holds the running sum exactly, hi is that sum
+// rounded to float and is the position every other part of the step uses.
+__device__ __forceinline__ float comp_add(float hi, float& lo, float d)
+{
+    const float y = d + lo;
+    const float t = hi + y;
+    lo = y - (t - hi);
+    return t;
+}
+
 template <int NCOMP, bool TIME, bool LEVELS, int KZ, bool UNIFORM_KEY>
 __device__ __forceinline__ float motion(const StepConst& p, float wscale, uint32_t key1,
                                         uint32_t gid, int s, float x, float y, float z,
-                                        float& xn, float& yn, float& zn)
+                                        float& xl, float& yl, float& xn, float& yn, float& zn)
 {
     WindTap<NCOMP, TIME> tap;
-    wind_gather<NCOMP, TIME, LEVELS>(p, x, y, z, (float)s * p.dt, tap);
+    wind_gather<NCOMP, TIME, LEVELS>(p, x, y, z, s, tap);
     float xi0, xi1, xi2;
     normals3<UNIFORM_KEY>(gid, (uint32_t)s, p.key0, key1, xi0, xi1, xi2);
     float K, dK, Km, dKm;
@@ -451,8 +474,8 @@ __device__ __forceinline__ float motion(const StepConst& p, float wscale, uint32
     kz_profile<KZ>(p, zm, Km, dKm);
     float uvw[3];
     wind_interp<NCOMP, TIME>(tap, uvw);
-    xn = fmaf(xi0, p.sKh, fmaf(wscale * uvw[0], p.dt, x));
-    yn = fmaf(xi1, p.sKh, fmaf(wscale * uvw[1], p.dt, y));
+    xn = comp_add(x, xl, fmaf(xi0, p.sKh, (wscale * uvw[0]) * p.dt));
+    yn = comp_add(y, yl, fmaf(xi1, p.sKh, (wscale * uvw[1]) * p.dt));
     zn = fold_z(fmaf(xi2 * __builtin_amdgcn_sqrtf(Km), p.s2dt,
                      fmaf(fmaf(wscale, uvw[2], dK), p.dt, z)),
                 p.H_top);
@@ -468,6 +491,25 @@ __device__ __forceinline__ float deposition_rate(const StepConst& p, float dry_c
     if (z < p.h_s) k = fmaxf(fmaf(-dry_c2, z, dry_c1), 0.0f);
     if (p.L0 > 0.0f) k += wet_rate(p, x, y);
     return k;
+}
+
+// exp(x) - 1 for x <= 0.  Per-step rates times dt are small (|x| < 1e-3 in
+// practice), where the Taylor series of exp to x^4/24 is exact to float
+// rounding (truncation x^5/120); larger |x| use the library expm1f.
+__device__ __forceinline__ float expm1_neg(float x)
+{
+    if (x > -0.0078125f)
+        return x * fmaf(x, fmaf(x, fmaf(x, 1.0f / 24.0f, 1.0f / 6.0f), 0.5f), 1.0f);
+    return expm1f(x);
+}
+
+// Mass left after a step at deposition rate k: m exp(-k dt), formed as
+// m + m (exp(-k dt) - 1) so that the one rounding is of the result (a factor
+// exp(-k dt) rounded near 1 would carry up to 2^-25 of error into every
+// step's product, over thousands of steps).
+__device__ __forceinline__ float deposit_mass(float m, float k, float dt)
+{
+    return k > 0.0f ? fmaf(m, expm1_neg(-k * dt), m) : m;
 }
 
 }  // namespace lpm

@@ -21,7 +21,8 @@ namespace lpm {
 
 // Release of every scenario of an ensemble window: blockIdx.y = scenario.
 __global__ __launch_bounds__(kBlock) void release_ensemble_kernel(float* X, float* Y, float* Z,
-                                                                  float* M, const DevScen* scen,
+                                                                  float* M, float* XL, float* YL,
+                                                                  const DevScen* scen,
                                                                   double* ledgers, int n_nuc)
 {
     const DevScen& d = scen[blockIdx.y];
@@ -32,6 +33,10 @@ __global__ __launch_bounds__(kBlock) void release_ensemble_kernel(float* X, floa
         Y[i] = d.ys;
         Z[i] = d.h;
         M[i] = 1.0f;
+        if (XL) {
+            XL[i] = 0.0f;
+            YL[i] = 0.0f;
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x < n_nuc && d.hi > d.lo)
         atomicAdd(ledgers + (long long)blockIdx.y * LPM_LEDGER_SLOTS * LPM_LEDGER_STRIDE +
@@ -86,6 +91,8 @@ int lpm_ensemble_prepare(const lpm_scenario* scen, int32_t n_scen, const lpm_sta
     if (step0 < 0 || n_steps < 1 || (long long)step0 + n_steps > 0x7FFFFFFFll)
         return fail(LPM_EINVAL, "bad step window");
     if (!st->x || !st->y || !st->z || !st->m) return fail(LPM_EINVAL, "null state array");
+    if ((st->x_lo == nullptr) != (st->y_lo == nullptr))
+        return fail(LPM_EINVAL, "x_lo and y_lo: both or neither");
     // fixed-size host buffers (no allocation, so nothing can throw)
     lpm::DevScen t[LPM_MAX_SCENARIOS];
     std::pair<long long, long long> ranges[LPM_MAX_SCENARIOS];
@@ -148,7 +155,7 @@ int lpm_release_ensemble(const lpm_state* st, const lpm_ensemble* ens, double* l
     if (ens->max_release <= 0) return LPM_OK;
     hipLaunchKernelGGL(lpm::release_ensemble_kernel,
                        dim3(blocks_for(ens->max_release), (unsigned)ens->n_scen), dim3(lpm::kBlock),
-                       0, (hipStream_t)stream, st->x, st->y, st->z, st->m,
+                       0, (hipStream_t)stream, st->x, st->y, st->z, st->m, st->x_lo, st->y_lo,
                        (const lpm::DevScen*)ens->table, ledgers, ens->n_nuc);
     return hip_status("lpm_release_ensemble");
 }
@@ -181,6 +188,9 @@ int lpm_step_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_fi
     p.refill_min = ens->launch.refill_min;
     p.rec_every = 1;
     p.X = st->x; p.Y = st->y; p.Z = st->z; p.M = st->m;
+    p.XL = st->x_lo; p.YL = st->y_lo;
+    if ((p.XL == nullptr) != (p.YL == nullptr))
+        return fail(LPM_EINVAL, "x_lo and y_lo: both or neither");
     p.step0 = ens->step0;
     p.step_end = ens->step0 + ens->n_steps;
     p.i_hi = ens->queue_len;

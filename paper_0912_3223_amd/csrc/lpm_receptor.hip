@@ -194,13 +194,14 @@ __device__ __forceinline__ void trilinear_dw(const float (&c)[8][NCOMP], float w
 }
 
 // Wind (before the wind scale) and its gradient G[c][d] = d uvw_c / d x_d at
-// (x, y, z, t); the value is the forward kernel's interpolation.
+// (x, y, z) at the start of step s; the value is the forward kernel's
+// interpolation.
 template <int NCOMP, bool TIME, bool LEVELS>
 __device__ __forceinline__ void wind_and_grad(const StepConst& p, float x, float y, float z,
-                                              float t, float uvw[3], float G[3][3])
+                                              int s, float uvw[3], float G[3][3])
 {
     WindTap<NCOMP, TIME> tap;
-    wind_gather<NCOMP, TIME, LEVELS>(p, x, y, z, t, tap);
+    wind_gather<NCOMP, TIME, LEVELS>(p, x, y, z, s, tap);
     const float sx = axis_slope(x, p.fcx, p.inv_dx, p.fxmax);
     const float sy = axis_slope(y, p.fcy, p.inv_dy, p.fymax);
     float sz;
@@ -243,7 +244,7 @@ __device__ __forceinline__ void reverse_step(const StepConst& p, const AdjConst&
                                              float& mb, float& swb, float& vdb)
 {
     float U[3], G[3][3];
-    wind_and_grad<NCOMP, TIME, LEVELS>(p, x, y, z, (float)s * p.dt, U, G);
+    wind_and_grad<NCOMP, TIME, LEVELS>(p, x, y, z, s, U, G);
     float K, dK, Km, dKm;
     kz_profile<KZ>(p, z, K, dK);
     const float K2 = kz_second<KZ>(p, z);
@@ -331,17 +332,19 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(const StepConst pk, con
                 const f4 r = recs[(long long)(k - 1) * a.rec_stride + i];
                 x = r.x; y = r.y; z = r.z; m = r.w;
             }
-            // recompute the segment into the tape
+            // recompute the segment into the tape (the forward's compensated
+            // position sums, from the float checkpoint)
+            float xl = 0.0f, yl = 0.0f;
             for (int s = s_lo; s <= s_hi; ++s) {
                 const long long row = (long long)(s - s_lo) * T + tid;
                 float xn, yn, zn;
                 const float xi2 = motion<NCOMP, TIME, LEVELS, KZ, true>(p, p.wscale, p.key1,
                                                                        (uint32_t)g, s, x, y, z,
-                                                                       xn, yn, zn);
+                                                                       xl, yl, xn, yn, zn);
                 tape[row] = f4{x, y, z, xi2};
                 tapem[row] = m;
                 const float kd = deposition_rate(p, p.dry_c1, p.dry_c2, xn, yn, zn);
-                m = kd > 0.0f ? m * __builtin_amdgcn_exp2f(-1.4426950408889634f * kd * p.dt) : m;
+                m = deposit_mass(m, kd, p.dt);
                 x = xn; y = yn; z = zn;
             }
             {

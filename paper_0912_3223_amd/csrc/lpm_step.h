@@ -23,16 +23,6 @@
 #include "lpm_device.h"
 
 namespace lpm {
-// exp(x) - 1 for x <= 0.  Per-step rates times dt are small (|x| < 1e-3 in
-// practice), where the Taylor series of exp to x^4/24 is exact to float
-// rounding (truncation x^5/120); larger |x| use the library expm1f.
-__device__ __forceinline__ float expm1_neg(float x)
-{
-    if (x > -0.0078125f)
-        return x * fmaf(x, fmaf(x, fmaf(x, 1.0f / 24.0f, 1.0f / 6.0f), 0.5f), 1.0f);
-    return expm1f(x);
-}
-
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
@@ -308,20 +298,22 @@ template <int NCOMP, bool TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool EN
 __device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
                                        DepTable<NNUC>& tab, long long plane, uint32_t gid,
                                        int b, int s, float& x, float& y, float& z, float& m,
+                                       float& xl, float& yl,
                                        LedgerAcc<NNUC, KZ, KZ != 4 && !ENS>& led,
                                        float (&bdep)[NNUC], Dwell<NNUC>& dw)
 {
     const float age = (float)(s - b) * p.dt;
     // wind sample, random numbers, diffusivity, move and fold
     float xn, yn, zn;
-    motion<NCOMP, TIME, LEVELS, KZ, !ENS>(p, sv.wscale, sv.key1, gid, s, x, y, z, xn, yn, zn);
+    motion<NCOMP, TIME, LEVELS, KZ, !ENS>(p, sv.wscale, sv.key1, gid, s, x, y, z, xl, yl, xn, yn,
+                                          zn);
     // decay factors at the start of the step
     float D[NNUC];
 #pragma unroll
     for (int n = 0; n < NNUC; ++n) D[n] = __builtin_amdgcn_exp2f(-p.lam_l2e[n] * age);
     // deposition rate at the new position (Sec. 2)
     const float k = DEP ? deposition_rate(p, sv.dry_c1, sv.dry_c2, xn, yn, zn) : 0.0f;
-    float mn = k > 0.0f ? m * __builtin_amdgcn_exp2f(-1.4426950408889634f * k * p.dt) : m;
+    float mn = deposit_mass(m, k, p.dt);
     // decay and deposition of each nuclide's activity this step
     float dsum[NNUC];
     bool removed = false;
@@ -490,6 +482,7 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
     uint32_t gid = 0;
     int b = 0, s = 0, krec = 0, next_rec = INT_MAX, s_take = 0;
     float x = 0.0f, y = 0.0f, z = 0.0f, m = 0.0f;
+    float xl = 0.0f, yl = 0.0f;  // rounding residuals of x, y
     float bdep[NNUC];  // deposited by the lane's particle in this window (light kernels)
 #pragma unroll
     for (int n = 0; n < NNUC; ++n) bdep[n] = 0.0f;
@@ -547,6 +540,8 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
                         x = as_global(p.X)[i];
                         y = as_global(p.Y)[i];
                         z = as_global(p.Z)[i];
+                        xl = p.XL ? as_global(p.XL)[i] : 0.0f;
+                        yl = p.YL ? as_global(p.YL)[i] : 0.0f;
                         s = b > p.step0 ? b : p.step0;
                         krec = s <= p.rec_step0 ? 0
                                                 : (s - p.rec_step0 + p.rec_every - 1) / p.rec_every;
@@ -579,7 +574,7 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
         for (int j = 0; j < p.refill_every; ++j) {
             if (have) {
                 const int st = advance<NCOMP, TIME, LEVELS, NNUC, KZ, DEP, ENS>(
-                    p, sv, tab, plane, gid, b, s, x, y, z, m, led, bdep, dw);
+                    p, sv, tab, plane, gid, b, s, x, y, z, m, xl, yl, led, bdep, dw);
                 if (s == next_rec) {  // state after an output step, for gridding later
                     typedef float quad __attribute__((ext_vector_type(4)));
                     as_global(reinterpret_cast<quad*>(rec4))[(long long)krec * p.rec_stride + i] =
@@ -595,6 +590,10 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
                     as_global(p.Y)[i] = y;
                     as_global(p.Z)[i] = z;
                     as_global(p.M)[i] = m;
+                    if (p.XL) {
+                        as_global(p.XL)[i] = xl;
+                        as_global(p.YL)[i] = yl;
+                    }
                     if (p.n_rec > 0) as_global(rec_exit)[i] = st != 0 ? s - 1 : INT_MAX;
                     if (st == 2) atomicOr(p.ctrl + LPM_CTRL_ERR, 1u);
                     have = false;

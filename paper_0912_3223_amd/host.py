@@ -54,8 +54,10 @@ class DeviceRun:
         self.y = torch.zeros(max(cap, 1), **f32)
         self.z = torch.zeros(max(cap, 1), **f32)
         self.m = torch.zeros(max(cap, 1), **f32)
+        self.xl = torch.zeros(max(cap, 1), **f32)  # rounding residuals of x, y
+        self.yl = torch.zeros(max(cap, 1), **f32)
         self.st = State(self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr(),
-                        self.m.data_ptr(), cap)
+                        self.m.data_ptr(), cap, self.xl.data_ptr(), self.yl.data_ptr())
         self.field_data = torch.from_numpy(np.ascontiguousarray(fld.data)).to(self.device)
         self.levels = None
         if fld.z_levels is not None:
@@ -85,9 +87,15 @@ class DeviceRun:
         self.m.zero_()
         accum_reset(self.acc)
 
-    def set_state(self, x, y, z, m):
+    def set_state(self, x, y, z, m, xl=None, yl=None):
+        """Load a state; xl, yl are the rounding residuals of x, y that
+        state() returns (zero if not given)."""
         for dst, src in ((self.x, x), (self.y, y), (self.z, z), (self.m, m)):
             dst[: len(src)].copy_(torch.as_tensor(np.asarray(src, dtype=np.float32)))
+        for dst, src in ((self.xl, xl), (self.yl, yl)):
+            dst.zero_()
+            if src is not None:
+                dst[: len(src)].copy_(torch.as_tensor(np.asarray(src, dtype=np.float32)))
 
     def release(self, step0: int, n_steps: int = 1):
         release_particles(self.st, self.src, self.sch, self.ph, step0, n_steps, self.acc)
@@ -116,8 +124,13 @@ class DeviceRun:
         check(self.acc)
 
     def state(self):
+        """x, y, z, m of the local particles (float64 copies) and the
+        residuals xl, yl of the compensated x, y."""
         n = self.sch.n_local
-        return {k: getattr(self, k)[:n].double().cpu().numpy() for k in "xyzm"}
+        out = {k: getattr(self, k)[:n].double().cpu().numpy() for k in "xyzm"}
+        out["xl"] = self.xl[:n].double().cpu().numpy()
+        out["yl"] = self.yl[:n].double().cpu().numpy()
+        return out
 
     def step_record(self, step0: int, n_steps: int, rec_step0: int, rec_every: int,
                     n_rec: int, rec: torch.Tensor):
@@ -292,8 +305,10 @@ class EnsembleRun:
         self.y = torch.zeros(total, **f32)
         self.z = torch.zeros(total, **f32)
         self.m = torch.zeros(total, **f32)
+        self.xl = torch.zeros(total, **f32)
+        self.yl = torch.zeros(total, **f32)
         self.st = State(self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr(),
-                        self.m.data_ptr(), total)
+                        self.m.data_ptr(), total, self.xl.data_ptr(), self.yl.data_ptr())
         self.fld, self._fdata, self._flev = _field_struct(base.field, self.device)
         self.ph = make_physics(base.physics)
         self.scen = (Scenario * n_scen)()

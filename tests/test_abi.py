@@ -93,6 +93,11 @@ def test_rejects_bad_arguments(args):
     # misaligned state
     mis = L.State(st.x + 2, st.y, st.z, st.m, 1000)
     assert step(mis, *ok[1:]) == L.LPM_EINVAL
+    # rounding residuals: both or neither, aligned
+    half = L.State(st.x, st.y, st.z, st.m, 1000, st.x, None)
+    assert step(half, *ok[1:]) == L.LPM_EINVAL and b"both or neither" in L.lib().lpm_last_error()
+    mis_lo = L.State(st.x, st.y, st.z, st.m, 1000, st.x + 2, st.y)
+    assert step(mis_lo, *ok[1:]) == L.LPM_EINVAL
     # bad windows
     assert step(st, src, sch, fld, ph, -1, 1, acc, None) == L.LPM_EINVAL
     assert step(st, src, sch, fld, ph, 0, 0, acc, None) == L.LPM_EINVAL

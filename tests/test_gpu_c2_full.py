@@ -16,9 +16,31 @@ tied to it three ways:
   parts of stride 64, each its own test: the GPU run of the part equals the
   full run's records of those ids bitwise, and the oracle recomputes the
   part from the same Philox counters -- trajectories at 3, 6 and 12 h (mean
-  <= 0.05 m, 99.9 % <= 1 m), cloud-in-cell concentration at those output
-  steps and the deposition grid (relative L2 <= 1e-4 over cells >= 1e-3 of
-  the peak), the ledger (<= 1e-6 of the released activity).
+  <= 0.05 m, 99.9 % <= 1 m), cloud-in-cell concentration at 3 h and 6 h
+  and the deposition grid (relative L2 <= 1e-4 over cells >= 1e-3 of the
+  peak), concentration at 12 h (below), the ledger (<= 1e-6 of the released
+  activity).
+
+After the release ends the cloud thins out: at 12 h a part keeps ~34k
+particles over ~360k cells above the mask, one or two per cell, so a cell's
+concentration moves with its particle's CIC weights, by ~ |e|/cell size for
+a trajectory difference e.  The float32 trajectories start to differ at the
+rounding level and the velocity gradients of the hourly fields stretch that
+(1e-3 m at 6 h, 1e-2 m at 12 h; the trajectory bars above hold throughout).
+So at 3 h and 6 h the concentration bar is 1e-4, and at 12 h it is 1e-4 or
+twice the rms CIC displacement scale of the measured trajectory
+differences, whichever is larger (this ties the concentration to the
+trajectories: an error in the gridding, the masses or the cells would exceed
+it).
+
+A particle that reaches the side of the exit box can leave it one step
+earlier or later on the two sides (the trajectories differ at the rounding
+level).  Near the end of the run, when few particles are left, one such
+particle decides a cell on its own; so status may differ for at most 0.1 %
+of the particles, each one at the box edge (<= 1 m from it) on the side that
+still holds it, and the concentrations are compared over the particles active
+on both sides, with the GPU's gridding of all its records checked against
+the oracle's gridding of them.
 """
 import numpy as np
 import pytest
@@ -81,6 +103,13 @@ def _meaningful(case, rr, last, step):
     g = sch.id_base + np.arange(len(last), dtype=np.int64) * sch.id_stride
     b = (g * sch.s_release) // sch.n_total
     return (b <= step) & (step < last) & (rr[:, 3] > 0)
+
+
+def _edge_distance(case, x, y):
+    """Distance of (x, y) to the nearest side of the exit box."""
+    f = case.field
+    return np.minimum.reduce([x - f.x0, f.x0 + f.nx * f.dx - x, y - f.y0,
+                              f.y0 + f.ny * f.dy - y]) if len(x) else np.zeros(0)
 
 
 def test_c2_full_run_invariants(full):
@@ -175,17 +204,49 @@ def test_c2_subset_parity(full, part):
         both = g_alive & o_alive
         gs = {"x": rr[:, 0], "y": rr[:, 1], "z": rr[:, 2]}
         d = distances(gs, state, both)
-        rel, ncell = rel_l2_masked(grids[k].double().cpu().numpy(), r["snaps"][0])
-        log("c2 part %d step %d: %d airborne, same status %.5f, P1 mean %.3e p99.9 %.3e max %.3e, "
-            "conc rel %.3e over %d cells" % (part, s, both.sum(), same, d.mean(),
-                                              np.quantile(d, 0.999), d.max(), rel, ncell))
+        # a particle active on one side only crossed the exit box within the
+        # rounding-level distance between the two trajectories: the side that
+        # still has it holds it at the edge of the box
+        flip = g_alive != o_alive
+        px = np.where(g_alive, rr[:, 0], state["x"])[flip]
+        py = np.where(g_alive, rr[:, 1], state["y"])[flip]
+        edge = _edge_distance(case, px, py)
+        # concentration of the particles active on both sides: the GPU's
+        # records and the oracle's states through the oracle's gridding; the
+        # GPU's own gridding of all its records against the oracle's
+        grid = o.grid_concentration
+        ref = grid(s, state["x"], state["y"], state["z"], np.where(both, state["m"], 0.0))
+        got = grid(s, rr[:, 0], rr[:, 1], rr[:, 2], np.where(both, rr[:, 3], 0.0))
+        rel, ncell = rel_l2_masked(got, ref)
+        g_all = grids[k].double().cpu().numpy()
+        rel_g, _ = rel_l2_masked(g_all, grid(s, rr[:, 0], rr[:, 1], rr[:, 2],
+                                              np.where(g_alive, rr[:, 3], 0.0)))
+        rel_all, _ = rel_l2_masked(g_all, r["snaps"][0])
+        dh = np.hypot(rr[both, 0] - state["x"][both], rr[both, 1] - state["y"][both])
+        dz = np.abs(rr[both, 2] - state["z"][both])
+        mb = np.mean(rr[both, 3] / state["m"][both] - 1.0)
+        # the cloud-in-cell weights of a particle moved by (ex, ey, ez) change
+        # by ~ |ex|/dx + |ey|/dy + |ez|/dz of its activity
+        cg = case.conc_grid
+        cic_scale = np.sqrt(np.mean((np.abs(rr[both, 0] - state["x"][both]) / cg.dx
+                                     + np.abs(rr[both, 1] - state["y"][both]) / cg.dy
+                                     + dz / cg.dz) ** 2))
+        log("c2 part %d step %d: horizontal mean %.3e, vertical mean %.3e, mass bias %.2e, "
+            "CIC displacement scale %.3e" % (part, s, dh.mean(), dz.mean(), mb, cic_scale))
+        log("c2 part %d step %d: %d airborne, %d on one side only (<= %.3f m from the box edge), "
+            "P1 mean %.3e p99.9 %.3e max %.3e, conc rel %.3e over %d cells (all particles %.3e), "
+            "GPU gridding rel %.3e" % (part, s, both.sum(), flip.sum(),
+                                       edge.max() if flip.any() else 0.0, d.mean(),
+                                       np.quantile(d, 0.999), d.max(), rel, ncell, rel_all, rel_g))
         assert same >= 0.999
+        assert np.all(edge <= 1.0)
         assert d.mean() <= 0.05 and np.quantile(d, 0.999) <= 1.0
         # masses: a float32 product of up to ~8600 per-step factors, each
         # rounded (<= 2^-24) after a hardware exp2 (~1 ulp): ~1e-5 typical,
         # 2e-4 leaves room for the tail of 250k particles
         np.testing.assert_allclose(rr[both, 3], state["m"][both], rtol=2e-4)
-        assert rel <= 1e-4
+        assert rel <= max(1e-4, 2.0 * cic_scale) if s > 4319 else rel <= 1e-4
+        assert rel_g <= 1e-6
     reld, ncell = rel_l2_masked(dep, o_dep)
     log("c2 part %d: deposition rel %.3e over %d cells" % (part, reld, ncell))
     assert reld <= 1e-4
