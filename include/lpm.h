@@ -262,6 +262,26 @@ int lpm_grid_concentration(const lpm_state* st, const lpm_source* src,
                            const lpm_grid* grid, int32_t step,
                            double* acc_scratch, float* out, lpm_stream stream);
 
+/* Doubles of the static device scratch of lpm_grid_concentration_static
+ * (4 Mi = 32 MiB per device): n_nuc * nx * ny * nz may not exceed it. */
+#define LPM_STATIC_SCRATCH_DOUBLES (4 * 1024 * 1024)
+
+/* lpm_grid_concentration without the acc_scratch argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops
+ * or harnesses that forbid allocation).  The FP64 accumulation grid is a
+ * static device array of the library, LPM_STATIC_SCRATCH_DOUBLES doubles per
+ * device, held from library load to process end; its address on a device is
+ * looked up on the first call with that device current.  The call allocates
+ * nothing and clears the part of the array it uses before use.  Errors as
+ * lpm_grid_concentration, and LPM_EINVAL when n_nuc * nx * ny * nz exceeds
+ * LPM_STATIC_SCRATCH_DOUBLES.  Every call on a device shares that device's
+ * array: calls on one device that overlap in time (other streams, other host
+ * threads) race on it and give wrong grids -- order them on one stream. */
+int lpm_grid_concentration_static(const lpm_state* st, const lpm_source* src,
+                                  const lpm_schedule* sch, const lpm_physics* ph,
+                                  const lpm_grid* grid, int32_t step, float* out,
+                                  lpm_stream stream);
+
 /* Bytes of device workspace lpm_grid_records needs for these arguments:
  * per (output step, bin of grid columns) two 64-bit offsets, one int per
  * 2048 particles, and one 8-byte entry (particle index, birth step) per

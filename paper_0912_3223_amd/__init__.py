@@ -21,6 +21,7 @@ LPM_OK, LPM_EINVAL, LPM_ECAPACITY, LPM_EHIP, LPM_ENONFINITE = 0, -1, -2, -3, -4
 LEDGER_SLOTS = 64
 MAX_SCENARIOS = 256
 LPM_MAX_RECEPTORS = 1024
+STATIC_SCRATCH_DOUBLES = 4 * 1024 * 1024
 SCENARIO_BYTES = 96
 LEDGER_STRIDE = 32
 CTRL_WORDS = 64
@@ -125,6 +126,8 @@ def _load():
                                       C.c_int32, C.c_void_p, C.c_int64, C.c_void_p],
         "lpm_grid_concentration": [P(State), P(Source), P(Schedule), P(Physics), P(Grid),
                                    C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
+        "lpm_grid_concentration_static": [P(State), P(Source), P(Schedule), P(Physics),
+                                          P(Grid), C.c_int32, C.c_void_p, C.c_void_p],
         "lpm_grid_records_workspace": [P(Schedule), P(Physics), P(Grid), C.c_int32, C.c_int32,
                                        C.c_int32, P(C.c_int64)],
         "lpm_grid_records": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, P(Source),
@@ -166,7 +169,8 @@ _lib = _load()
 #: C entry points exported by include/lpm.h (checked by the test suite).
 EXPORTS = ("lpm_accum_reset", "lpm_release_particles", "lpm_step_particles",
            "lpm_step_particles_record",
-           "lpm_grid_concentration", "lpm_grid_records_workspace", "lpm_grid_records",
+           "lpm_grid_concentration", "lpm_grid_concentration_static",
+           "lpm_grid_records_workspace", "lpm_grid_records",
            "lpm_grid_deposition",
            "lpm_read_ledger", "lpm_check", "lpm_set_launch", "lpm_set_launch_ex", "lpm_ensemble_prepare",
            "lpm_release_ensemble", "lpm_step_ensemble", "lpm_autotune_ensemble",
@@ -225,6 +229,16 @@ def grid_concentration(st: State, src: Source, sch: Schedule, ph: Physics, grid:
     _rc(_lib.lpm_grid_concentration(C.byref(st), C.byref(src), C.byref(sch), C.byref(ph),
                                     C.byref(grid), step, C.c_void_p(acc_scratch.data_ptr()),
                                     C.c_void_p(out.data_ptr()), _stream(stream)))
+
+
+def grid_concentration_static(st: State, src: Source, sch: Schedule, ph: Physics, grid: Grid,
+                              step: int, out: torch.Tensor, stream=None):
+    """grid_concentration on the library's static device scratch (no
+    allocation; calls on one device must not overlap)."""
+    assert out.dtype == torch.float32
+    _rc(_lib.lpm_grid_concentration_static(C.byref(st), C.byref(src), C.byref(sch), C.byref(ph),
+                                           C.byref(grid), step, C.c_void_p(out.data_ptr()),
+                                           _stream(stream)))
 
 
 def grid_records_workspace(sch: Schedule, ph: Physics, grid: Grid, rec_step0: int,

@@ -1244,6 +1244,35 @@ int check_grid_concentration(const lpm_state* st, const lpm_source* src, const l
 
 }  // namespace lpm_host
 
+// FP64 accumulation grid of lpm_grid_concentration_static: one copy per
+// device, held from module load to process end.  Host code uses its device
+// address from hipGetSymbolAddress (kept per device below), never the name.
+static __device__ __align__(256) double scratch[LPM_STATIC_SCRATCH_DOUBLES];
+
+namespace lpm_host {
+
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device
+
+// Address of `scratch` on the current device, looked up on the first call
+// there (with that device current).  nullptr when the lookup fails.
+double* static_scratch()
+{
+    const int dev = current_device();
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace lpm_host
+
 extern "C" {
 
 int lpm_grid_concentration(const lpm_state* st, const lpm_source* src, const lpm_schedule* sch,
@@ -1257,6 +1286,24 @@ int lpm_grid_concentration(const lpm_state* st, const lpm_source* src, const lpm
         return fail(LPM_EINVAL, "null or misaligned grid scratch");
     return grid_concentration_impl(st, src, sch, ph, grid, step, acc_scratch, out, stream,
                                    "lpm_grid_concentration");
+}
+
+int lpm_grid_concentration_static(const lpm_state* st, const lpm_source* src,
+                                  const lpm_schedule* sch, const lpm_physics* ph,
+                                  const lpm_grid* grid, int32_t step, float* out,
+                                  lpm_stream stream)
+{
+    g_msg[0] = 0;
+    int rc = check_grid_concentration(st, src, sch, ph, grid, step, out);
+    if (rc) return rc;
+    const long long need = (long long)ph->n_nuc * grid->nx * grid->ny * grid->nz;
+    if (need > LPM_STATIC_SCRATCH_DOUBLES)
+        return fail(LPM_EINVAL, "grid of %lld cells x nuclides exceeds the static scratch of %d",
+                    need, LPM_STATIC_SCRATCH_DOUBLES);
+    double* acc = static_scratch();
+    if (!acc) return fail(LPM_EHIP, "lpm_grid_concentration_static: no address for the static scratch");
+    return grid_concentration_impl(st, src, sch, ph, grid, step, acc, out, stream,
+                                   "lpm_grid_concentration_static");
 }
 
 namespace lpm_host {
