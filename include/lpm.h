@@ -116,16 +116,25 @@ typedef struct {
     int32_t reserved;
 } lpm_schedule;
 
+/* Layouts of lpm_field.data. */
+#define LPM_FIELD_NODES 0      /* float [nt][nz][ny][nx][ncomp] */
+#define LPM_FIELD_TIME_PAIRS 1 /* one interval, both times per node (lpm_field_interval) */
+
 /* Gridded wind (Sec. 3.2: weather sampled linearly in x, y, z and time).
- * data: device float [nt][nz][ny][nx][ncomp]; z_levels: device float[nz],
- * increasing node heights, or NULL for (k + 1/2) dz.  bounded != 0: a
- * particle whose post-step (x, y) leaves [x0, x0 + nx dx) x [y0, y0 + ny dy)
- * is inactivated and its activity booked as exited (Sec. 3.2). */
+ * data: device float [nt][nz][ny][nx][ncomp] (layout LPM_FIELD_NODES), or
+ * the time-pair copy of one interval that lpm_field_interval writes (layout
+ * LPM_FIELD_TIME_PAIRS); z_levels: device float[nz], increasing node
+ * heights, or NULL for (k + 1/2) dz.  Time node k is at t0 + k dt_field.
+ * bounded != 0: a particle whose post-step (x, y) leaves [x0, x0 + nx dx) x
+ * [y0, y0 + ny dy) is inactivated and its activity booked as exited
+ * (Sec. 3.2). */
 typedef struct {
     const float* data;
     const float* z_levels;
     int32_t nx, ny, nz, nt, ncomp, bounded;
     double x0, y0, dx, dy, dz, t0, dt_field;
+    int32_t layout;   /* LPM_FIELD_NODES or LPM_FIELD_TIME_PAIRS */
+    int32_t interval; /* time-pair fields: the interval k that data holds */
 } lpm_field;
 
 /* Physical constants (Sec. 2, Eqs. 2-3).
@@ -261,6 +270,33 @@ int lpm_grid_concentration(const lpm_state* st, const lpm_source* src,
                            const lpm_schedule* sch, const lpm_physics* ph,
                            const lpm_grid* grid, int32_t step,
                            double* acc_scratch, float* out, lpm_stream stream);
+
+/* *bytes (host) = the size of the time-pair copy of one interval of fld
+ * (lpm_field_interval): nz * ny * nx nodes of 16 bytes (ncomp 2) or 32
+ * bytes (ncomp 3).  LPM_EINVAL unless fld is an LPM_FIELD_NODES field with
+ * nt >= 2 and nx >= 2. */
+int lpm_field_interval_bytes(const lpm_field* fld, int64_t* bytes);
+
+/* The wind of a step is linear in time between two weather times (Sec. 3.2),
+ * so a step reads the stencil at both times of its field interval.  Writes
+ * interval k, [t0 + k dt_field, t0 + (k + 1) dt_field], of fld (layout
+ * LPM_FIELD_NODES, nt >= 2, nx >= 2, 0 <= k <= nt - 2) into out with both
+ * times of each node side by side: per node (u, v) at the interval's start,
+ * then at its end (ncomp 2, 16 bytes), or (u, v, w, 0) at the start, then
+ * at the end (ncomp 3, 32 bytes), nodes in [nz][ny][nx] order.  A step's
+ * wind stencil then takes one set of cache lines for both times instead of
+ * one per time.  out: caller-owned device memory of
+ * lpm_field_interval_bytes bytes, 16-byte aligned, not overlapping
+ * fld->data.  *packed (host) receives the descriptor of the copy: fld with
+ * data = out, layout = LPM_FIELD_TIME_PAIRS and interval = k (nt, t0 and
+ * dt_field stay those of fld).  lpm_step_particles,
+ * lpm_step_particles_record and lpm_step_ensemble take it for calls all of
+ * whose steps interpolate in interval k -- start times in [t_k, t_k+1), and
+ * before t_0 for k = 0, from t_k+1 on for k = nt - 2 (where fld clamps) --
+ * with results equal to those on fld bitwise, and reject other calls
+ * (LPM_EINVAL); the adjoint does not take it.  Stream-ordered. */
+int lpm_field_interval(const lpm_field* fld, int32_t k, void* out, lpm_field* packed,
+                       lpm_stream stream);
 
 /* Doubles of the static device scratch of lpm_grid_concentration_static
  * (4 Mi = 32 MiB per device): n_nuc * nx * ny * nz may not exceed it. */
@@ -417,15 +453,17 @@ typedef struct {
     lpm_launch launch; /* the chosen setting (also written to ens->launch) */
     double best_ms;    /* median trial time of the chosen setting */
     double worst_ms;   /* median trial time of the slowest setting */
-    int32_t n_tried;   /* settings timed */
+    int32_t n_tried;   /* distinct launches timed */
     int32_t reps;      /* timed trials per setting (the median is kept) */
 } lpm_tuning;
 
 /* Autotuner: time the ensemble step over the first `trial_steps` steps of
  * the prepared window for each candidate setting -- queue schedule (refill
  * interval and idle lanes before a refill), threads per block and blocks per
- * compute unit -- `reps` times each (1 .. 15, after one untimed warm-up), and
- * keep in ens->launch the first candidate, in a fixed order, whose median
+ * compute unit -- `reps` times each (1 .. 15, after one untimed warm-up;
+ * candidates that would launch alike, the same schedule and block size on
+ * the same number of resident blocks, are timed once, as the first of
+ * them), and keep in ens->launch the first candidate, in a fixed order, whose median
  * time is within 3 % of the smallest median (settings that time alike are
  * told apart by the order, so repeated calls pick the same setting; nothing
  * process-wide changes).  It runs release and step on the given buffers, so

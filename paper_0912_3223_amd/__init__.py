@@ -54,7 +54,8 @@ class Field(C.Structure):
                 ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nt", C.c_int32),
                 ("ncomp", C.c_int32), ("bounded", C.c_int32),
                 ("x0", C.c_double), ("y0", C.c_double), ("dx", C.c_double), ("dy", C.c_double),
-                ("dz", C.c_double), ("t0", C.c_double), ("dt_field", C.c_double)]
+                ("dz", C.c_double), ("t0", C.c_double), ("dt_field", C.c_double),
+                ("layout", C.c_int32), ("interval", C.c_int32)]
 
 
 class Physics(C.Structure):
@@ -150,6 +151,8 @@ def _load():
                                        P(Source), P(Schedule), P(Physics), P(Receptors),
                                        C.c_void_p, C.c_void_p],
         "lpm_adjoint_workspace": [P(Field), P(Schedule), C.c_int32, P(C.c_int64)],
+        "lpm_field_interval_bytes": [P(Field), P(C.c_int64)],
+        "lpm_field_interval": [P(Field), C.c_int32, C.c_void_p, P(Field), C.c_void_p],
         "lpm_surface_layer": [C.c_double] * 5 + [P(C.c_double), P(C.c_double)],
         "lpm_receptor_adjoint": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, P(Source),
                                  P(Schedule), P(Field), P(Physics), P(Receptors), C.c_void_p,
@@ -175,7 +178,7 @@ EXPORTS = ("lpm_accum_reset", "lpm_release_particles", "lpm_step_particles",
            "lpm_read_ledger", "lpm_check", "lpm_set_launch", "lpm_set_launch_ex", "lpm_ensemble_prepare",
            "lpm_release_ensemble", "lpm_step_ensemble", "lpm_autotune_ensemble",
            "lpm_receptor_concentration", "lpm_adjoint_workspace", "lpm_receptor_adjoint",
-           "lpm_surface_layer",
+           "lpm_surface_layer", "lpm_field_interval_bytes", "lpm_field_interval",
            "lpm_last_error", "lpm_version")
 
 
@@ -239,6 +242,25 @@ def grid_concentration_static(st: State, src: Source, sch: Schedule, ph: Physics
     _rc(_lib.lpm_grid_concentration_static(C.byref(st), C.byref(src), C.byref(sch), C.byref(ph),
                                            C.byref(grid), step, C.c_void_p(out.data_ptr()),
                                            _stream(stream)))
+
+
+FIELD_NODES, FIELD_TIME_PAIRS = 0, 1
+
+
+def field_interval_bytes(fld: Field) -> int:
+    n = C.c_int64(0)
+    _rc(_lib.lpm_field_interval_bytes(C.byref(fld), C.byref(n)))
+    return n.value
+
+
+def field_interval(fld: Field, k: int, out: torch.Tensor, stream=None) -> Field:
+    """Time-pair copy of field interval k into ``out``; returns its
+    descriptor (which refers to ``out``: keep it alive)."""
+    assert out.is_contiguous() and out.numel() * out.element_size() >= field_interval_bytes(fld)
+    packed = Field()
+    _rc(_lib.lpm_field_interval(C.byref(fld), k, C.c_void_p(out.data_ptr()), C.byref(packed),
+                                _stream(stream)))
+    return packed
 
 
 def grid_records_workspace(sch: Schedule, ph: Physics, grid: Grid, rec_step0: int,

@@ -616,6 +616,31 @@ __global__ __launch_bounds__(kBlock) void fill_u32(uint32_t* p, long long n)
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) p[i] = 0u;
 }
 
+// Time-pair copy of one field interval: node n of the two time slabs a, b
+// (ncomp floats each) becomes (a_n | b_n), padded to 4 floats per time for
+// three components.  One node per thread: coalesced 8- or 4-byte reads and
+// 16-byte writes.
+template <int NCOMP>
+__global__ __launch_bounds__(kBlock) void field_pairs(const float* __restrict__ a,
+                                                      const float* __restrict__ b,
+                                                      float* __restrict__ out, long long nodes)
+{
+    typedef float quad __attribute__((ext_vector_type(4)));
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long n = (long long)blockIdx.x * kBlock + threadIdx.x; n < nodes; n += stride) {
+        if constexpr (NCOMP == 2) {
+            const float2 u = reinterpret_cast<const float2*>(a)[n];
+            const float2 v = reinterpret_cast<const float2*>(b)[n];
+            reinterpret_cast<quad*>(out)[n] = quad{u.x, u.y, v.x, v.y};
+        } else {
+            const float* pa = a + 3 * n;
+            const float* pb = b + 3 * n;
+            reinterpret_cast<quad*>(out)[2 * n] = quad{pa[0], pa[1], pa[2], 0.0f};
+            reinterpret_cast<quad*>(out)[2 * n + 1] = quad{pb[0], pb[1], pb[2], 0.0f};
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void to_f32(const double* __restrict__ src, float* dst,
                                                  long long n, double scale)
 {
@@ -894,7 +919,16 @@ int fill_field(lpm::StepConst& p, const lpm_field* f)
     if (f->ncomp != 2 && f->ncomp != 3) return fail(LPM_EINVAL, "field ncomp must be 2 or 3");
     if (!(f->dx > 0 && f->dy > 0 && (f->z_levels || f->dz > 0) && (f->nt == 1 || f->dt_field > 0)))
         return fail(LPM_EINVAL, "field spacings must be positive");
-    const double total = (double)f->nt * f->nz * f->ny * f->nx * f->ncomp;
+    const bool tpair = f->layout == LPM_FIELD_TIME_PAIRS;
+    if (f->layout != LPM_FIELD_NODES && !tpair) return fail(LPM_EINVAL, "unknown field layout");
+    // floats per node and time block: (u, v) or (u, v, w); a time-pair node
+    // holds both times, (u, v | u, v) or (u, v, w, 0 | u, v, w, 0)
+    const int rec = tpair ? (f->ncomp == 2 ? 4 : 8) : f->ncomp;
+    if (tpair && (f->nt < 2 || f->nx < 2 || f->interval < 0 || f->interval > f->nt - 2))
+        return fail(LPM_EINVAL, "a time-pair field needs nt >= 2, nx >= 2 and interval in [0, nt - 2]");
+    if (tpair && ((uintptr_t)f->data & 15u))
+        return fail(LPM_EINVAL, "a time-pair field must be 16-byte aligned");
+    const double total = (double)(tpair ? 1 : f->nt) * f->nz * f->ny * f->nx * rec;
     if (total >= 2147483647.0) return fail(LPM_EINVAL, "field larger than 2^31 floats");
     if (f->ncomp == 2 && ((uintptr_t)f->data & 7u))
         return fail(LPM_EINVAL, "two-component field must be 8-byte aligned");
@@ -913,13 +947,15 @@ int fill_field(lpm::StepConst& p, const lpm_field* f)
     p.inv_dz = f->z_levels ? 0.0f : (float)(1.0 / f->dz);
     p.inv_dtf = f->nt > 1 ? 1.0 / f->dt_field : 0.0;
     p.ft_zero = f->nt > 1 ? -f->t0 / f->dt_field : 0.0;
-    p.sj = f->nx * f->ncomp;
+    p.si = rec;
+    p.sj = f->nx * rec;
     p.sk = f->ny * p.sj;
-    p.st = f->nz * p.sk;
-    p.di = f->nx > 1 ? f->ncomp : 0;
+    p.st = tpair ? 0 : f->nz * p.sk;
+    p.di = f->nx > 1 ? rec : 0;
     p.dj = f->ny > 1 ? p.sj : 0;
     p.dk = f->nz > 1 ? p.sk : 0;
-    p.dt_off = f->nt > 1 ? p.st : 0;
+    p.dt_off = tpair ? rec / 2 : (f->nt > 1 ? p.st : 0);
+    p.tpair = tpair;
     p.bounded = f->bounded != 0;
     p.X0 = (float)f->x0; p.X1 = (float)(f->x0 + f->nx * f->dx);
     p.Y0 = (float)f->y0; p.Y1 = (float)(f->y0 + f->ny * f->dy);
@@ -941,6 +977,26 @@ void fill_source(lpm::StepConst& p, const lpm_source* src, const lpm_schedule* s
         p.dry_c1 = (float)(2.0 * src->v_d / ph->h_s);
         p.dry_c2 = (float)(2.0 * src->v_d / (ph->h_s * ph->h_s));
     }
+}
+
+// Lower time node of step s, as the step kernel takes it.
+static int time_node(const lpm::StepConst& p, long long s)
+{
+    const double ft = fmin(fmax(fma((double)s, p.ft_step, p.ft_zero), 0.0), (double)p.ftmax);
+    return std::min((int)ft, p.tmaxi);
+}
+
+// A time-pair field holds one interval: every step of [step0, step0 +
+// n_steps) must interpolate in it (the node is monotone in the step, so the
+// first and the last step decide).  After fill_field and fill_physics.
+int check_field_steps(const lpm::StepConst& p, const lpm_field* f, long long step0,
+                      long long n_steps)
+{
+    if (!p.tpair) return LPM_OK;
+    if (time_node(p, step0) != f->interval || time_node(p, step0 + n_steps - 1) != f->interval)
+        return fail(LPM_EINVAL, "steps %lld..%lld do not all interpolate in field interval %d",
+                    step0, step0 + n_steps - 1, f->interval);
+    return LPM_OK;
 }
 
 // After fill_field (the time-node step needs the field interval).
@@ -1140,6 +1196,7 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
 
     fill_source(p, src, sch, ph);
     fill_physics(p, ph);
+    if ((rc = check_field_steps(p, fld, step0, n_steps))) return rc;
     fill_depgrid(p, acc->dep_grid);
     p.dep = acc->dep; p.ledger = acc->ledger; p.ctrl = acc->ctrl;
 
@@ -1501,6 +1558,60 @@ int lpm_grid_deposition(const lpm_accum* acc, float* out, lpm_stream stream)
     hipLaunchKernelGGL(lpm::to_f32, dim3(fb), dim3(lpm::kBlock), 0, (hipStream_t)stream, acc->dep,
                        out, total, 1.0);
     return hip_status("lpm_grid_deposition");
+}
+
+static int64_t interval_bytes(const lpm_field* fld)
+{
+    if (!fld || !fld->data) return fail(LPM_EINVAL, "null field");
+    if (fld->layout != LPM_FIELD_NODES) return fail(LPM_EINVAL, "the field must be in the node layout");
+    if (fld->nt < 2 || fld->nx < 2) return fail(LPM_EINVAL, "a field interval needs nt >= 2 and nx >= 2");
+    if (fld->ncomp != 2 && fld->ncomp != 3) return fail(LPM_EINVAL, "field ncomp must be 2 or 3");
+    if (fld->ny < 1 || fld->nz < 1) return fail(LPM_EINVAL, "bad field shape");
+    return (int64_t)fld->nx * fld->ny * fld->nz * (fld->ncomp == 2 ? 16 : 32);
+}
+
+int lpm_field_interval_bytes(const lpm_field* fld, int64_t* bytes)
+{
+    g_msg[0] = 0;
+    if (!bytes) return fail(LPM_EINVAL, "null output");
+    const int64_t b = interval_bytes(fld);
+    if (b < 0) return (int)b;
+    *bytes = b;
+    return LPM_OK;
+}
+
+int lpm_field_interval(const lpm_field* fld, int32_t k, void* out, lpm_field* packed,
+                       lpm_stream stream)
+{
+    g_msg[0] = 0;
+    const int64_t bytes = interval_bytes(fld);
+    if (bytes < 0) return (int)bytes;
+    if (k < 0 || k > fld->nt - 2) return fail(LPM_EINVAL, "interval %d outside [0, %d]", k, fld->nt - 2);
+    if (!out || ((uintptr_t)out & 15u)) return fail(LPM_EINVAL, "null or misaligned output");
+    if (!packed) return fail(LPM_EINVAL, "null descriptor");
+    if (fld->ncomp == 2 && ((uintptr_t)fld->data & 7u))
+        return fail(LPM_EINVAL, "two-component field must be 8-byte aligned");
+    const long long nodes = (long long)fld->nx * fld->ny * fld->nz;
+    const char* o = static_cast<const char*>(out);
+    const char* d = reinterpret_cast<const char*>(fld->data);
+    const long long src_bytes = (long long)fld->nt * nodes * fld->ncomp * 4;
+    if (o < d + src_bytes && d < o + bytes) return fail(LPM_EINVAL, "output overlaps the field");
+    const float* a = fld->data + (long long)k * nodes * fld->ncomp;
+    const float* b = a + nodes * fld->ncomp;
+    const unsigned nb = blocks_for(nodes) < 8192 ? blocks_for(nodes) : 8192;
+    hipStream_t s = (hipStream_t)stream;
+    if (fld->ncomp == 2)
+        hipLaunchKernelGGL(lpm::field_pairs<2>, dim3(nb), dim3(lpm::kBlock), 0, s, a, b,
+                           static_cast<float*>(out), nodes);
+    else
+        hipLaunchKernelGGL(lpm::field_pairs<3>, dim3(nb), dim3(lpm::kBlock), 0, s, a, b,
+                           static_cast<float*>(out), nodes);
+    lpm_field q = *fld;
+    q.data = static_cast<const float*>(out);
+    q.layout = LPM_FIELD_TIME_PAIRS;
+    q.interval = k;
+    *packed = q;
+    return hip_status("lpm_field_interval");
 }
 
 int lpm_read_ledger(const lpm_accum* acc, double* host_out, lpm_stream stream)

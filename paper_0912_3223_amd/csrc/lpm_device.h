@@ -63,8 +63,9 @@ struct StepConst {
     float fcx, fcy, inv_dx, inv_dy, inv_dz;
     double ft_step, ft_zero, inv_dtf;
     int di, dj, dk, dt_off;               // float offsets of the upper neighbours
-    int sj, sk, st, pad1;                 // float strides of j, k, t
+    int si, sj, sk, st;                   // float strides of i, j, k, t
     int bounded;
+    int tpair;                            // time-pair copy of one field interval
     float X0, X1, Y0, Y1;                 // exit box
     // physics
     float dt, sKh, s2dt, half_dt;
@@ -287,6 +288,32 @@ __device__ __forceinline__ void gather8(const float* __restrict__ fp, int base, 
     }
 }
 
+// The stencil at both times from a time-pair copy of a two-component field
+// interval: per node (u, v) at the interval's start and end side by side,
+// 16 bytes, so the two x-neighbours of a (y, z) corner are 32 contiguous
+// bytes -- two 16-byte loads, mostly in one cache line, for both times.
+__device__ __forceinline__ void gather8_tpair(const float* __restrict__ fp, int base, int dj,
+                                              int dk, float (&c)[2][8][2])
+{
+    typedef float quad __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(1))) const quad gquad;
+    const gfloat* f = as_global(fp);
+    const int o[4] = {base, base + dj, base + dk, base + dk + dj};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const quad a = *reinterpret_cast<gquad*>(f + o[q]);
+        const quad b = *reinterpret_cast<gquad*>(f + o[q] + 4);
+        c[0][2 * q][0] = a.x;
+        c[0][2 * q][1] = a.y;
+        c[1][2 * q][0] = a.z;
+        c[1][2 * q][1] = a.w;
+        c[0][2 * q + 1][0] = b.x;
+        c[0][2 * q + 1][1] = b.y;
+        c[1][2 * q + 1][0] = b.z;
+        c[1][2 * q + 1][1] = b.w;
+    }
+}
+
 template <int NCOMP>
 __device__ __forceinline__ void trilinear(const float (&c)[8][NCOMP], float wx, float wy,
                                           float wz, float out[3])
@@ -313,7 +340,7 @@ __device__ __forceinline__ void wind_gather(const StepConst& p, float x, float y
     axis(y, p.fcy, p.inv_dy, p.fymax, p.jmax, j0, w.wy);
     if constexpr (LEVELS) levels(p.lev, p.nz, z, k0, w.wz);
     else axis(z, -0.5f, p.inv_dz, p.fzmax, p.kmax, k0, w.wz);
-    int base = k0 * p.sk + j0 * p.sj + i0 * NCOMP;
+    int base = k0 * p.sk + j0 * p.sj + i0 * p.si;
     if constexpr (TIME) {
         // time nodes sit at t0 + k dt_field (not cell-centred).  The time
         // weight is the same for every particle of a step; in FP32 the
@@ -324,6 +351,12 @@ __device__ __forceinline__ void wind_gather(const StepConst& p, float x, float y
         const int t0 = min((int)ft, p.tmaxi);
         w.wt = (float)(ft - (double)t0);
         base += t0 * p.st;
+        if constexpr (NCOMP == 2) {
+            if (p.tpair) {
+                gather8_tpair(p.f, base, p.dj, p.dk, w.c);
+                return;
+            }
+        }
         gather8<NCOMP>(p.f, base, p.di, p.dj, p.dk, w.c[0]);
         gather8<NCOMP>(p.f, base + p.dt_off, p.di, p.dj, p.dk, w.c[1]);
     } else {

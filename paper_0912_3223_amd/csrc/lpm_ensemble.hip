@@ -160,9 +160,12 @@ int lpm_release_ensemble(const lpm_state* st, const lpm_ensemble* ens, double* l
     return hip_status("lpm_release_ensemble");
 }
 
-int lpm_step_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_field* fld,
-                      const lpm_physics* ph, const lpm_grid* dep_grid, double* dep,
-                      double* ledgers, uint32_t* ctrl, lpm_stream stream)
+// lpm_step_ensemble; with `plan`, only validates and stores in *plan the
+// number of blocks the step launch would take (nothing is launched).
+static int step_ensemble_impl(const lpm_state* st, const lpm_ensemble* ens,
+                              const lpm_field* fld, const lpm_physics* ph,
+                              const lpm_grid* dep_grid, double* dep, double* ledgers,
+                              uint32_t* ctrl, lpm_stream stream, unsigned* plan)
 {
     g_msg[0] = 0;
     int rc;
@@ -183,6 +186,7 @@ int lpm_step_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_fi
     memset(&p, 0, sizeof p);
     if ((rc = fill_field(p, fld))) return rc;
     fill_physics(p, ph);
+    if ((rc = check_field_steps(p, fld, ens->step0, ens->n_steps))) return rc;
     fill_depgrid(p, *dep_grid);
     p.refill_every = ens->launch.refill_every;
     p.refill_min = ens->launch.refill_min;
@@ -197,29 +201,37 @@ int lpm_step_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_fi
     p.scen = (const lpm::DevScen*)ens->table;
     p.n_scen = ens->n_scen;
     p.dep = dep; p.ledger = ledgers; p.ctrl = ctrl;
+    if (plan) *plan = 0;
     if (p.i_hi <= 0) return LPM_OK;
     // wet deposition, or dry deposition of any scenario (v_d is per scenario
     // and only known to the device table here), selects the depositing variant
     const bool dep_any = p.L0 > 0.0f || ph->h_s > 0.0;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(lpm::clear_queue, dim3(1), dim3(64), 0, s, ctrl);
+    if (!plan) hipLaunchKernelGGL(lpm::clear_queue, dim3(1), dim3(64), 0, s, ctrl);
     const int bpc = ens->launch.blocks_per_cu;
     const bool time = fld->nt > 1;
     switch (ens->launch.block) {
     case 128:
         launch_ensemble<128>(fld->ncomp, time, ph->n_nuc, ph->kz_kind, dep_any,
-                             (unsigned)((p.i_hi + 127) / 128), s, p, bpc);
+                             (unsigned)((p.i_hi + 127) / 128), s, p, bpc, plan);
         break;
     case 512:
         launch_ensemble<512>(fld->ncomp, time, ph->n_nuc, ph->kz_kind, dep_any,
-                             (unsigned)((p.i_hi + 511) / 512), s, p, bpc);
+                             (unsigned)((p.i_hi + 511) / 512), s, p, bpc, plan);
         break;
     default:
         launch_ensemble<256>(fld->ncomp, time, ph->n_nuc, ph->kz_kind, dep_any,
-                             (unsigned)((p.i_hi + 255) / 256), s, p, bpc);
+                             (unsigned)((p.i_hi + 255) / 256), s, p, bpc, plan);
         break;
     }
-    return hip_status("lpm_step_ensemble");
+    return plan ? LPM_OK : hip_status("lpm_step_ensemble");
+}
+
+int lpm_step_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_field* fld,
+                      const lpm_physics* ph, const lpm_grid* dep_grid, double* dep,
+                      double* ledgers, uint32_t* ctrl, lpm_stream stream)
+{
+    return step_ensemble_impl(st, ens, fld, ph, dep_grid, dep, ledgers, ctrl, stream, nullptr);
 }
 
 int lpm_autotune_ensemble(const lpm_state* st, lpm_ensemble* ens, const lpm_scenario* scen,
@@ -254,6 +266,32 @@ int lpm_autotune_ensemble(const lpm_state* st, lpm_ensemble* ens, const lpm_scen
     int rc = lpm_ensemble_prepare(scen, ens->n_scen, st, ph, ens->step0, trial_steps, ens->table,
                                   (int64_t)ens->n_scen * LPM_SCENARIO_BYTES, &trial, stream);
     if (rc) return rc;
+    // Settings that launch alike (the same block size and schedule on the
+    // same number of resident blocks: a wave count at or above what fits is
+    // "as many as fit") are timed once, as the first of them.
+    {
+        unsigned grid_of[5 * 3 * 3];
+        int kept = 0;
+        for (int c = 0; c < n_cand && !rc; ++c) {
+            trial.launch = cand[c];
+            rc = step_ensemble_impl(st, &trial, fld, ph, dep_grid, dep, ledgers, ctrl, stream,
+                                    &grid_of[kept]);
+            bool dup = false;
+            for (int j = 0; j < kept && !rc; ++j)
+                dup |= cand[j].refill_every == cand[c].refill_every &&
+                       cand[j].refill_min == cand[c].refill_min &&
+                       cand[j].block == cand[c].block && grid_of[j] == grid_of[kept];
+            if (!rc && !dup) cand[kept++] = cand[c];
+        }
+        n_cand = kept;
+    }
+    if (rc) {
+        lpm_ensemble again;
+        (void)lpm_ensemble_prepare(scen, ens->n_scen, st, ph, ens->step0, ens->n_steps,
+                                   ens->table, (int64_t)ens->n_scen * LPM_SCENARIO_BYTES, &again,
+                                   stream);
+        return rc;
+    }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return hip_status("lpm_autotune_ensemble");
     if (hipEventCreate(&e1) != hipSuccess) {

@@ -27,6 +27,8 @@ int fill_field(lpm::StepConst& p, const lpm_field* f);
 void fill_source(lpm::StepConst& p, const lpm_source* src, const lpm_schedule* sch,
                  const lpm_physics* ph);
 void fill_physics(lpm::StepConst& p, const lpm_physics* ph);
+int check_field_steps(const lpm::StepConst& p, const lpm_field* f, long long step0,
+                      long long n_steps);
 void fill_depgrid(lpm::StepConst& p, const lpm_grid& dg);
 void activity_coefficients(const lpm_physics* ph, double bc[4][4]);
 
@@ -53,9 +55,12 @@ void launch_plain(bool lev, int nnuc, int kz, bool dep, unsigned nb, hipStream_t
                   const lpm::StepConst& p, int blocks_per_cu);
 
 // Ensemble step launch with `block` threads per block (128, 256 or 512);
-// defined, one block size per unit, in lpm_step_ensemble.hip.
+// defined, one block size per unit, in lpm_step_ensemble.hip.  With `plan`
+// nothing is launched: *plan receives the number of blocks the launch
+// would take.
 template <int BLOCK>
 void launch_ensemble(int ncomp, bool time, int nnuc, int kz, bool dep, unsigned nb,
-                     hipStream_t s, const lpm::StepConst& p, int blocks_per_cu);
+                     hipStream_t s, const lpm::StepConst& p, int blocks_per_cu,
+                     unsigned* plan = nullptr);
 
 }  // namespace lpm_host

@@ -595,6 +595,8 @@ int lpm_receptor_adjoint(const float* rec, int64_t rec_stride, int32_t rec_every
         return fail(LPM_EINVAL, "the adjoint covers kz_kind 0..2 and mass-depletion deposition");
     lpm::StepConst p;
     memset(&p, 0, sizeof p);
+    if (fld && fld->layout != LPM_FIELD_NODES)
+        return fail(LPM_EINVAL, "the adjoint takes fields in the node layout");
     if ((rc = fill_field(p, fld))) return rc;
     const unsigned nb_cap = adjoint_capacity_blocks(sch->n_local);
     const long long T = (long long)nb_cap * lpm::kBlock;

@@ -6,6 +6,7 @@ from __future__ import annotations
 
 import ctypes
 
+from fractions import Fraction
 from typing import Callable, Iterable, Optional
 
 import numpy as np
@@ -16,7 +17,8 @@ from . import (Accum, Field, Grid, Physics, Receptors, Schedule, Scenario, Sourc
                adjoint_workspace, autotune_ensemble, ensemble_prepare, grid_concentration,
                grid_deposition, grid_records, grid_records_workspace, read_ledger, receptor_adjoint,
                receptor_concentration, release_ensemble, release_particles, step_ensemble,
-               step_particles, step_particles_record, check)
+               step_particles, step_particles_record, check, field_interval,
+               field_interval_bytes)
 
 
 def make_source(src) -> Source:
@@ -133,9 +135,33 @@ class DeviceRun:
         return out
 
     def step_record(self, step0: int, n_steps: int, rec_step0: int, rec_every: int,
-                    n_rec: int, rec: torch.Tensor):
-        step_particles_record(self.st, self.src, self.sch, self.fld, self.ph, step0, n_steps,
-                              self.acc, rec_step0, rec_every, n_rec, rec, self.rec_stride)
+                    n_rec: int, rec: torch.Tensor, fld: Optional[Field] = None):
+        step_particles_record(self.st, self.src, self.sch, self.fld if fld is None else fld,
+                              self.ph, step0, n_steps, self.acc, rec_step0, rec_every, n_rec,
+                              rec, self.rec_stride)
+
+    def time_node(self, s: int) -> int:
+        """Lower time node of the wind for step s, taken as the library
+        takes it (FP64 s * (dt / dt_field) - t0 / dt_field, fused, clamped
+        to the field's nodes)."""
+        f, dt = self.fld, float(self.case.physics.dt)
+        if f.nt < 2:
+            return 0
+        ft_step = dt * (1.0 / f.dt_field)
+        ft = float(Fraction(s) * Fraction(ft_step) + Fraction(-f.t0 / f.dt_field))
+        ft = min(max(ft, 0.0), float(f.nt - 1))
+        return min(int(ft), f.nt - 2)
+
+    def interval_field(self, k: int) -> Field:
+        """Time-pair copy of wind interval k (lpm_field_interval), in a
+        buffer kept between calls."""
+        if getattr(self, "_interval_k", None) != k:
+            if getattr(self, "_interval_buf", None) is None:
+                self._interval_buf = torch.empty(field_interval_bytes(self.fld) // 4,
+                                                 dtype=torch.float32, device=self.device)
+            self._interval_fld = field_interval(self.fld, k, self._interval_buf)
+            self._interval_k = k
+        return self._interval_fld
 
     @property
     def rec_stride(self) -> int:
@@ -164,7 +190,7 @@ class DeviceRun:
 
     def run_recorded(self, every: int, window: Optional[int] = None,
                      out: Optional[torch.Tensor] = None, on_window: Optional[Callable] = None,
-                     step_events: Optional[list] = None):
+                     step_events: Optional[list] = None, time_pairs: bool = True):
         """The whole run as the benchmark runs it: release, step and grid in
         windows of ``window`` steps (a multiple of ``every``; the whole run by
         default).  Each window is one step launch that records the state
@@ -173,8 +199,11 @@ class DeviceRun:
         particle of a launch on the same pair of hourly wind fields.
         ``on_window(w0, rec, n_rec)`` sees each window's record buffer before
         it is reused; ``step_events`` (a list) receives a pair of timing events
-        around each step launch, recorded on the current stream.  Returns
-        ``out`` ([n_out][n_nuc][nz][ny][nx], float)."""
+        around each step launch, recorded on the current stream.  With
+        ``time_pairs`` a window whose steps all interpolate in one interval
+        of a time-dependent wind steps on the time-pair copy of that interval
+        (same results, fewer cache lines per wind stencil).  Returns ``out``
+        ([n_out][n_nuc][nz][ny][nx], float)."""
         S = self.case.n_steps
         window = S if window is None else window
         if window % every or S % window:
@@ -188,11 +217,16 @@ class DeviceRun:
         work = self._grid_work(S - window + every - 1, every, n_rec)
         for w0 in range(0, S, window):
             self.release(w0, window)
+            fld = None
+            if time_pairs and self.fld.nt > 1 and self.fld.nx > 1:
+                k = self.time_node(w0)
+                if self.time_node(w0 + window - 1) == k:
+                    fld = self.interval_field(k)
             if step_events is not None:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(torch.cuda.current_stream())
-            self.step_record(w0, window, w0 + every - 1, every, n_rec, rec)
+            self.step_record(w0, window, w0 + every - 1, every, n_rec, rec, fld)
             if step_events is not None:
                 e1.record(torch.cuda.current_stream())
                 step_events.append((e0, e1))

@@ -229,3 +229,40 @@ def test_record_gridding_workspace_and_rejections(args):
     assert call(C.c_void_p(0x10010), n.value, fake) == L.LPM_EINVAL  # not 256-byte aligned
     assert call(None, n.value, fake) == L.LPM_EINVAL
     assert call(fake, n.value, None) == L.LPM_EINVAL
+
+
+def test_time_pair_fields_are_checked(args):
+    """lpm_field_interval_bytes / lpm_field_interval and time-pair fields in
+    step calls: sizes, and every invalid use rejected before a launch."""
+    L, st, src, sch, ph, fld, acc, grid = args
+    hourly = L.Field.from_buffer_copy(fld)
+    hourly.nt = 3
+    n = C.c_int64(0)
+    assert code(L, "lpm_field_interval_bytes", hourly, C.byref(n)) == L.LPM_OK
+    assert n.value == 200 * 200 * 30 * 16
+    three = L.Field.from_buffer_copy(hourly)
+    three.ncomp = 3
+    assert code(L, "lpm_field_interval_bytes", three, C.byref(n)) == L.LPM_OK
+    assert n.value == 200 * 200 * 30 * 32
+    assert code(L, "lpm_field_interval_bytes", fld, C.byref(n)) == L.LPM_EINVAL  # nt = 1
+    packed = L.Field()
+    out = C.c_void_p(0x40000000)
+    pack = lambda f, k, o=out: code(L, "lpm_field_interval", f, k, o, C.byref(packed), None)
+    assert pack(hourly, 2) == L.LPM_EINVAL and b"interval" in L.lib().lpm_last_error()
+    assert pack(hourly, -1) == L.LPM_EINVAL
+    assert pack(hourly, 0, C.c_void_p(0x40000008)) == L.LPM_EINVAL  # 16-byte alignment
+    assert pack(hourly, 0, C.c_void_p(fld.data + 64)) == L.LPM_EINVAL
+    assert b"overlaps" in L.lib().lpm_last_error()
+    # a time-pair descriptor in step calls
+    tp = L.Field.from_buffer_copy(hourly)
+    tp.layout, tp.interval = L.FIELD_TIME_PAIRS, 1
+    step = lambda f, s0, n: code(L, "lpm_step_particles", st, src, sch, f, ph, s0, n, acc, None)
+    assert step(tp, 0, 10) == L.LPM_EINVAL  # steps 0..9 interpolate in interval 0
+    assert b"interpolate in field interval 1" in L.lib().lpm_last_error()
+    assert step(tp, 715, 10) == L.LPM_EINVAL  # steps 715..724 straddle t = 1 h
+    for bad in (dict(interval=2), dict(interval=-1), dict(nx=1), dict(layout=7),
+                dict(data=fld.data + 8)):
+        f = L.Field.from_buffer_copy(tp)
+        for k, v in bad.items():
+            setattr(f, k, v)
+        assert step(f, 720, 10) == L.LPM_EINVAL, bad

@@ -84,8 +84,10 @@ def test_autotuner_changes_no_result():
     log("autotune: refill %d/%d lanes, block %d, blocks/cu %d, median %.3f ms, worst %.3f ms "
         "(%d tried, %d reps)" % (t.launch.refill_every, t.launch.refill_min, t.launch.block,
                                  t.launch.blocks_per_cu, t.best_ms, t.worst_ms, t.n_tried, t.reps))
-    # 5 queue schedules x (128: 3, 256: 3, 512: 2 distinct occupancies)
-    assert t.n_tried == 40 and t.reps == 3 and t.best_ms <= t.worst_ms
+    # 5 queue schedules x 3 block sizes x up to 3 resident-wave settings;
+    # settings that launch alike are timed once (this small trial fills
+    # fewer blocks than any setting allows: one launch per schedule and size)
+    assert t.n_tried == 15 and t.reps == 3 and t.best_ms <= t.worst_ms
     assert e.ens.launch.as_tuple() == t.launch.as_tuple()
     assert t.launch.block in (128, 256, 512)
     e.run()

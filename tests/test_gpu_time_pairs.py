@@ -1,0 +1,112 @@
+"""Time-pair copies of wind intervals (lpm_field_interval): the copy holds
+the field's two times of each node side by side, and hour-long windows that
+step on the copies give the records, states and grids of the same windows on
+the field itself, bitwise, for two- and three-component winds."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import synth
+from parity import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _case(ncomp: int):
+    """4 hourly 400 x 400 x 40 fields, 3 h, 3e4 particles released over the
+    first hour; ncomp 3 adds a vertical wind of 1 % of u."""
+    case = synth.c2(n_total=30_000, n_steps=2160, s_release=720, n_hours=4)
+    if ncomp == 3:
+        d = case.field.data
+        w = (0.01 * d[..., :1]).astype(np.float32)
+        case = case.with_(field=replace(case.field, data=np.ascontiguousarray(
+            np.concatenate([d, w], axis=4))))
+    return case
+
+
+@pytest.mark.parametrize("ncomp", [2, 3])
+def test_interval_copy_layout(ncomp):
+    import torch
+    import paper_0912_3223_amd as L
+    case = _case(ncomp)
+    run = L.DeviceRun(case)
+    f = case.field
+    nodes = f.nz * f.ny * f.nx
+    for k in (0, 2):
+        packed = run.interval_field(k)
+        assert packed.layout == L.FIELD_TIME_PAIRS and packed.interval == k
+        assert packed.nt == f.nt and packed.t0 == f.t0
+        got = run._interval_buf.cpu().numpy().reshape(nodes, 2, -1)
+        rec = got.shape[2]
+        assert rec == (2 if ncomp == 2 else 4)
+        a = f.data[k].reshape(nodes, ncomp)
+        b = f.data[k + 1].reshape(nodes, ncomp)
+        np.testing.assert_array_equal(got[:, 0, :ncomp], a)
+        np.testing.assert_array_equal(got[:, 1, :ncomp], b)
+        if rec > ncomp:
+            assert not got[:, :, ncomp:].any()
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("ncomp", [2, 3])
+def test_windows_on_time_pairs_equal_the_field(ncomp):
+    import torch
+    import paper_0912_3223_amd as L
+    case = _case(ncomp)
+    out = {}
+    for tp in (False, True):
+        run = L.DeviceRun(case)
+        recs = []
+        grids = run.run_recorded(60, 720, time_pairs=tp,
+                                 on_window=lambda w0, rec, n_rec: recs.append(rec.clone()))
+        run.check()
+        out[tp] = dict(state=run.state(), grids=grids.double().cpu().numpy(), recs=recs,
+                       dep=run.grid_deposition().double().cpu().numpy(), led=run.ledger(),
+                       used=getattr(run, "_interval_k", None))
+    a, b = out[False], out[True]
+    assert a["used"] is None and b["used"] == 2  # the last window's interval
+    for key in ("x", "y", "z", "m", "xl", "yl"):
+        np.testing.assert_array_equal(a["state"][key], b["state"][key])
+    # records: the meaningful ones (born by the output step, still active
+    # after it) and every particle's `last`
+    n, sch = case.schedule.local_count, case.schedule
+    birth = torch.from_numpy((sch.id_base + np.arange(n) * sch.id_stride) * sch.s_release
+                             // sch.n_total).cuda()
+    for w, (ra, rb) in enumerate(zip(a["recs"], b["recs"])):
+        la, lb = ra[48 * n: 49 * n].view(torch.int32), rb[48 * n: 49 * n].view(torch.int32)
+        assert torch.equal(la, lb)
+        for k in range(12):
+            s = 720 * w + 60 * k + 59
+            use = (birth <= s) & (s < la)
+            va, vb = ra[: 48 * n].view(12, n, 4)[k], rb[: 48 * n].view(12, n, 4)[k]
+            assert torch.equal(va[use], vb[use]), (w, k)
+    # grids and deposition: the same float32 contributions, FP64 sums in
+    # the order the atomics arrive
+    np.testing.assert_allclose(b["grids"], a["grids"], rtol=1e-6, atol=0)
+    np.testing.assert_allclose(b["dep"], a["dep"], rtol=1e-6, atol=0)
+    np.testing.assert_allclose(b["led"], a["led"], rtol=1e-12, atol=0)
+    log("time pairs ncomp %d: %d airborne at the end, records of %d windows equal"
+        % (ncomp, int((b["state"]["m"] > 0).sum()), len(b["recs"])))
+
+
+def test_steps_outside_the_interval_are_rejected():
+    import paper_0912_3223_amd as L
+    case = _case(2)
+    run = L.DeviceRun(case)
+    packed = run.interval_field(1)
+    rec = run.record_buffer(1)
+    run.release(0, 720)
+    with pytest.raises(L.LpmError) as e:
+        run.step_record(660, 60, 719, 60, 1, rec, packed)  # steps of interval 0
+    assert e.value.code == L.LPM_EINVAL
+    run.step_record(0, 720, 719, 720, 1, rec)  # the field itself takes them
+    run.step_record(720, 60, 779, 60, 1, rec, packed)
+    run.check()
