@@ -381,13 +381,17 @@ typedef struct {
 
 /* Launch settings of later plain step launches (lpm_step_particles[_record])
  * in this process: refill interval, blocks per compute unit and idle lanes
- * before a refill (defaults 24, 0 and 56).  This setting is the library's
+ * before a refill (defaults 24, 0 and 0; refill_min 0 lets the wind decide:
+ * 56 idle lanes on a steady field, 40 on a field interpolated in time, the
+ * faster settings on the 6 h steady and the 24 h hourly workloads, which
+ * differ in how long particles stay).  This setting is the library's
  * only mutable process-wide state; it is read atomically at each launch, so
  * a call from another thread affects launches made after it returns.
  * Ensemble launches carry their own settings in lpm_ensemble. */
 int lpm_set_launch(int32_t refill_every, int32_t blocks_per_cu);
 
-/* lpm_set_launch with the number of idle lanes before a refill. */
+/* lpm_set_launch with the number of idle lanes before a refill (1 .. 64, or
+ * 0 for the default that depends on the wind). */
 int lpm_set_launch_ex(int32_t refill_every, int32_t blocks_per_cu, int32_t refill_min);
 
 /* ---------------------------------------------------------------------------

@@ -372,7 +372,9 @@ def surface_layer(U: float, z_ref: float, z0: float, dtheta: float, T0: float):
     return us.value, il.value
 
 
-def set_launch(refill_every: int = 24, blocks_per_cu: int = 0, refill_min: int = 56):
+def set_launch(refill_every: int = 24, blocks_per_cu: int = 0, refill_min: int = 0):
+    """Plain step launch settings (refill_min 0: the library's default for
+    the wind of each launch)."""
     _rc(_lib.lpm_set_launch_ex(refill_every, blocks_per_cu, refill_min))
 
 

@@ -660,8 +660,13 @@ thread_local char g_msg[kMsgLen] = "";
 
 // Launch settings of plain step launches: the library's only mutable
 // process-wide state (lpm_set_launch), read atomically at each launch.
+// Idle lanes before a refill when none is set: particles stay longer in the
+// hourly 24 h workload than in the steady 6 h one, where waiting for nearly
+// all lanes keeps the lanes of a wave on the same branches.
+constexpr int kRefillMinSteady = 56;
+constexpr int kRefillMinTime = 40;
 std::atomic<int> g_refill_every{24};
-std::atomic<int> g_refill_min{56};
+std::atomic<int> g_refill_min{0};    // 0: by the wind (kRefillMinSteady / kRefillMinTime)
 std::atomic<int> g_blocks_per_cu{0};  // 0: as many as the device holds
 
 lpm_launch plain_launch()
@@ -849,9 +854,9 @@ int lpm_set_launch(int32_t refill_every, int32_t blocks_per_cu)
 int lpm_set_launch_ex(int32_t refill_every, int32_t blocks_per_cu, int32_t refill_min)
 {
     g_msg[0] = 0;
-    if (refill_every < 1 || refill_every > 4096 || blocks_per_cu < 0 || refill_min < 1 ||
+    if (refill_every < 1 || refill_every > 4096 || blocks_per_cu < 0 || refill_min < 0 ||
         refill_min > 64)
-        return fail(LPM_EINVAL, "refill_every in [1, 4096], blocks_per_cu >= 0, refill_min in [1, 64]");
+        return fail(LPM_EINVAL, "refill_every in [1, 4096], blocks_per_cu >= 0, refill_min in [0, 64]");
     g_refill_every = refill_every;
     g_blocks_per_cu = blocks_per_cu;
     g_refill_min = refill_min;
@@ -1179,7 +1184,7 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
     if ((rc = fill_field(p, fld))) return rc;
     const lpm_launch lc = plain_launch();
     p.refill_every = lc.refill_every;
-    p.refill_min = lc.refill_min;
+    p.refill_min = lc.refill_min ? lc.refill_min : (fld->nt > 1 ? kRefillMinTime : kRefillMinSteady);
     p.rec = n_rec > 0 ? rec : nullptr;
     p.rec_stride = rec_stride;
     p.rec_step0 = rec_step0;

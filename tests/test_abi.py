@@ -266,3 +266,16 @@ def test_time_pair_fields_are_checked(args):
         for k, v in bad.items():
             setattr(f, k, v)
         assert step(f, 720, 10) == L.LPM_EINVAL, bad
+
+
+def test_launch_settings_are_checked():
+    import paper_0912_3223_amd as L
+    lib = L.lib()
+    assert lib.lpm_set_launch_ex(24, 0, -1) == L.LPM_EINVAL
+    assert lib.lpm_set_launch_ex(24, 0, 65) == L.LPM_EINVAL
+    assert lib.lpm_set_launch_ex(0, 0, 0) == L.LPM_EINVAL
+    assert lib.lpm_set_launch_ex(4097, 0, 0) == L.LPM_EINVAL
+    assert lib.lpm_set_launch_ex(24, -1, 0) == L.LPM_EINVAL
+    assert lib.lpm_set_launch_ex(16, 2, 32) == L.LPM_OK
+    assert lib.lpm_set_launch(24, 0) == L.LPM_OK  # keeps refill_min 32
+    L.set_launch()  # the defaults: 24, 0, and the idle-lane threshold by the wind
