@@ -88,6 +88,13 @@ typedef struct {
     int64_t capacity; /* elements of each array */
     float* x_lo;
     float* y_lo;
+    /* Optional work order of the next step launch (NULL: index order): the
+     * permutation of the launch's local indices [0, n_order) that
+     * lpm_order_particles writes; n_order must be the launch's particle
+     * count.  The order changes no result, only the speed.  Ensemble
+     * launches take no order. */
+    const int32_t* order;
+    int64_t n_order;
 } lpm_state;
 
 /* Point source of one release scenario (Sec. 2).  q: release rate in
@@ -270,6 +277,27 @@ int lpm_grid_concentration(const lpm_state* st, const lpm_source* src,
                            const lpm_schedule* sch, const lpm_physics* ph,
                            const lpm_grid* grid, int32_t step,
                            double* acc_scratch, float* out, lpm_stream stream);
+
+/* *bytes (host) = the device workspace lpm_order_particles needs for this
+ * field: two 8-byte words per wind-grid node and a few for the scan. */
+int lpm_order_workspace(const lpm_field* fld, int64_t* bytes);
+
+/* Particles never interact (Sec. 3.2), so the order in which a step launch
+ * takes them changes no result; it decides how much the lanes of a wave
+ * share wind stencils in the caches.  For the step launch over [step0,
+ * step0 + n_steps), whose particles are the local indices [0, n) born
+ * before its end, order (device int32[order_capacity], caller-owned;
+ * LPM_EINVAL if n exceeds order_capacity) receives in its first n entries: the
+ * particles active at step0 grouped by the wind node they are at (by
+ * column, j then i, and by level within a column; clamped to the grid;
+ * nonuniform levels: by column only), then the particles born in the
+ * window in index order, then the inactive ones.  *n_order (host) = n,
+ * computed on the host.  Put order and n into st->order and st->n_order of
+ * that launch.  work: device scratch of lpm_order_workspace bytes, 8-byte
+ * aligned.  n < 2^31.  Stream-ordered. */
+int lpm_order_particles(const lpm_state* st, const lpm_schedule* sch, const lpm_field* fld,
+                        int32_t step0, int32_t n_steps, int32_t* order, int64_t order_capacity,
+                        int64_t* n_order, void* work, int64_t work_bytes, lpm_stream stream);
 
 /* *bytes (host) = the size of the time-pair copy of one interval of fld
  * (lpm_field_interval): nz * ny * nx nodes of 16 bytes (ncomp 2) or 32

@@ -35,7 +35,8 @@ class LpmError(RuntimeError):
 
 class State(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("m", C.c_void_p),
-                ("capacity", C.c_int64), ("x_lo", C.c_void_p), ("y_lo", C.c_void_p)]
+                ("capacity", C.c_int64), ("x_lo", C.c_void_p), ("y_lo", C.c_void_p),
+                ("order", C.c_void_p), ("n_order", C.c_int64)]
 
 
 class Source(C.Structure):
@@ -152,6 +153,10 @@ def _load():
                                        C.c_void_p, C.c_void_p],
         "lpm_adjoint_workspace": [P(Field), P(Schedule), C.c_int32, P(C.c_int64)],
         "lpm_field_interval_bytes": [P(Field), P(C.c_int64)],
+        "lpm_order_workspace": [P(Field), P(C.c_int64)],
+        "lpm_order_particles": [P(State), P(Schedule), P(Field), C.c_int32, C.c_int32,
+                                C.c_void_p, C.c_int64, P(C.c_int64), C.c_void_p, C.c_int64,
+                                C.c_void_p],
         "lpm_field_interval": [P(Field), C.c_int32, C.c_void_p, P(Field), C.c_void_p],
         "lpm_surface_layer": [C.c_double] * 5 + [P(C.c_double), P(C.c_double)],
         "lpm_receptor_adjoint": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, P(Source),
@@ -179,6 +184,7 @@ EXPORTS = ("lpm_accum_reset", "lpm_release_particles", "lpm_step_particles",
            "lpm_release_ensemble", "lpm_step_ensemble", "lpm_autotune_ensemble",
            "lpm_receptor_concentration", "lpm_adjoint_workspace", "lpm_receptor_adjoint",
            "lpm_surface_layer", "lpm_field_interval_bytes", "lpm_field_interval",
+           "lpm_order_workspace", "lpm_order_particles",
            "lpm_last_error", "lpm_version")
 
 
@@ -245,6 +251,25 @@ def grid_concentration_static(st: State, src: Source, sch: Schedule, ph: Physics
 
 
 FIELD_NODES, FIELD_TIME_PAIRS = 0, 1
+
+
+def order_workspace(fld: Field) -> int:
+    n = C.c_int64(0)
+    _rc(_lib.lpm_order_workspace(C.byref(fld), C.byref(n)))
+    return n.value
+
+
+def order_particles(st: State, sch: Schedule, fld: Field, step0: int, n_steps: int,
+                    order: torch.Tensor, work: torch.Tensor, stream=None) -> int:
+    """Work order of the step launch over [step0, step0 + n_steps) into
+    ``order`` (int32); returns its length."""
+    assert order.dtype == torch.int32 and order.is_contiguous()
+    n = C.c_int64(0)
+    _rc(_lib.lpm_order_particles(C.byref(st), C.byref(sch), C.byref(fld), step0, n_steps,
+                                 C.c_void_p(order.data_ptr()), order.numel(), C.byref(n),
+                                 C.c_void_p(work.data_ptr()), work.numel() * work.element_size(),
+                                 _stream(stream)))
+    return n.value
 
 
 def field_interval_bytes(fld: Field) -> int:

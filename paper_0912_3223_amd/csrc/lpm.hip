@@ -506,6 +506,82 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(unsigned long long* 
         }
 }
 
+// Work order of a step launch: a counting sort of the particles by the wind
+// node they are at.  Bins: node (j nx + i) nz + k of the particles active at
+// the launch's first step, then one bin of the particles born in the window
+// (kept in index order), then one of the inactive ones.
+struct OrderConst {
+    const float* X;
+    const float* Y;
+    const float* Z;
+    const float* M;
+    long long n_old;   // local indices born before the first step: [0, n_old)
+    long long n_all;   // the launch's particles: [0, n_all)
+    float fcx, fcy, inv_dx, inv_dy, inv_dz;  // node i = floor(x inv_dx + fcx); inv_dz 0: k = 0
+    int nx, ny, nz;
+    long long nbin;
+    unsigned long long* cur;  // counts, then (after the scan) running offsets
+    const unsigned long long* off;  // bin starts (after the scan)
+    int* order;
+};
+
+__device__ __forceinline__ long long order_bin(const OrderConst& o, long long i)
+{
+    if (!(as_global(o.M)[i] > 0.0f)) return o.nbin - 1;
+    const int ix = min(max((int)floorf(fmaf(as_global(o.X)[i], o.inv_dx, o.fcx)), 0), o.nx - 1);
+    const int iy = min(max((int)floorf(fmaf(as_global(o.Y)[i], o.inv_dy, o.fcy)), 0), o.ny - 1);
+    const int iz = o.inv_dz > 0.0f
+                       ? min(max((int)floorf(as_global(o.Z)[i] * o.inv_dz), 0), o.nz - 1)
+                       : 0;
+    return ((long long)iy * o.nx + ix) * o.nz + iz;
+}
+
+// The inactive particles of a wave share one bin: one atomic per wave.
+__device__ __forceinline__ unsigned long long wave_claim(unsigned long long* counter, bool want)
+{
+    const unsigned long long mask = __ballot(want);
+    if (!mask) return 0ull;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    return base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
+}
+
+__global__ __launch_bounds__(kBlock) void order_count_kernel(const OrderConst o)
+{
+    const long long stride = (long long)gridDim.x * kBlock;
+    // whole waves iterate together (the wave claim needs every lane)
+    for (long long i0 = (long long)blockIdx.x * kBlock; i0 < o.n_old; i0 += stride) {
+        const long long i = i0 + threadIdx.x;
+        const long long bin = i < o.n_old ? order_bin(o, i) : -1;
+        const bool dead = bin == o.nbin - 1;
+        (void)wave_claim(o.cur + o.nbin - 1, dead);
+        if (bin >= 0 && !dead) atomicAdd(o.cur + bin, 1ull);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        atomicAdd(o.cur + o.nbin - 2, (unsigned long long)(o.n_all - o.n_old));
+}
+
+__global__ __launch_bounds__(kBlock) void order_scatter_kernel(const OrderConst o)
+{
+    const long long stride = (long long)gridDim.x * kBlock;
+    auto order = as_global(o.order);
+    for (long long i0 = (long long)blockIdx.x * kBlock; i0 < o.n_all; i0 += stride) {
+        const long long i = i0 + threadIdx.x;
+        const long long bin = i < o.n_old ? order_bin(o, i) : -1;
+        const bool dead = bin == o.nbin - 1;
+        const unsigned long long pd = wave_claim(o.cur + o.nbin - 1, dead);
+        if (i >= o.n_all) continue;
+        long long pos;
+        if (dead) pos = (long long)pd;
+        else if (bin >= 0) pos = (long long)atomicAdd(o.cur + bin, 1ull);
+        else pos = (long long)as_global(o.off)[o.nbin - 2] + (i - o.n_old);
+        order[pos] = (int)i;
+    }
+}
+
 // Pass 4: one block per (owner tile, output step).  LDS: the tile's cells,
 // double [NNUC][nz][ps] (ty tx cells per level, padded).
 constexpr int kTileBatch = 4;
@@ -720,6 +796,7 @@ int check_state(const lpm_state* st, const lpm_schedule* sch)
         return fail(LPM_EINVAL, "x_lo and y_lo: both or neither");
     if (!aligned4(st->x_lo) || !aligned4(st->y_lo))
         return fail(LPM_EINVAL, "residual arrays must be 4-byte aligned");
+    if (!aligned4(st->order)) return fail(LPM_EINVAL, "work order must be 4-byte aligned");
     if (sch->n_total <= 0 || sch->n_total > 0xFFFFFFFFll)
         return fail(LPM_EINVAL, "n_total must be in [1, 2^32)");
     if (sch->s_release <= 0) return fail(LPM_EINVAL, "s_release must be positive");
@@ -1198,6 +1275,12 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
     p.step0 = step0;
     p.step_end = step0 + n_steps;
     p.i_hi = first_local_born_at_or_after(sch, (long long)p.step_end);
+    if (st->order) {
+        if (st->n_order != p.i_hi)
+            return fail(LPM_EINVAL, "work order of %lld particles for a launch of %lld",
+                        (long long)st->n_order, p.i_hi);
+        p.order = st->order;
+    }
 
     fill_source(p, src, sch, ph);
     fill_physics(p, ph);
@@ -1563,6 +1646,81 @@ int lpm_grid_deposition(const lpm_accum* acc, float* out, lpm_stream stream)
     hipLaunchKernelGGL(lpm::to_f32, dim3(fb), dim3(lpm::kBlock), 0, (hipStream_t)stream, acc->dep,
                        out, total, 1.0);
     return hip_status("lpm_grid_deposition");
+}
+
+// Work-order bins of a field: nodes (uniform levels) or columns, and two more.
+static long long order_bins(const lpm_field* fld)
+{
+    return (long long)fld->nx * fld->ny * (fld->z_levels ? 1 : fld->nz) + 2;
+}
+
+static long long order_scan_blocks(long long nbin)
+{
+    return (nbin + lpm::kScanChunk - 1) / lpm::kScanChunk;
+}
+
+int lpm_order_workspace(const lpm_field* fld, int64_t* bytes)
+{
+    g_msg[0] = 0;
+    if (!fld || !bytes) return fail(LPM_EINVAL, "null argument");
+    if (fld->nx < 1 || fld->ny < 1 || fld->nz < 1) return fail(LPM_EINVAL, "bad field shape");
+    const long long nbin = order_bins(fld);
+    *bytes = (int64_t)(8 * (2 * nbin + order_scan_blocks(nbin)));
+    return LPM_OK;
+}
+
+int lpm_order_particles(const lpm_state* st, const lpm_schedule* sch, const lpm_field* fld,
+                        int32_t step0, int32_t n_steps, int32_t* order, int64_t order_capacity,
+                        int64_t* n_order, void* work, int64_t work_bytes, lpm_stream stream)
+{
+    g_msg[0] = 0;
+    int rc = check_state(st, sch);
+    if (rc) return rc;
+    if (!fld || !order || !n_order || !work) return fail(LPM_EINVAL, "null argument");
+    if (fld->nx < 1 || fld->ny < 1 || fld->nz < 1) return fail(LPM_EINVAL, "bad field shape");
+    if (!(fld->dx > 0 && fld->dy > 0 && (fld->z_levels || fld->dz > 0)))
+        return fail(LPM_EINVAL, "field spacings must be positive");
+    if (step0 < 0 || n_steps < 1 || (long long)step0 + n_steps > 0x7FFFFFFFll)
+        return fail(LPM_EINVAL, "bad step window");
+    if (!aligned4(order) || ((uintptr_t)work & 7u)) return fail(LPM_EINVAL, "misaligned order or workspace");
+    const long long nbin = order_bins(fld), nscan = order_scan_blocks(nbin);
+    if (work_bytes < 8 * (2 * nbin + nscan))
+        return fail(LPM_EINVAL, "workspace of %lld bytes below the %lld needed",
+                    (long long)work_bytes, 8 * (2 * nbin + nscan));
+    const long long n_all = first_local_born_at_or_after(sch, (long long)step0 + n_steps);
+    if (n_all > 0x7FFFFFFFll) return fail(LPM_EINVAL, "work order of more than 2^31 - 1 particles");
+    if (n_all > order_capacity)
+        return fail(LPM_EINVAL, "work order of %lld particles exceeds its capacity of %lld", n_all,
+                    (long long)order_capacity);
+    *n_order = n_all;
+    if (n_all == 0) return LPM_OK;
+    lpm::OrderConst o;
+    memset(&o, 0, sizeof o);
+    o.X = st->x; o.Y = st->y; o.Z = st->z; o.M = st->m;
+    o.n_old = first_local_born_at_or_after(sch, step0);
+    o.n_all = n_all;
+    o.fcx = (float)(-fld->x0 / fld->dx); o.fcy = (float)(-fld->y0 / fld->dy);
+    o.inv_dx = (float)(1.0 / fld->dx); o.inv_dy = (float)(1.0 / fld->dy);
+    o.inv_dz = fld->z_levels ? 0.0f : (float)(1.0 / fld->dz);
+    o.nx = fld->nx; o.ny = fld->ny; o.nz = fld->z_levels ? 1 : fld->nz;
+    o.nbin = nbin;
+    auto* cur = static_cast<unsigned long long*>(work);
+    auto* off = cur + nbin;
+    auto* bsum = off + nbin;
+    o.cur = cur; o.off = off; o.order = order;
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned fb = blocks_for(nbin) < 8192 ? blocks_for(nbin) : 8192;
+    hipLaunchKernelGGL(lpm::fill_f64, dim3(fb), dim3(lpm::kBlock), 0, s,
+                       reinterpret_cast<double*>(cur), nbin);
+    const unsigned nb = blocks_for(n_all) < 16384 ? blocks_for(n_all) : 16384;
+    hipLaunchKernelGGL(lpm::order_count_kernel, dim3(nb), dim3(lpm::kBlock), 0, s, o);
+    hipLaunchKernelGGL(lpm::scan_sums_kernel, dim3((unsigned)nscan), dim3(lpm::kBlock), 0, s,
+                       (const unsigned long long*)cur, nbin, bsum);
+    hipLaunchKernelGGL(lpm::scan_bsum_kernel, dim3(1), dim3(lpm::kBlock), 0, s, bsum, nscan);
+    hipLaunchKernelGGL(lpm::scan_apply_kernel, dim3((unsigned)nscan), dim3(lpm::kBlock), 0, s,
+                       cur, off, nbin, (const unsigned long long*)bsum);
+    hipLaunchKernelGGL(lpm::order_scatter_kernel, dim3(nb), dim3(lpm::kBlock), 0, s, o);
+    return hip_status("lpm_order_particles");
 }
 
 static int64_t interval_bytes(const lpm_field* fld)

@@ -44,6 +44,7 @@ struct StepConst {
     float* M;
     float* XL;
     float* YL;
+    const int* order;  // work order of the queue, or null: index order
     // schedule
     long long n_total, id_base, id_stride, i_hi;
     int s_release, step0, step_end, pad0;

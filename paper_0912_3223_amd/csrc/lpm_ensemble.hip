@@ -195,6 +195,7 @@ static int step_ensemble_impl(const lpm_state* st, const lpm_ensemble* ens,
     p.XL = st->x_lo; p.YL = st->y_lo;
     if ((p.XL == nullptr) != (p.YL == nullptr))
         return fail(LPM_EINVAL, "x_lo and y_lo: both or neither");
+    if (st->order) return fail(LPM_EINVAL, "ensemble launches take no work order");
     p.step0 = ens->step0;
     p.step_end = ens->step0 + ens->n_steps;
     p.i_hi = ens->queue_len;

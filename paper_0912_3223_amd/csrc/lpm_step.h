@@ -530,12 +530,15 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
                         b = (int)birth(g, ds.s_release, ds.n_total);
                         i = ds.offset + g;                 // element in the state arrays
                     } else {
-                        i = q;
-                        g = p.id_base + q * p.id_stride;
+                        i = p.order ? (long long)as_global(p.order)[q] : q;
+                        // an entry outside the launch (not a permutation)
+                        // takes nothing
+                        if ((unsigned long long)i >= (unsigned long long)p.i_hi) i = -1;
+                        g = p.id_base + i * p.id_stride;
                         b = (int)birth(g, p.s_release, p.n_total);
                     }
                     gid = (uint32_t)g;
-                    m = as_global(p.M)[i];
+                    m = i >= 0 ? as_global(p.M)[i] : 0.0f;
                     if (m > 0.0f) {
                         x = as_global(p.X)[i];
                         y = as_global(p.Y)[i];
@@ -558,7 +561,7 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
                                     __builtin_amdgcn_exp2f(-p.lam_l2e[n] * age0)));
                             }
                         }
-                    } else if (p.n_rec > 0) {
+                    } else if (p.n_rec > 0 && i >= 0) {
                         as_global(rec_exit)[i] = INT_MIN;  // inactive before this window
                     }
                 }

@@ -18,7 +18,7 @@ from . import (Accum, Field, Grid, Physics, Receptors, Schedule, Scenario, Sourc
                grid_deposition, grid_records, grid_records_workspace, read_ledger, receptor_adjoint,
                receptor_concentration, release_ensemble, release_particles, step_ensemble,
                step_particles, step_particles_record, check, field_interval,
-               field_interval_bytes)
+               field_interval_bytes, order_particles, order_workspace)
 
 
 def make_source(src) -> Source:
@@ -135,10 +135,26 @@ class DeviceRun:
         return out
 
     def step_record(self, step0: int, n_steps: int, rec_step0: int, rec_every: int,
-                    n_rec: int, rec: torch.Tensor, fld: Optional[Field] = None):
-        step_particles_record(self.st, self.src, self.sch, self.fld if fld is None else fld,
-                              self.ph, step0, n_steps, self.acc, rec_step0, rec_every, n_rec,
-                              rec, self.rec_stride)
+                    n_rec: int, rec: torch.Tensor, fld: Optional[Field] = None,
+                    st: Optional[State] = None):
+        step_particles_record(self.st if st is None else st, self.src, self.sch,
+                              self.fld if fld is None else fld, self.ph, step0, n_steps,
+                              self.acc, rec_step0, rec_every, n_rec, rec, self.rec_stride)
+
+    def work_order(self, step0: int, n_steps: int) -> State:
+        """The state descriptor for the step launch over [step0, step0 +
+        n_steps) with its particles in wind-node order
+        (lpm_order_particles), in buffers kept between calls."""
+        if getattr(self, "_order", None) is None:
+            self._order = torch.empty(max(self.sch.n_local, 1), dtype=torch.int32,
+                                      device=self.device)
+            self._order_work = torch.empty(order_workspace(self.fld), dtype=torch.uint8,
+                                           device=self.device)
+        n = order_particles(self.st, self.sch, self.fld, step0, n_steps, self._order,
+                            self._order_work)
+        st = State.from_buffer_copy(self.st)
+        st.order, st.n_order = self._order.data_ptr(), n
+        return st
 
     def time_node(self, s: int) -> int:
         """Lower time node of the wind for step s, taken as the library
@@ -190,7 +206,8 @@ class DeviceRun:
 
     def run_recorded(self, every: int, window: Optional[int] = None,
                      out: Optional[torch.Tensor] = None, on_window: Optional[Callable] = None,
-                     step_events: Optional[list] = None, time_pairs: bool = True):
+                     step_events: Optional[list] = None, time_pairs: bool = True,
+                     order: bool = True):
         """The whole run as the benchmark runs it: release, step and grid in
         windows of ``window`` steps (a multiple of ``every``; the whole run by
         default).  Each window is one step launch that records the state
@@ -202,7 +219,9 @@ class DeviceRun:
         around each step launch, recorded on the current stream.  With
         ``time_pairs`` a window whose steps all interpolate in one interval
         of a time-dependent wind steps on the time-pair copy of that interval
-        (same results, fewer cache lines per wind stencil).  Returns ``out``
+        (same results, fewer cache lines per wind stencil); with ``order``
+        each step launch takes its particles in wind-node order (same
+        results; the lanes of a wave share stencils).  Returns ``out``
         ([n_out][n_nuc][nz][ny][nx], float)."""
         S = self.case.n_steps
         window = S if window is None else window
@@ -222,11 +241,12 @@ class DeviceRun:
                 k = self.time_node(w0)
                 if self.time_node(w0 + window - 1) == k:
                     fld = self.interval_field(k)
+            st = self.work_order(w0, window) if order else None
             if step_events is not None:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(torch.cuda.current_stream())
-            self.step_record(w0, window, w0 + every - 1, every, n_rec, rec, fld)
+            self.step_record(w0, window, w0 + every - 1, every, n_rec, rec, fld, st)
             if step_events is not None:
                 e1.record(torch.cuda.current_stream())
                 step_events.append((e0, e1))

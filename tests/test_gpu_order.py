@@ -1,0 +1,111 @@
+"""Work orders (lpm_order_particles): the order is a permutation of the
+launch's particles grouped as documented -- active particles by wind node,
+then those born in the window in index order, then the inactive ones -- and
+windows stepped in that order give the records, states and grids of the
+same windows in index order, bitwise."""
+import numpy as np
+import pytest
+
+import synth
+from parity import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _hourly():
+    """4 hourly 400 x 400 x 40 fields, 3 h, 6e4 particles released over the
+    first 2 h (windows with active, newborn and exited particles)."""
+    return synth.c2(n_total=60_000, n_steps=2160, s_release=1440, n_hours=4)
+
+
+def test_order_groups_particles_by_wind_node():
+    """The 50 km steady-wind domain after 4 h of a 6 h release: particles
+    active, left through the side, and still to be born in the window."""
+    import torch
+    import paper_0912_3223_amd as L
+    case = synth.c1(n_total=60_000, n_steps=4320)
+    run = L.DeviceRun(case)
+    rec = run.record_buffer(24)
+    for w0 in (0, 1440):
+        run.release(w0, 1440)
+        run.step_record(w0, 1440, w0 + 59, 60, 24, rec)
+    run.release(2880, 1440)
+    st = run.work_order(2880, 1440)
+    n = st.n_order
+    sch, f = case.schedule, case.field
+    assert n == sch.local_count  # every particle is born by the end of this window
+    order = run._order[:n].cpu().numpy()
+    assert np.array_equal(np.sort(order), np.arange(n))
+    state = run.state()
+    g = sch.id_base + np.arange(n) * sch.id_stride
+    born_before = (g * sch.s_release) // sch.n_total < 2880
+    alive = born_before & (state["m"] > 0)
+    newborn = ~born_before
+    n_alive, n_new = int(alive.sum()), int(newborn.sum())
+    assert n_alive > 0 and n_new > 0 and (born_before & ~alive).sum() > 0
+    assert alive[order[:n_alive]].all()
+    np.testing.assert_array_equal(order[n_alive:n_alive + n_new], np.flatnonzero(newborn))
+    assert not alive[order[n_alive + n_new:]].any()
+    # node keys (float64 here, fused float32 in the kernel: a particle within
+    # 1e-4 of a node boundary may fall on either side)
+    x, y, z = (state[k][order[:n_alive]] for k in "xyz")
+    fi = (x - f.x0) / f.dx
+    fj = (y - f.y0) / f.dy
+    fk = z / f.dz
+    key = ((np.clip(np.floor(fj), 0, f.ny - 1) * f.nx + np.clip(np.floor(fi), 0, f.nx - 1)) * f.nz
+           + np.clip(np.floor(fk), 0, f.nz - 1))
+    near = np.minimum.reduce([np.abs(v - np.round(v)) for v in (fi, fj, fk)]) < 1e-4
+    down = np.flatnonzero(np.diff(key) < 0)
+    assert all(near[d] or near[d + 1] for d in down)
+    log("order: %d active in %d nodes, %d born in the window, %d inactive"
+        % (n_alive, len(np.unique(key)), n_new, n - n_alive - n_new))
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kind", ["hourly", "steady"])
+def test_windows_in_work_order_equal_index_order(kind):
+    import torch
+    import paper_0912_3223_amd as L
+    if kind == "hourly":
+        case, window = _hourly(), 720
+    else:
+        case, window = synth.c1(n_total=50_000, n_steps=1440, s_release=720), 480
+    out = {}
+    for order in (False, True):
+        run = L.DeviceRun(case)
+        recs = []
+        grids = run.run_recorded(60, window, order=order,
+                                 on_window=lambda w0, rec, n_rec: recs.append(rec.clone()))
+        run.check()
+        out[order] = dict(state=run.state(), grids=grids.double().cpu().numpy(), recs=recs,
+                          dep=run.grid_deposition().double().cpu().numpy(), led=run.ledger())
+    a, b = out[False], out[True]
+    for key in ("x", "y", "z", "m", "xl", "yl"):
+        np.testing.assert_array_equal(a["state"][key], b["state"][key])
+    n, sch = case.schedule.local_count, case.schedule
+    n_rec = window // 60
+    birth = torch.from_numpy((sch.id_base + np.arange(n) * sch.id_stride) * sch.s_release
+                             // sch.n_total).cuda()
+    for w, (ra, rb) in enumerate(zip(a["recs"], b["recs"])):
+        la = ra[4 * n_rec * n: (4 * n_rec + 1) * n].view(torch.int32)
+        lb = rb[4 * n_rec * n: (4 * n_rec + 1) * n].view(torch.int32)
+        w_end = (w + 1) * window
+        born = birth < w_end
+        assert torch.equal(la[born], lb[born])
+        for k in range(n_rec):
+            s = window * w + 60 * k + 59
+            use = (birth <= s) & (s < la)
+            va = ra[: 4 * n_rec * n].view(n_rec, n, 4)[k]
+            vb = rb[: 4 * n_rec * n].view(n_rec, n, 4)[k]
+            assert torch.equal(va[use], vb[use]), (w, k)
+    np.testing.assert_allclose(b["grids"], a["grids"], rtol=1e-6, atol=0)
+    np.testing.assert_allclose(b["dep"], a["dep"], rtol=1e-6, atol=0)
+    np.testing.assert_allclose(b["led"], a["led"], rtol=1e-12, atol=0)
+    log("work order %s: %d windows equal" % (kind, len(b["recs"])))
