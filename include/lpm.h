@@ -302,18 +302,19 @@ int lpm_order_particles(const lpm_state* st, const lpm_schedule* sch, const lpm_
 /* *bytes (host) = the size of the time-pair copy of one interval of fld
  * (lpm_field_interval): nz * ny * nx nodes of 16 bytes (ncomp 2) or 32
  * bytes (ncomp 3).  LPM_EINVAL unless fld is an LPM_FIELD_NODES field with
- * nt >= 2 and nx >= 2. */
+ * nt >= 2. */
 int lpm_field_interval_bytes(const lpm_field* fld, int64_t* bytes);
 
 /* The wind of a step is linear in time between two weather times (Sec. 3.2),
  * so a step reads the stencil at both times of its field interval.  Writes
  * interval k, [t0 + k dt_field, t0 + (k + 1) dt_field], of fld (layout
- * LPM_FIELD_NODES, nt >= 2, nx >= 2, 0 <= k <= nt - 2) into out with both
- * times of each node side by side: per node (u, v) at the interval's start,
- * then at its end (ncomp 2, 16 bytes), or (u, v, w, 0) at the start, then
- * at the end (ncomp 3, 32 bytes), nodes in [nz][ny][nx] order.  A step's
- * wind stencil then takes one set of cache lines for both times instead of
- * one per time.  out: caller-owned device memory of
+ * LPM_FIELD_NODES, nt >= 2, 0 <= k <= nt - 2) into out with both times of
+ * each node side by side: per node (u, v) at the interval's start, then at
+ * its end (ncomp 2, 16 bytes), or (u, v, w, 0) at the start, then at the
+ * end (ncomp 3, 32 bytes), nodes in [ny][nx][nz] order (levels innermost).
+ * A step's wind stencil then takes one set of cache lines for both times
+ * instead of one per time, and particles of one column share lines at any
+ * height (see lpm_order_particles).  out: caller-owned device memory of
  * lpm_field_interval_bytes bytes, 16-byte aligned, not overlapping
  * fld->data.  *packed (host) receives the descriptor of the copy: fld with
  * data = out, layout = LPM_FIELD_TIME_PAIRS and interval = k (nt, t0 and

@@ -692,27 +692,31 @@ __global__ __launch_bounds__(kBlock) void fill_u32(uint32_t* p, long long n)
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) p[i] = 0u;
 }
 
-// Time-pair copy of one field interval: node n of the two time slabs a, b
-// (ncomp floats each) becomes (a_n | b_n), padded to 4 floats per time for
-// three components.  One node per thread: coalesced 8- or 4-byte reads and
-// 16-byte writes.
+// Time-pair copy of one field interval: node (k, j, i) of the two time slabs
+// a, b ([nz][ny][nx] nodes of NCOMP floats) becomes (a | b) at node
+// (j, i, k) of the copy (levels innermost), padded to 4 floats per time for
+// three components.  One output node per thread: 16-byte coalesced writes,
+// the reads strided by a level.
 template <int NCOMP>
 __global__ __launch_bounds__(kBlock) void field_pairs(const float* __restrict__ a,
                                                       const float* __restrict__ b,
-                                                      float* __restrict__ out, long long nodes)
+                                                      float* __restrict__ out, int nx, int ny,
+                                                      int nz)
 {
     typedef float quad __attribute__((ext_vector_type(4)));
+    const long long nodes = (long long)nx * ny * nz;
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long n = (long long)blockIdx.x * kBlock + threadIdx.x; n < nodes; n += stride) {
+        const int k = (int)(n % nz);
+        const long long col = n / nz;  // j nx + i
+        const long long src = ((long long)k * ny * nx + col) * NCOMP;
         if constexpr (NCOMP == 2) {
-            const float2 u = reinterpret_cast<const float2*>(a)[n];
-            const float2 v = reinterpret_cast<const float2*>(b)[n];
+            const float2 u = *reinterpret_cast<const float2*>(a + src);
+            const float2 v = *reinterpret_cast<const float2*>(b + src);
             reinterpret_cast<quad*>(out)[n] = quad{u.x, u.y, v.x, v.y};
         } else {
-            const float* pa = a + 3 * n;
-            const float* pb = b + 3 * n;
-            reinterpret_cast<quad*>(out)[2 * n] = quad{pa[0], pa[1], pa[2], 0.0f};
-            reinterpret_cast<quad*>(out)[2 * n + 1] = quad{pb[0], pb[1], pb[2], 0.0f};
+            reinterpret_cast<quad*>(out)[2 * n] = quad{a[src], a[src + 1], a[src + 2], 0.0f};
+            reinterpret_cast<quad*>(out)[2 * n + 1] = quad{b[src], b[src + 1], b[src + 2], 0.0f};
         }
     }
 }
@@ -1006,8 +1010,8 @@ int fill_field(lpm::StepConst& p, const lpm_field* f)
     // floats per node and time block: (u, v) or (u, v, w); a time-pair node
     // holds both times, (u, v | u, v) or (u, v, w, 0 | u, v, w, 0)
     const int rec = tpair ? (f->ncomp == 2 ? 4 : 8) : f->ncomp;
-    if (tpair && (f->nt < 2 || f->nx < 2 || f->interval < 0 || f->interval > f->nt - 2))
-        return fail(LPM_EINVAL, "a time-pair field needs nt >= 2, nx >= 2 and interval in [0, nt - 2]");
+    if (tpair && (f->nt < 2 || f->interval < 0 || f->interval > f->nt - 2))
+        return fail(LPM_EINVAL, "a time-pair field needs nt >= 2 and interval in [0, nt - 2]");
     if (tpair && ((uintptr_t)f->data & 15u))
         return fail(LPM_EINVAL, "a time-pair field must be 16-byte aligned");
     const double total = (double)(tpair ? 1 : f->nt) * f->nz * f->ny * f->nx * rec;
@@ -1029,11 +1033,18 @@ int fill_field(lpm::StepConst& p, const lpm_field* f)
     p.inv_dz = f->z_levels ? 0.0f : (float)(1.0 / f->dz);
     p.inv_dtf = f->nt > 1 ? 1.0 / f->dt_field : 0.0;
     p.ft_zero = f->nt > 1 ? -f->t0 / f->dt_field : 0.0;
-    p.si = rec;
-    p.sj = f->nx * rec;
-    p.sk = f->ny * p.sj;
-    p.st = tpair ? 0 : f->nz * p.sk;
-    p.di = f->nx > 1 ? rec : 0;
+    if (tpair) {  // [ny][nx][nz] nodes: levels innermost
+        p.sk = rec;
+        p.si = f->nz * rec;
+        p.sj = f->nx * p.si;
+        p.st = 0;
+    } else {      // [nt][nz][ny][nx]
+        p.si = rec;
+        p.sj = f->nx * rec;
+        p.sk = f->ny * p.sj;
+        p.st = f->nz * p.sk;
+    }
+    p.di = f->nx > 1 ? p.si : 0;
     p.dj = f->ny > 1 ? p.sj : 0;
     p.dk = f->nz > 1 ? p.sk : 0;
     p.dt_off = tpair ? rec / 2 : (f->nt > 1 ? p.st : 0);
@@ -1727,7 +1738,7 @@ static int64_t interval_bytes(const lpm_field* fld)
 {
     if (!fld || !fld->data) return fail(LPM_EINVAL, "null field");
     if (fld->layout != LPM_FIELD_NODES) return fail(LPM_EINVAL, "the field must be in the node layout");
-    if (fld->nt < 2 || fld->nx < 2) return fail(LPM_EINVAL, "a field interval needs nt >= 2 and nx >= 2");
+    if (fld->nt < 2) return fail(LPM_EINVAL, "a field interval needs nt >= 2");
     if (fld->ncomp != 2 && fld->ncomp != 3) return fail(LPM_EINVAL, "field ncomp must be 2 or 3");
     if (fld->ny < 1 || fld->nz < 1) return fail(LPM_EINVAL, "bad field shape");
     return (int64_t)fld->nx * fld->ny * fld->nz * (fld->ncomp == 2 ? 16 : 32);
@@ -1765,10 +1776,10 @@ int lpm_field_interval(const lpm_field* fld, int32_t k, void* out, lpm_field* pa
     hipStream_t s = (hipStream_t)stream;
     if (fld->ncomp == 2)
         hipLaunchKernelGGL(lpm::field_pairs<2>, dim3(nb), dim3(lpm::kBlock), 0, s, a, b,
-                           static_cast<float*>(out), nodes);
+                           static_cast<float*>(out), fld->nx, fld->ny, fld->nz);
     else
         hipLaunchKernelGGL(lpm::field_pairs<3>, dim3(nb), dim3(lpm::kBlock), 0, s, a, b,
-                           static_cast<float*>(out), nodes);
+                           static_cast<float*>(out), fld->nx, fld->ny, fld->nz);
     lpm_field q = *fld;
     q.data = static_cast<const float*>(out);
     q.layout = LPM_FIELD_TIME_PAIRS;

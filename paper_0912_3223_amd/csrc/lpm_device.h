@@ -291,27 +291,29 @@ __device__ __forceinline__ void gather8(const float* __restrict__ fp, int base, 
 
 // The stencil at both times from a time-pair copy of a two-component field
 // interval: per node (u, v) at the interval's start and end side by side,
-// 16 bytes, so the two x-neighbours of a (y, z) corner are 32 contiguous
-// bytes -- two 16-byte loads, mostly in one cache line, for both times.
-__device__ __forceinline__ void gather8_tpair(const float* __restrict__ fp, int base, int dj,
-                                              int dk, float (&c)[2][8][2])
+// 16 bytes, levels innermost, so the two levels of each of the four
+// columns are 32 contiguous bytes -- two 16-byte loads, mostly in one cache
+// line, for both times -- and particles of one column at any height share
+// lines.  Corner q of the trilinear stencil: bit 0 i, bit 1 j, bit 2 k.
+__device__ __forceinline__ void gather8_tpair(const float* __restrict__ fp, int base, int di,
+                                              int dj, int dk, float (&c)[2][8][2])
 {
     typedef float quad __attribute__((ext_vector_type(4)));
     typedef __attribute__((address_space(1))) const quad gquad;
     const gfloat* f = as_global(fp);
-    const int o[4] = {base, base + dj, base + dk, base + dk + dj};
+    const int o[4] = {base, base + di, base + dj, base + dj + di};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const quad a = *reinterpret_cast<gquad*>(f + o[q]);
-        const quad b = *reinterpret_cast<gquad*>(f + o[q] + 4);
-        c[0][2 * q][0] = a.x;
-        c[0][2 * q][1] = a.y;
-        c[1][2 * q][0] = a.z;
-        c[1][2 * q][1] = a.w;
-        c[0][2 * q + 1][0] = b.x;
-        c[0][2 * q + 1][1] = b.y;
-        c[1][2 * q + 1][0] = b.z;
-        c[1][2 * q + 1][1] = b.w;
+        const quad b = *reinterpret_cast<gquad*>(f + o[q] + dk);
+        c[0][q][0] = a.x;
+        c[0][q][1] = a.y;
+        c[1][q][0] = a.z;
+        c[1][q][1] = a.w;
+        c[0][q + 4][0] = b.x;
+        c[0][q + 4][1] = b.y;
+        c[1][q + 4][0] = b.z;
+        c[1][q + 4][1] = b.w;
     }
 }
 
@@ -354,7 +356,7 @@ __device__ __forceinline__ void wind_gather(const StepConst& p, float x, float y
         base += t0 * p.st;
         if constexpr (NCOMP == 2) {
             if (p.tpair) {
-                gather8_tpair(p.f, base, p.dj, p.dk, w.c);
+                gather8_tpair(p.f, base, p.di, p.dj, p.dk, w.c);
                 return;
             }
         }

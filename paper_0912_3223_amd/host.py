@@ -237,7 +237,7 @@ class DeviceRun:
         for w0 in range(0, S, window):
             self.release(w0, window)
             fld = None
-            if time_pairs and self.fld.nt > 1 and self.fld.nx > 1:
+            if time_pairs and self.fld.nt > 1:
                 k = self.time_node(w0)
                 if self.time_node(w0 + window - 1) == k:
                     fld = self.interval_field(k)

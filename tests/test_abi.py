@@ -260,8 +260,7 @@ def test_time_pair_fields_are_checked(args):
     assert step(tp, 0, 10) == L.LPM_EINVAL  # steps 0..9 interpolate in interval 0
     assert b"interpolate in field interval 1" in L.lib().lpm_last_error()
     assert step(tp, 715, 10) == L.LPM_EINVAL  # steps 715..724 straddle t = 1 h
-    for bad in (dict(interval=2), dict(interval=-1), dict(nx=1), dict(layout=7),
-                dict(data=fld.data + 8)):
+    for bad in (dict(interval=2), dict(interval=-1), dict(layout=7), dict(data=fld.data + 8)):
         f = L.Field.from_buffer_copy(tp)
         for k, v in bad.items():
             setattr(f, k, v)

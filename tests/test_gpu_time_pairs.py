@@ -1,7 +1,8 @@
 """Time-pair copies of wind intervals (lpm_field_interval): the copy holds
-the field's two times of each node side by side, and hour-long windows that
-step on the copies give the records, states and grids of the same windows on
-the field itself, bitwise, for two- and three-component winds."""
+the field's two times of each node side by side, levels innermost, and
+hour-long windows that step on the copies give the records, states and
+grids of the same windows on the field itself, bitwise, for two- and
+three-component winds."""
 from dataclasses import replace
 
 import numpy as np
@@ -47,8 +48,9 @@ def test_interval_copy_layout(ncomp):
         got = run._interval_buf.cpu().numpy().reshape(nodes, 2, -1)
         rec = got.shape[2]
         assert rec == (2 if ncomp == 2 else 4)
-        a = f.data[k].reshape(nodes, ncomp)
-        b = f.data[k + 1].reshape(nodes, ncomp)
+        # nodes [ny][nx][nz]: levels innermost
+        a = f.data[k].transpose(1, 2, 0, 3).reshape(nodes, ncomp)
+        b = f.data[k + 1].transpose(1, 2, 0, 3).reshape(nodes, ncomp)
         np.testing.assert_array_equal(got[:, 0, :ncomp], a)
         np.testing.assert_array_equal(got[:, 1, :ncomp], b)
         if rec > ncomp:
