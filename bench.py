@@ -135,11 +135,13 @@ def make_case(name, n):
 
 
 def window_of(case):
-    """Steps per step launch: the whole run on a steady field; one field
-    interval (an hour, 720 steps) on hourly fields, so that every particle of
-    a launch samples the same two fields and they stay cache-resident."""
+    """Steps per step launch: the whole run on a steady field.  On hourly
+    fields half a field interval (360 steps): every launch steps on the
+    time-pair copy of one interval, and each launch takes its particles in
+    a fresh wind-node order (they drift apart within an hour)."""
     if case.field.nt > 1:
-        return int(round(case.field.dt_field / case.physics.dt))
+        per = int(round(case.field.dt_field / case.physics.dt))
+        return per // 2 if per % (2 * case.out_every) == 0 else per
     return case.n_steps
 
 

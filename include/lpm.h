@@ -279,8 +279,9 @@ int lpm_grid_concentration(const lpm_state* st, const lpm_source* src,
                            double* acc_scratch, float* out, lpm_stream stream);
 
 /* *bytes (host) = the device workspace lpm_order_particles needs for this
- * field: two 8-byte words per wind-grid node and a few for the scan. */
-int lpm_order_workspace(const lpm_field* fld, int64_t* bytes);
+ * schedule and field: two (node, index) pairs per local particle and the
+ * digit counts of the sort (about 17 bytes per particle). */
+int lpm_order_workspace(const lpm_schedule* sch, const lpm_field* fld, int64_t* bytes);
 
 /* Particles never interact (Sec. 3.2), so the order in which a step launch
  * takes them changes no result; it decides how much the lanes of a wave
@@ -293,8 +294,11 @@ int lpm_order_workspace(const lpm_field* fld, int64_t* bytes);
  * nonuniform levels: by column only), then the particles born in the
  * window in index order, then the inactive ones.  *n_order (host) = n,
  * computed on the host.  Put order and n into st->order and st->n_order of
- * that launch.  work: device scratch of lpm_order_workspace bytes, 8-byte
- * aligned.  n < 2^31.  Stream-ordered. */
+ * that launch.  The active particles are sorted by node with a radix sort
+ * (their order within a node, and that of the inactive ones, is left
+ * open).  work: device scratch of
+ * lpm_order_workspace bytes, 256-byte aligned.  n < 2^31.
+ * Stream-ordered. */
 int lpm_order_particles(const lpm_state* st, const lpm_schedule* sch, const lpm_field* fld,
                         int32_t step0, int32_t n_steps, int32_t* order, int64_t order_capacity,
                         int64_t* n_order, void* work, int64_t work_bytes, lpm_stream stream);

@@ -153,7 +153,7 @@ def _load():
                                        C.c_void_p, C.c_void_p],
         "lpm_adjoint_workspace": [P(Field), P(Schedule), C.c_int32, P(C.c_int64)],
         "lpm_field_interval_bytes": [P(Field), P(C.c_int64)],
-        "lpm_order_workspace": [P(Field), P(C.c_int64)],
+        "lpm_order_workspace": [P(Schedule), P(Field), P(C.c_int64)],
         "lpm_order_particles": [P(State), P(Schedule), P(Field), C.c_int32, C.c_int32,
                                 C.c_void_p, C.c_int64, P(C.c_int64), C.c_void_p, C.c_int64,
                                 C.c_void_p],
@@ -253,9 +253,9 @@ def grid_concentration_static(st: State, src: Source, sch: Schedule, ph: Physics
 FIELD_NODES, FIELD_TIME_PAIRS = 0, 1
 
 
-def order_workspace(fld: Field) -> int:
+def order_workspace(sch: Schedule, fld: Field) -> int:
     n = C.c_int64(0)
-    _rc(_lib.lpm_order_workspace(C.byref(fld), C.byref(n)))
+    _rc(_lib.lpm_order_workspace(C.byref(sch), C.byref(fld), C.byref(n)))
     return n.value
 
 

@@ -506,10 +506,10 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(unsigned long long* 
         }
 }
 
-// Work order of a step launch: a counting sort of the particles by the wind
-// node they are at.  Bins: node (j nx + i) nz + k of the particles active at
-// the launch's first step, then one bin of the particles born in the window
-// (kept in index order), then one of the inactive ones.
+// Work order of a step launch: the particles active at its first step sorted
+// by the wind node they are at (an LSD radix sort of (node, index) pairs,
+// 8 bits per pass, counts in LDS: no global atomics per particle), then
+// those born in the window in index order, then the inactive ones.
 struct OrderConst {
     const float* X;
     const float* Y;
@@ -519,15 +519,16 @@ struct OrderConst {
     long long n_all;   // the launch's particles: [0, n_all)
     float fcx, fcy, inv_dx, inv_dy, inv_dz;  // node i = floor(x inv_dx + fcx); inv_dz 0: k = 0
     int nx, ny, nz;
-    long long nbin;
-    unsigned long long* cur;  // counts, then (after the scan) running offsets
-    const unsigned long long* off;  // bin starts (after the scan)
+    unsigned long long* count;  // [0] active, [1] inactive particles
+    unsigned* keys;             // nodes of the active particles
+    int* vals;                  // their indices
     int* order;
 };
 
-__device__ __forceinline__ long long order_bin(const OrderConst& o, long long i)
+// Node (j nx + i) nz + k of particle i, or -1 when it is inactive.
+__device__ __forceinline__ long long order_node(const OrderConst& o, long long i)
 {
-    if (!(as_global(o.M)[i] > 0.0f)) return o.nbin - 1;
+    if (!(as_global(o.M)[i] > 0.0f)) return -1;
     const int ix = min(max((int)floorf(fmaf(as_global(o.X)[i], o.inv_dx, o.fcx)), 0), o.nx - 1);
     const int iy = min(max((int)floorf(fmaf(as_global(o.Y)[i], o.inv_dy, o.fcy)), 0), o.ny - 1);
     const int iz = o.inv_dz > 0.0f
@@ -536,49 +537,144 @@ __device__ __forceinline__ long long order_bin(const OrderConst& o, long long i)
     return ((long long)iy * o.nx + ix) * o.nz + iz;
 }
 
-// The inactive particles of a wave share one bin: one atomic per wave.
-__device__ __forceinline__ unsigned long long wave_claim(unsigned long long* counter, bool want)
-{
-    const unsigned long long mask = __ballot(want);
-    if (!mask) return 0ull;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)mask) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-    base = __shfl(base, leader, 64);
-    return base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
-}
+// Particles per block of the sort kernels.
+constexpr int kSortTile = 16 * kBlock;
 
-__global__ __launch_bounds__(kBlock) void order_count_kernel(const OrderConst o)
+// Active particles -> (node, index) pairs; inactive ones straight to the end
+// of the order (from the back).  A block takes kSortTile particles at a time
+// and claims its slots with one atomic per list (the lists' order is left
+// open).
+__global__ __launch_bounds__(kBlock) void order_keys_kernel(const OrderConst o)
 {
-    const long long stride = (long long)gridDim.x * kBlock;
-    // whole waves iterate together (the wave claim needs every lane)
-    for (long long i0 = (long long)blockIdx.x * kBlock; i0 < o.n_old; i0 += stride) {
-        const long long i = i0 + threadIdx.x;
-        const long long bin = i < o.n_old ? order_bin(o, i) : -1;
-        const bool dead = bin == o.nbin - 1;
-        (void)wave_claim(o.cur + o.nbin - 1, dead);
-        if (bin >= 0 && !dead) atomicAdd(o.cur + bin, 1ull);
+    constexpr int kPer = kSortTile / kBlock;
+    __shared__ unsigned long long scan_s[kBlock];
+    __shared__ unsigned long long base_s[2];
+    for (long long a = (long long)blockIdx.x * kSortTile; a < o.n_old;
+         a += (long long)gridDim.x * kSortTile) {
+        long long node[kPer];
+        unsigned n_act = 0u, n_off = 0u;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const long long e = a + (long long)j * kBlock + threadIdx.x;
+            node[j] = e < o.n_old ? order_node(o, e) : -2;
+            n_act += node[j] >= 0;
+            n_off += node[j] == -1;
+        }
+        // active counts in the low word, inactive in the high word (<= 4096 each)
+        unsigned long long tot;
+        const unsigned long long ex =
+            block_exclusive_scan(((unsigned long long)n_off << 32) | n_act, scan_s, &tot);
+        if (threadIdx.x == 0) {
+            base_s[0] = atomicAdd(o.count, tot & 0xFFFFFFFFull);
+            base_s[1] = atomicAdd(o.count + 1, tot >> 32);
+        }
+        __syncthreads();
+        unsigned long long pa = base_s[0] + (ex & 0xFFFFFFFFull);
+        unsigned long long pd = base_s[1] + (ex >> 32);
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const long long e = a + (long long)j * kBlock + threadIdx.x;
+            if (node[j] >= 0) {
+                as_global(o.keys)[pa] = (unsigned)node[j];
+                as_global(o.vals)[pa] = (int)e;
+                ++pa;
+            } else if (node[j] == -1) {
+                as_global(o.order)[o.n_all - 1 - (long long)pd] = (int)e;
+                ++pd;
+            }
+        }
+        __syncthreads();  // base_s and scan_s are reused
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        atomicAdd(o.cur + o.nbin - 2, (unsigned long long)(o.n_all - o.n_old));
 }
 
-__global__ __launch_bounds__(kBlock) void order_scatter_kernel(const OrderConst o)
+// The particles born in the window follow the active ones.
+__global__ __launch_bounds__(kBlock) void order_born_kernel(const OrderConst o)
 {
+    const long long n_active = (long long)o.count[0];
     const long long stride = (long long)gridDim.x * kBlock;
-    auto order = as_global(o.order);
-    for (long long i0 = (long long)blockIdx.x * kBlock; i0 < o.n_all; i0 += stride) {
-        const long long i = i0 + threadIdx.x;
-        const long long bin = i < o.n_old ? order_bin(o, i) : -1;
-        const bool dead = bin == o.nbin - 1;
-        const unsigned long long pd = wave_claim(o.cur + o.nbin - 1, dead);
-        if (i >= o.n_all) continue;
-        long long pos;
-        if (dead) pos = (long long)pd;
-        else if (bin >= 0) pos = (long long)atomicAdd(o.cur + bin, 1ull);
-        else pos = (long long)as_global(o.off)[o.nbin - 2] + (i - o.n_old);
-        order[pos] = (int)i;
+    for (long long i = o.n_old + (long long)blockIdx.x * kBlock + threadIdx.x; i < o.n_all; i += stride)
+        as_global(o.order)[n_active + (i - o.n_old)] = (int)i;
+}
+
+// One pass of the radix sort: 8 bits at `shift`.  Block b owns elements
+// [b kSortTile, (b + 1) kSortTile) of the `n` (device count) pairs.
+struct SortPass {
+    const unsigned* kin;
+    const int* vin;
+    unsigned* kout;   // null in the last pass
+    int* vout;
+    const unsigned long long* n;
+    unsigned long long* table;  // [256][nblocks]: digit counts, then their exclusive offsets
+    long long nblocks;
+    int shift;
+};
+
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const SortPass c)
+{
+    static_assert(kBlock == 256, "one digit per thread");
+    __shared__ unsigned h[256];
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    const long long n = (long long)*c.n;
+    const long long a = (long long)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortTile / kBlock; ++r) {
+        const long long e = a + (long long)r * kBlock + threadIdx.x;
+        if (e < n) atomicAdd(&h[(as_global(c.kin)[e] >> c.shift) & 255u], 1u);
+    }
+    __syncthreads();
+    c.table[(long long)threadIdx.x * c.nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: the tile in rounds of one element per thread, in order;
+// within a wave the lanes of one digit find each other with eight ballots.
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const SortPass c)
+{
+    __shared__ unsigned long long base[256];  // next slot of each digit
+    __shared__ unsigned cnt[kBlock / 64][256];  // per wave and digit, this round
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    base[threadIdx.x] = c.table[(long long)threadIdx.x * c.nblocks + blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) cnt[q][threadIdx.x] = 0u;
+    __syncthreads();
+    const long long n = (long long)*c.n;
+    const long long a = (long long)blockIdx.x * kSortTile;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int r = 0; r < kSortTile / kBlock; ++r) {
+        const long long e = a + (long long)r * kBlock + threadIdx.x;
+        const bool valid = e < n;
+        unsigned key = 0u, d = 0u;
+        int val = 0;
+        if (valid) {
+            key = as_global(c.kin)[e];
+            val = as_global(c.vin)[e];
+            d = (key >> c.shift) & 255u;
+        }
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool one = (d >> bit) & 1u;
+            const unsigned long long on = __ballot(valid && one);
+            peers &= one ? on : ~on;
+        }
+        const unsigned rank = (unsigned)__popcll(peers & lt);
+        if (valid && rank == 0u) cnt[w][d] = (unsigned)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            unsigned pre = 0u;
+            for (int q = 0; q < w; ++q) pre += cnt[q][d];
+            const unsigned long long dst = base[d] + pre + rank;
+            if (c.kout) as_global(c.kout)[dst] = key;
+            as_global(c.vout)[dst] = val;
+        }
+        __syncthreads();
+        unsigned sum = 0u;
+#pragma unroll
+        for (int q = 0; q < kBlock / 64; ++q) {
+            sum += cnt[q][threadIdx.x];
+            cnt[q][threadIdx.x] = 0u;
+        }
+        base[threadIdx.x] += sum;
+        __syncthreads();
     }
 }
 
@@ -1659,24 +1755,47 @@ int lpm_grid_deposition(const lpm_accum* acc, float* out, lpm_stream stream)
     return hip_status("lpm_grid_deposition");
 }
 
-// Work-order bins of a field: nodes (uniform levels) or columns, and two more.
-static long long order_bins(const lpm_field* fld)
+// Work order: nodes of a field (columns with nonuniform levels), and the
+// workspace of a sort of up to n pairs.
+static long long order_nodes(const lpm_field* fld)
 {
-    return (long long)fld->nx * fld->ny * (fld->z_levels ? 1 : fld->nz) + 2;
+    return (long long)fld->nx * fld->ny * (fld->z_levels ? 1 : fld->nz);
 }
 
-static long long order_scan_blocks(long long nbin)
+struct OrderLayout {
+    long long nblocks, ntable, nscan;
+    long long off_keys[2], off_vals[2], off_table, off_bsum, bytes;
+};
+
+static OrderLayout order_layout(long long n)
 {
-    return (nbin + lpm::kScanChunk - 1) / lpm::kScanChunk;
+    auto up = [](long long b) { return (b + 255) & ~255ll; };
+    OrderLayout L;
+    L.nblocks = (n + lpm::kSortTile - 1) / lpm::kSortTile;
+    L.ntable = 256 * L.nblocks;
+    L.nscan = (L.ntable + lpm::kScanChunk - 1) / lpm::kScanChunk;
+    long long at = 256;  // the two counters
+    for (int b = 0; b < 2; ++b) {
+        L.off_keys[b] = at;
+        at += up(4 * n);
+        L.off_vals[b] = at;
+        at += up(4 * n);
+    }
+    L.off_table = at;
+    at += up(8 * L.ntable);
+    L.off_bsum = at;
+    at += up(8 * (L.nscan > 0 ? L.nscan : 1));
+    L.bytes = at;
+    return L;
 }
 
-int lpm_order_workspace(const lpm_field* fld, int64_t* bytes)
+int lpm_order_workspace(const lpm_schedule* sch, const lpm_field* fld, int64_t* bytes)
 {
     g_msg[0] = 0;
-    if (!fld || !bytes) return fail(LPM_EINVAL, "null argument");
+    if (!sch || !fld || !bytes) return fail(LPM_EINVAL, "null argument");
+    if (sch->n_local < 0) return fail(LPM_EINVAL, "bad local id range");
     if (fld->nx < 1 || fld->ny < 1 || fld->nz < 1) return fail(LPM_EINVAL, "bad field shape");
-    const long long nbin = order_bins(fld);
-    *bytes = (int64_t)(8 * (2 * nbin + order_scan_blocks(nbin)));
+    *bytes = (int64_t)order_layout(sch->n_local).bytes;
     return LPM_OK;
 }
 
@@ -1691,13 +1810,15 @@ int lpm_order_particles(const lpm_state* st, const lpm_schedule* sch, const lpm_
     if (fld->nx < 1 || fld->ny < 1 || fld->nz < 1) return fail(LPM_EINVAL, "bad field shape");
     if (!(fld->dx > 0 && fld->dy > 0 && (fld->z_levels || fld->dz > 0)))
         return fail(LPM_EINVAL, "field spacings must be positive");
+    if (order_nodes(fld) > 0xFFFFFFFFll) return fail(LPM_EINVAL, "field of more than 2^32 nodes");
     if (step0 < 0 || n_steps < 1 || (long long)step0 + n_steps > 0x7FFFFFFFll)
         return fail(LPM_EINVAL, "bad step window");
-    if (!aligned4(order) || ((uintptr_t)work & 7u)) return fail(LPM_EINVAL, "misaligned order or workspace");
-    const long long nbin = order_bins(fld), nscan = order_scan_blocks(nbin);
-    if (work_bytes < 8 * (2 * nbin + nscan))
+    if (!aligned4(order) || ((uintptr_t)work & 255u))
+        return fail(LPM_EINVAL, "misaligned order or workspace");
+    const OrderLayout L = order_layout(sch->n_local);
+    if (work_bytes < L.bytes)
         return fail(LPM_EINVAL, "workspace of %lld bytes below the %lld needed",
-                    (long long)work_bytes, 8 * (2 * nbin + nscan));
+                    (long long)work_bytes, L.bytes);
     const long long n_all = first_local_born_at_or_after(sch, (long long)step0 + n_steps);
     if (n_all > 0x7FFFFFFFll) return fail(LPM_EINVAL, "work order of more than 2^31 - 1 particles");
     if (n_all > order_capacity)
@@ -1705,6 +1826,7 @@ int lpm_order_particles(const lpm_state* st, const lpm_schedule* sch, const lpm_
                     (long long)order_capacity);
     *n_order = n_all;
     if (n_all == 0) return LPM_OK;
+    char* w = static_cast<char*>(work);
     lpm::OrderConst o;
     memset(&o, 0, sizeof o);
     o.X = st->x; o.Y = st->y; o.Z = st->z; o.M = st->m;
@@ -1714,23 +1836,49 @@ int lpm_order_particles(const lpm_state* st, const lpm_schedule* sch, const lpm_
     o.inv_dx = (float)(1.0 / fld->dx); o.inv_dy = (float)(1.0 / fld->dy);
     o.inv_dz = fld->z_levels ? 0.0f : (float)(1.0 / fld->dz);
     o.nx = fld->nx; o.ny = fld->ny; o.nz = fld->z_levels ? 1 : fld->nz;
-    o.nbin = nbin;
-    auto* cur = static_cast<unsigned long long*>(work);
-    auto* off = cur + nbin;
-    auto* bsum = off + nbin;
-    o.cur = cur; o.off = off; o.order = order;
+    o.count = reinterpret_cast<unsigned long long*>(w);
+    o.keys = reinterpret_cast<unsigned*>(w + L.off_keys[0]);
+    o.vals = reinterpret_cast<int*>(w + L.off_vals[0]);
+    o.order = order;
     hipStream_t s = (hipStream_t)stream;
-    const unsigned fb = blocks_for(nbin) < 8192 ? blocks_for(nbin) : 8192;
-    hipLaunchKernelGGL(lpm::fill_f64, dim3(fb), dim3(lpm::kBlock), 0, s,
-                       reinterpret_cast<double*>(cur), nbin);
-    const unsigned nb = blocks_for(n_all) < 16384 ? blocks_for(n_all) : 16384;
-    hipLaunchKernelGGL(lpm::order_count_kernel, dim3(nb), dim3(lpm::kBlock), 0, s, o);
-    hipLaunchKernelGGL(lpm::scan_sums_kernel, dim3((unsigned)nscan), dim3(lpm::kBlock), 0, s,
-                       (const unsigned long long*)cur, nbin, bsum);
-    hipLaunchKernelGGL(lpm::scan_bsum_kernel, dim3(1), dim3(lpm::kBlock), 0, s, bsum, nscan);
-    hipLaunchKernelGGL(lpm::scan_apply_kernel, dim3((unsigned)nscan), dim3(lpm::kBlock), 0, s,
-                       cur, off, nbin, (const unsigned long long*)bsum);
-    hipLaunchKernelGGL(lpm::order_scatter_kernel, dim3(nb), dim3(lpm::kBlock), 0, s, o);
+    hipLaunchKernelGGL(lpm::fill_f64, dim3(1), dim3(lpm::kBlock), 0, s,
+                       reinterpret_cast<double*>(o.count), 2ll);
+    if (o.n_old > 0) {
+        const long long tiles = (o.n_old + lpm::kSortTile - 1) / lpm::kSortTile;
+        hipLaunchKernelGGL(lpm::order_keys_kernel, dim3((unsigned)(tiles < 4096 ? tiles : 4096)),
+                           dim3(lpm::kBlock), 0, s, o);
+        // passes of 8 bits over the node index
+        int bits = 1;
+        while (bits < 32 && (1ll << bits) < order_nodes(fld)) ++bits;
+        const int passes = (bits + 7) / 8;
+        auto* table = reinterpret_cast<unsigned long long*>(w + L.off_table);
+        auto* bsum = reinterpret_cast<unsigned long long*>(w + L.off_bsum);
+        const dim3 g((unsigned)L.nblocks), bs(lpm::kBlock);
+        for (int q = 0; q < passes; ++q) {
+            lpm::SortPass c;
+            c.kin = reinterpret_cast<const unsigned*>(w + L.off_keys[q & 1]);
+            c.vin = reinterpret_cast<const int*>(w + L.off_vals[q & 1]);
+            const bool last = q == passes - 1;
+            c.kout = last ? nullptr : reinterpret_cast<unsigned*>(w + L.off_keys[(q + 1) & 1]);
+            c.vout = last ? order : reinterpret_cast<int*>(w + L.off_vals[(q + 1) & 1]);
+            c.n = o.count;
+            c.table = table;
+            c.nblocks = L.nblocks;
+            c.shift = 8 * q;
+            hipLaunchKernelGGL(lpm::radix_hist_kernel, g, bs, 0, s, c);
+            hipLaunchKernelGGL(lpm::scan_sums_kernel, dim3((unsigned)L.nscan), bs, 0, s,
+                               (const unsigned long long*)table, L.ntable, bsum);
+            hipLaunchKernelGGL(lpm::scan_bsum_kernel, dim3(1), bs, 0, s, bsum, L.nscan);
+            hipLaunchKernelGGL(lpm::scan_apply_kernel, dim3((unsigned)L.nscan), bs, 0, s, table,
+                               table, L.ntable, (const unsigned long long*)bsum);
+            hipLaunchKernelGGL(lpm::radix_scatter_kernel, g, bs, 0, s, c);
+        }
+    }
+    if (n_all > o.n_old) {
+        const long long nb_born = n_all - o.n_old;
+        const unsigned nb = blocks_for(nb_born) < 8192 ? blocks_for(nb_born) : 8192;
+        hipLaunchKernelGGL(lpm::order_born_kernel, dim3(nb), dim3(lpm::kBlock), 0, s, o);
+    }
     return hip_status("lpm_order_particles");
 }
 

@@ -148,8 +148,8 @@ class DeviceRun:
         if getattr(self, "_order", None) is None:
             self._order = torch.empty(max(self.sch.n_local, 1), dtype=torch.int32,
                                       device=self.device)
-            self._order_work = torch.empty(order_workspace(self.fld), dtype=torch.uint8,
-                                           device=self.device)
+            self._order_work = torch.empty(order_workspace(self.sch, self.fld),
+                                           dtype=torch.uint8, device=self.device)
         n = order_particles(self.st, self.sch, self.fld, step0, n_steps, self._order,
                             self._order_work)
         st = State.from_buffer_copy(self.st)
