@@ -212,9 +212,9 @@ class DeviceRun:
         windows of ``window`` steps (a multiple of ``every``; the whole run by
         default).  Each window is one step launch that records the state
         after each of its output steps (every ``every``-th step), gridded right
-        after into ``out[k]`` for output step k.  Hour-long windows keep every
-        particle of a launch on the same pair of hourly wind fields.
-        ``on_window(w0, rec, n_rec)`` sees each window's record buffer before
+        after into ``out[k]`` for output step k.  Windows inside one field
+        interval keep every particle of a launch on the same pair of hourly
+        wind fields.  ``on_window(w0, rec, n_rec)`` sees each window's record buffer before
         it is reused; ``step_events`` (a list) receives a pair of timing events
         around each step launch, recorded on the current stream.  With
         ``time_pairs`` a window whose steps all interpolate in one interval

@@ -1,6 +1,6 @@
 """Time-pair copies of wind intervals (lpm_field_interval): the copy holds
 the field's two times of each node side by side, levels innermost, and
-hour-long windows that step on the copies give the records, states and
+windows that step on the copies give the records, states and
 grids of the same windows on the field itself, bitwise, for two- and
 three-component winds."""
 from dataclasses import replace
