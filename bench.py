@@ -219,19 +219,25 @@ def valu(fw, profile):
     (None while the summary is missing or stale): instructions per
     particle-step and the share of the VALU issue peak they occupy at the
     event-timed launch duration."""
-    vals = profile_values(profile)
     per_launch = fw["psteps"] / fw["launches"]
     model = {"model_lane_ops_per_particle_step": MODEL_LANE_OPS_PER_PSTEP,
              "model_frac": MODEL_LANE_OPS_PER_PSTEP * per_launch / (fw["launch_ms"] / 1e3)
              / (VALU_WAVE_INSTS_PEAK * 64)}
+    return dict(model, **counter_valu(profile, per_launch, fw["launch_ms"]))
+
+
+def counter_valu(profile, per_launch, launch_ms):
+    """The counter part of a `valu` object: from the summary's
+    machine-readable lines, per launch of `per_launch` particle-steps timed
+    at `launch_ms`."""
+    vals = profile_values(profile)
     if not vals or "sq_insts_valu_per_launch" not in vals:
-        return dict(model, counters=None)
+        return {"counters": None}
     insts = float(vals["sq_insts_valu_per_launch"])
-    out = dict(model, counters=profile,
-               wave_insts_per_launch=insts,
-               wave_insts_per_particle_step=insts / per_launch,
-               lane_insts_per_particle_step=64 * insts / per_launch,
-               issue_frac=insts / (fw["launch_ms"] / 1e3) / VALU_WAVE_INSTS_PEAK)
+    out = {"counters": profile, "wave_insts_per_launch": insts,
+           "wave_insts_per_particle_step": insts / per_launch,
+           "lane_insts_per_particle_step": 64 * insts / per_launch,
+           "issue_frac": insts / (launch_ms / 1e3) / VALU_WAVE_INSTS_PEAK}
     if "valu_busy_frac" in vals:
         out["busy_frac_counters"] = float(vals["valu_busy_frac"])
     return out
@@ -339,6 +345,9 @@ def ensemble_vs_plain(a):
                           "settings_tried": tune.n_tried, "reps": tune.reps}}
 
 
+ADJ_PROFILE = "c1_adjoint_counters.md"
+
+
 def adjoint_bench(a):
     """Gradient evaluations per second of the receptor misfit at theta0 on
     the 1e6-particle 6 h workload: forward (release, whole-run step with the
@@ -379,6 +388,9 @@ def adjoint_bench(a):
     back_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
     loss = float(((torch.log(c + eps) - torch.log(o + eps)) ** 2).sum())
     achieved = B_GRAD * psteps / dt
+    vals = profile_values(ADJ_PROFILE)
+    traffic = float(vals["adjoint_kernel_hbm_bytes_per_launch"]) if vals and \
+        "adjoint_kernel_hbm_bytes_per_launch" in vals else None
     return {"workload": "receptor log-misfit gradient in (h, q, s_w, v_d) at theta0 = "
                         "(50 m, 1, 1, 0.002 m/s); 1e6 particles, 4320 steps, 50 ground "
                         "receptors (Gaussian kernel 250 m / 40 m), checkpoints every 60 steps",
@@ -388,9 +400,10 @@ def adjoint_bench(a):
             "adjoint_particle_steps_per_s": psteps / (back_ms / 1e3),
             "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                          "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                         "bytes_per_particle_step": B_GRAD,
+                         "bytes_per_particle_step": B_GRAD, "traffic": traffic,
                          "what": "one gradient evaluation (forward + adjoint) per B_GRAD x "
                                  "forward particle-steps"},
+            "valu": counter_valu(ADJ_PROFILE, psteps, back_ms),
             "loss": loss, "grad": [float(v) for v in g[:4].cpu()]}
 
 
