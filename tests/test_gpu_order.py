@@ -109,3 +109,63 @@ def test_windows_in_work_order_equal_index_order(kind):
     np.testing.assert_allclose(b["dep"], a["dep"], rtol=1e-6, atol=0)
     np.testing.assert_allclose(b["led"], a["led"], rtol=1e-12, atol=0)
     log("work order %s: %d windows equal" % (kind, len(b["recs"])))
+
+
+def _order_of(run, step0, n_steps):
+    st = run.work_order(step0, n_steps)
+    return st.n_order, run._order[:st.n_order].cpu().numpy()
+
+
+def test_order_degenerate_cases():
+    """No particle born before the window (the order is the index order), no
+    particle at all, every particle inactive, a one-node field (one bin), and
+    nonuniform levels (columns only): always a permutation of the launch's
+    particles with the documented grouping."""
+    import torch
+    import paper_0912_3223_amd as L
+    # nothing born before step 0: all particles are born in the window
+    case = synth.c1(n_total=5000, n_steps=600, s_release=300)
+    run = L.DeviceRun(case)
+    run.release(0, 600)
+    n, order = _order_of(run, 0, 600)
+    assert n == 5000 and np.array_equal(order, np.arange(5000))
+    # a one-step window at step 0: the particles born in it (ids g with
+    # g * 300 // 5000 == 0, i.e. 0..16)
+    assert run.work_order(0, 1).n_order == 17
+    # every particle inactive: set them all to m = 0 after their births
+    run.set_state(np.zeros(5000), np.zeros(5000), np.full(5000, 50.0), np.zeros(5000))
+    n, order = _order_of(run, 300, 300)
+    assert n == 5000 and np.array_equal(np.sort(order), np.arange(5000))
+    # a one-node field: one bin
+    one = synth.c0(n_total=4000, n_steps=200)
+    run1 = L.DeviceRun(one)
+    run1.release(0, 200)
+    run1.step(0, 100)
+    n, order = _order_of(run1, 100, 100)
+    g = one.schedule.id_base + np.arange(n) * one.schedule.id_stride
+    born_before = (g * one.schedule.s_release) // one.schedule.n_total < 100
+    n_act = int((born_before & (run1.state()["m"] > 0)).sum())
+    assert np.array_equal(np.sort(order), np.arange(n))
+    assert np.array_equal(np.sort(order[:n_act]), np.flatnonzero(born_before))
+    # nonuniform levels: grouped by column
+    lev_case = synth.c1(n_total=20_000, n_steps=600, s_release=300)
+    f = lev_case.field
+    lev = (1200.0 * (np.linspace(0.0, 1.0, f.nz) ** 1.5) + 5.0).astype(np.float32)
+    lev_case = lev_case.with_(field=synth.replace(f, z_levels=lev))
+    runl = L.DeviceRun(lev_case)
+    runl.release(0, 600)
+    runl.step(0, 300)
+    n, order = _order_of(runl, 300, 300)
+    st = runl.state()
+    gl = np.arange(n)
+    act = ((gl * 300) // 20_000 < 300) & (st["m"] > 0)
+    n_act = int(act.sum())
+    assert np.array_equal(np.sort(order), np.arange(n)) and act[order[:n_act]].all()
+    col = (np.clip(np.floor((st["y"] - f.y0) / f.dy), 0, f.ny - 1) * f.nx
+           + np.clip(np.floor((st["x"] - f.x0) / f.dx), 0, f.nx - 1))[order[:n_act]]
+    fx = ((st["x"] - f.x0) / f.dx)[order[:n_act]]
+    fy = ((st["y"] - f.y0) / f.dy)[order[:n_act]]
+    near = np.minimum(np.abs(fx - np.round(fx)), np.abs(fy - np.round(fy))) < 1e-4
+    down = np.flatnonzero(np.diff(col) < 0)
+    assert all(near[d] or near[d + 1] for d in down)
+    torch.cuda.synchronize()

@@ -112,3 +112,23 @@ def test_steps_outside_the_interval_are_rejected():
     run.step_record(0, 720, 719, 720, 1, rec)  # the field itself takes them
     run.step_record(720, 60, 779, 60, 1, rec, packed)
     run.check()
+
+
+@pytest.mark.parametrize("shape", [(1, 8, 1), (5, 1, 3), (1, 1, 1)])
+def test_time_pairs_on_degenerate_grids(shape):
+    """Fields one node wide in some directions (the stencil's neighbour in
+    that direction is the node itself): time-pair copies still give the
+    field's states bitwise."""
+    import paper_0912_3223_amd as L
+    nx, ny, nz = shape
+    base = synth.c2(n_total=3000, n_steps=720, s_release=360, n_hours=2)
+    fld = synth.wind_field([1000, 1001], nx, ny, nz, 250.0, 250.0, 40.0, bounded=False)
+    case = base.with_(field=fld)
+    states = []
+    for tp in (False, True):
+        run = L.DeviceRun(case)
+        run.run_recorded(60, 360, time_pairs=tp)
+        run.check()
+        states.append(run.state())
+    for key in ("x", "y", "z", "m", "xl", "yl"):
+        np.testing.assert_array_equal(states[0][key], states[1][key])
