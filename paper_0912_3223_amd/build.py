@@ -29,9 +29,9 @@ UNITS = [
     ("lpm_receptor", "lpm_receptor.hip", []),
     ("lpm_ensemble", "lpm_ensemble.hip", []),
 ] + [
-    (f"step_plain_{nc}{'t' if t else 's'}", "lpm_step_plain.hip",
+    (f"step_plain_{nc}{'stp'[t]}", "lpm_step_plain.hip",
      [f"-DLPM_SLICE_NCOMP={nc}", f"-DLPM_SLICE_TIME={t}"])
-    for nc in (2, 3) for t in (0, 1)
+    for nc in (2, 3) for t in (0, 1, 2)
 ] + [
     (f"step_ensemble_{b}", "lpm_step_ensemble.hip", [f"-DLPM_SLICE_BLOCK={b}"])
     for b in (128, 256, 512)

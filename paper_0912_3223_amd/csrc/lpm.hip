@@ -32,6 +32,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <atomic>
 #include <mutex>
 #include <utility>
@@ -1400,19 +1401,21 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
     hipStream_t s = (hipStream_t)stream;
     // the work queue starts empty
     hipLaunchKernelGGL(lpm::fill_u32, dim3(1), dim3(lpm::kBlock), 0, s, acc->ctrl + LPM_CTRL_QUEUE, 2ll);
-    const bool time = fld->nt > 1;
+    // steady, two time nodes, or a time-pair copy (its gather compiled in)
+    const int time = fld->nt > 1 ? (p.tpair ? 2 : 1) : 0;
     const bool dep = p.dry_c1 > 0.0f || p.L0 > 0.0f;
     // the general kernel (K_z kind at run time) serves the paper-literal variants
     const int kz = (ph->chain || ph->dep_mode || ph->kz_kind == 3) ? 4 : ph->kz_kind;
     const bool lev = fld->z_levels != nullptr;
     const int bpc = lc.blocks_per_cu;
-    if (fld->ncomp == 2) {
-        if (time) launch_plain<2, true>(lev, ph->n_nuc, kz, dep, nb, s, p, bpc);
-        else launch_plain<2, false>(lev, ph->n_nuc, kz, dep, nb, s, p, bpc);
-    } else {
-        if (time) launch_plain<3, true>(lev, ph->n_nuc, kz, dep, nb, s, p, bpc);
-        else launch_plain<3, false>(lev, ph->n_nuc, kz, dep, nb, s, p, bpc);
-    }
+    auto go = [&](auto nc) {
+        constexpr int NC = decltype(nc)::value;
+        if (time == 2) launch_plain<NC, 2>(lev, ph->n_nuc, kz, dep, nb, s, p, bpc);
+        else if (time == 1) launch_plain<NC, 1>(lev, ph->n_nuc, kz, dep, nb, s, p, bpc);
+        else launch_plain<NC, 0>(lev, ph->n_nuc, kz, dep, nb, s, p, bpc);
+    };
+    if (fld->ncomp == 2) go(std::integral_constant<int, 2>{});
+    else go(std::integral_constant<int, 3>{});
     return hip_status("lpm_step_particles");
 }
 

@@ -243,7 +243,7 @@ __device__ __forceinline__ void levels(const float* __restrict__ levp, int nz, f
 // the loads) and interpolating are separate so that the random numbers and
 // the diffusivity, which do not depend on the wind, are computed while the
 // loads are in flight.
-template <int NCOMP, bool TIME>
+template <int NCOMP, int TIME>
 struct WindTap {
     float c[TIME ? 2 : 1][8][NCOMP];
     float wx, wy, wz, wt;
@@ -334,7 +334,7 @@ __device__ __forceinline__ void trilinear(const float (&c)[8][NCOMP], float wx, 
 
 // Issue the loads of the wind stencil at (x, y, z) at the start of step s
 // (Sec. 3.2: linear in x, y, z and t).
-template <int NCOMP, bool TIME, bool LEVELS>
+template <int NCOMP, int TIME, bool LEVELS>
 __device__ __forceinline__ void wind_gather(const StepConst& p, float x, float y, float z,
                                             int s, WindTap<NCOMP, TIME>& w)
 {
@@ -354,7 +354,10 @@ __device__ __forceinline__ void wind_gather(const StepConst& p, float x, float y
         const int t0 = min((int)ft, p.tmaxi);
         w.wt = (float)(ft - (double)t0);
         base += t0 * p.st;
-        if constexpr (NCOMP == 2) {
+        if constexpr (NCOMP == 2 && TIME == 2) {  // a time-pair copy, known at compile time
+            gather8_tpair(p.f, base, p.di, p.dj, p.dk, w.c);
+            return;
+        } else if constexpr (NCOMP == 2) {
             if (p.tpair) {
                 gather8_tpair(p.f, base, p.di, p.dj, p.dk, w.c);
                 return;
@@ -368,7 +371,7 @@ __device__ __forceinline__ void wind_gather(const StepConst& p, float x, float y
     }
 }
 
-template <int NCOMP, bool TIME>
+template <int NCOMP, int TIME>
 __device__ __forceinline__ void wind_interp(const WindTap<NCOMP, TIME>& w, float uvw[3])
 {
     trilinear<NCOMP>(w.c[0], w.wx, w.wy, w.wz, uvw);
@@ -495,7 +498,7 @@ __device__ __forceinline__ float comp_add(float hi, float& lo, float d)
     return t;
 }
 
-template <int NCOMP, bool TIME, bool LEVELS, int KZ, bool UNIFORM_KEY>
+template <int NCOMP, int TIME, bool LEVELS, int KZ, bool UNIFORM_KEY>
 __device__ __forceinline__ float motion(const StepConst& p, float wscale, uint32_t key1,
                                         uint32_t gid, int s, float x, float y, float z,
                                         float& xl, float& yl, float& xn, float& yn, float& zn)

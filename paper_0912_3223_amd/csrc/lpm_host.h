@@ -50,7 +50,7 @@ lpm_launch plain_launch();
 // fields or not, nonuniform levels, nuclide count, K_z kind -- 4 = the
 // general kernel -- and deposition on/off); defined, one slice of NCOMP x
 // TIME per unit, in lpm_step_plain.hip.
-template <int NCOMP, bool TIME>
+template <int NCOMP, int TIME>
 void launch_plain(bool lev, int nnuc, int kz, bool dep, unsigned nb, hipStream_t s,
                   const lpm::StepConst& p, int blocks_per_cu);
 

@@ -294,7 +294,7 @@ struct LedgerAcc {
 // K_z kind at run time (including Eq. 3 with stability), decay chains and
 // stochastic deposition.
 // ---------------------------------------------------------------------------
-template <int NCOMP, bool TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS>
+template <int NCOMP, int TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS>
 __device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
                                        DepTable<NNUC>& tab, long long plane, uint32_t gid,
                                        int b, int s, float& x, float& y, float& z, float& m,
@@ -420,15 +420,17 @@ __device__ __forceinline__ void lane_ledger(LedgerAcc<NNUC, KZ, false>& led, dou
 // picks by itself even where it spills a few registers (1e6-particle run:
 // 7.3 vs 7.8 ms; 64-scenario ensemble: 94 vs 103 ms); heavier variants keep
 // the default.
-template <int NCOMP, bool TIME, int NNUC, int KZ, bool DEP, bool ENS>
+template <int NCOMP, int TIME, int NNUC, int KZ, bool DEP, bool ENS>
 constexpr int step_min_blocks()
 {
-    return (NCOMP == 3) + TIME + DEP + (NNUC >= 3) + (KZ == 4) <= 1 ? 4 : 1;
+    return (NCOMP == 3) + (TIME != 0) + DEP + (NNUC >= 3) + (KZ == 4) <= 1 ? 4 : 1;
 }
 
 // BLOCK: threads per block (a multiple of 64); the second launch bound is the
-// number of waves per SIMD the register allocation must allow.
-template <int BLOCK, int NCOMP, bool TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS>
+// number of waves per SIMD the register allocation must allow.  TIME: 0 a
+// steady field, 1 two time nodes (the node layout, or a time-pair copy
+// recognised at run time), 2 a time-pair copy.
+template <int BLOCK, int NCOMP, int TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS>
 __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP, ENS>())) void step_kernel(const StepConst pk)
 {
     static_assert(BLOCK % 64 == 0 && BLOCK >= 64 && BLOCK <= 1024, "block of whole waves");

@@ -1,19 +1,20 @@
 // Plain (single-release) launches of the persistent step kernel for one
 // slice of its compile-time variants: LPM_SLICE_NCOMP wind components and
-// steady (LPM_SLICE_TIME = 0) or time-interpolated (1) fields, with every
-// level, nuclide-count, K_z and deposition variant of that slice.  The build
-// compiles this file once per slice, so the slices compile in parallel.
+// steady (LPM_SLICE_TIME = 0), time-interpolated (1) or time-pair-copy (2)
+// fields, with every level, nuclide-count, K_z and deposition variant of
+// that slice.  The build compiles this file once per slice, so the slices
+// compile in parallel.
 #include "lpm_host.h"
 #include "lpm_step.h"
 
 #if !defined(LPM_SLICE_NCOMP) || !defined(LPM_SLICE_TIME)
-#error "compile with -DLPM_SLICE_NCOMP=2|3 -DLPM_SLICE_TIME=0|1"
+#error "compile with -DLPM_SLICE_NCOMP=2|3 -DLPM_SLICE_TIME=0|1|2"
 #endif
 
 namespace lpm_host {
 namespace {
 
-template <int NCOMP, bool TIME, bool LEV, int NNUC, int KZ, bool DEP>
+template <int NCOMP, int TIME, bool LEV, int NNUC, int KZ, bool DEP>
 void go(unsigned nb, hipStream_t s, const lpm::StepConst& p, int bpc)
 {
     auto k = lpm::step_kernel<lpm::kBlock, NCOMP, TIME, LEV, NNUC, KZ, DEP, false>;
@@ -21,7 +22,7 @@ void go(unsigned nb, hipStream_t s, const lpm::StepConst& p, int bpc)
     hipLaunchKernelGGL(k, dim3(grid), dim3(lpm::kBlock), 0, s, p);
 }
 
-template <int NCOMP, bool TIME, bool LEV, int NNUC>
+template <int NCOMP, int TIME, bool LEV, int NNUC>
 void by_kz(int kz, bool dep, unsigned nb, hipStream_t s, const lpm::StepConst& p, int bpc)
 {
     switch (kz) {
@@ -36,7 +37,7 @@ void by_kz(int kz, bool dep, unsigned nb, hipStream_t s, const lpm::StepConst& p
     }
 }
 
-template <int NCOMP, bool TIME, bool LEV>
+template <int NCOMP, int TIME, bool LEV>
 void by_nnuc(int nnuc, int kz, bool dep, unsigned nb, hipStream_t s, const lpm::StepConst& p,
              int bpc)
 {
@@ -50,7 +51,7 @@ void by_nnuc(int nnuc, int kz, bool dep, unsigned nb, hipStream_t s, const lpm::
 
 }  // namespace
 
-template <int NCOMP, bool TIME>
+template <int NCOMP, int TIME>
 void launch_plain(bool lev, int nnuc, int kz, bool dep, unsigned nb, hipStream_t s,
                   const lpm::StepConst& p, int blocks_per_cu)
 {
@@ -58,7 +59,7 @@ void launch_plain(bool lev, int nnuc, int kz, bool dep, unsigned nb, hipStream_t
     else by_nnuc<NCOMP, TIME, false>(nnuc, kz, dep, nb, s, p, blocks_per_cu);
 }
 
-template void launch_plain<LPM_SLICE_NCOMP, (LPM_SLICE_TIME != 0)>(
+template void launch_plain<LPM_SLICE_NCOMP, LPM_SLICE_TIME>(
     bool, int, int, bool, unsigned, hipStream_t, const lpm::StepConst&, int);
 
 }  // namespace lpm_host
