@@ -242,8 +242,9 @@ __global__ __launch_bounds__(kBlock) void conc_kernel(const GridConst g)
 constexpr int kRecChunk = 8 * kBlock;
 // LDS bytes per bin: the counting pass keeps a 32-bit count, the scatter pass
 // a 32-bit rank and a 64-bit base per bin of the output step.
-constexpr int kBinCountLds = 4;
-constexpr int kBinScatterLds = 12;
+constexpr int kBinCountLds = 4;     // LDS bytes per bin of the count pass
+constexpr int kBinScatterLds = 12;  // and of the scatter pass
+constexpr int kBinWindow = 2048;    // bins in a block's LDS window (24 KB for the scatter)
 
 struct TileConst {
     int tx, ty;        // tile width and depth in cells (powers of two)
@@ -254,7 +255,7 @@ struct TileConst {
     int ntx, nty;      // owner tiles
     int nbx, nby;      // bin tiles (nx / tx + 1, ny / ty + 1)
     long long nbk;     // bins per output step: nbx nby 4
-    int bins_lds;      // 1: the bins of an output step fit one block's LDS (else global atomics)
+    int nwin;          // bins of a block's LDS window: min(nbk, kBinWindow)
     unsigned long long* off;  // [n_rec nbk] first index of each bin
     unsigned long long* cur;  // [n_rec nbk] counts, then end of each bin
     unsigned long long* bsum; // per-block sums of the scan
@@ -339,14 +340,33 @@ __global__ __launch_bounds__(kBlock) void chunk_end_kernel(const int* last, long
     }
 }
 
-// Pass 1: records per bin.  LDS: nbk counters when the bins fit (bins_lds).
+// The lowest bin of a block's records (records of consecutive ids lie close
+// together, so the block's bins mostly fall in a window of kBinWindow bins
+// from there).  Every thread of the block calls it.
+template <int N>
+__device__ __forceinline__ int bin_low(const int (&bin)[N])
+{
+    __shared__ int s_lo;
+    int a = INT_MAX;
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+        if (bin[u] >= 0) a = min(a, bin[u]);
+    if (threadIdx.x == 0) s_lo = INT_MAX;
+    __syncthreads();
+    if (a != INT_MAX) atomicMin(&s_lo, a);
+    __syncthreads();
+    return s_lo;
+}
+
+// Pass 1: records per bin: counted in an LDS window of nwin bins from the
+// block's lowest bin, records beyond the window with global atomics.
 __global__ __launch_bounds__(kBlock) void bin_count_kernel(const GridConst g, const TileConst t,
                                                            const float4* rec, const int* last,
                                                            long long rec_stride, int rec_step0,
                                                            int rec_every)
 {
     extern __shared__ unsigned long long lds_u64[];
-    uint32_t* hist = reinterpret_cast<uint32_t*>(lds_u64);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(lds_u64);  // [nwin]
     const int k = blockIdx.y;
     const int step = rec_step0 + k * rec_every;
     const long long i0 = (long long)blockIdx.x * kRecChunk;
@@ -361,27 +381,26 @@ __global__ __launch_bounds__(kBlock) void bin_count_kernel(const GridConst g, co
         bin[u] = binned_record(g, t, rec_k, last, i0 + u * kBlock + threadIdx.x, step, b);
         any |= bin[u] >= 0;
     }
-    const bool lds = t.bins_lds != 0;
-    if (!lds) {
-#pragma unroll
-        for (int u = 0; u < kRecChunk / kBlock; ++u)
-            if (bin[u] >= 0) atomicAdd(cnt + bin[u], 1ull);
-        return;
-    }
     if (!__syncthreads_or(any)) return;
-    for (int b = threadIdx.x; b < (int)t.nbk; b += kBlock) hist[b] = 0u;
+    const int lo = bin_low(bin);
+    for (int b = threadIdx.x; b < t.nwin; b += kBlock) hist[b] = 0u;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kRecChunk / kBlock; ++u)
-        if (bin[u] >= 0) atomicAdd(hist + bin[u], 1u);
+        if (bin[u] >= 0) {
+            const int d = bin[u] - lo;
+            if (d < t.nwin) atomicAdd(hist + d, 1u);
+            else atomicAdd(cnt + bin[u], 1ull);
+        }
     __syncthreads();
-    for (int b = threadIdx.x; b < (int)t.nbk; b += kBlock)
-        if (hist[b]) atomicAdd(cnt + b, (unsigned long long)hist[b]);
+    for (int b = threadIdx.x; b < t.nwin; b += kBlock)
+        if (hist[b]) atomicAdd(cnt + lo + b, (unsigned long long)hist[b]);
 }
 
-// Pass 3: particle indices into their bins.  With LDS, a block ranks its
-// records per bin, reserves one range per bin with a single global atomic and
-// writes the indices there.
+// Pass 3: particle indices into their bins.  A block ranks its records per
+// bin in its LDS window, reserves one range per bin with a single global
+// atomic and writes the indices there; records beyond the window take one
+// global atomic each.
 __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(const GridConst g, const TileConst t,
                                                              const float4* rec, const int* last,
                                                              long long rec_stride, int rec_step0,
@@ -401,33 +420,26 @@ __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(const GridConst g, 
         bin[u] = binned_record(g, t, rec_k, last, i0 + u * kBlock + threadIdx.x, step, born[u]);
         any |= bin[u] >= 0;
     }
-    const bool lds = t.bins_lds != 0;
-    if (!lds) {
-#pragma unroll
-        for (int u = 0; u < kRecChunk / kBlock; ++u)
-            if (bin[u] >= 0) {
-                const unsigned long long pos = atomicAdd(cur + bin[u], 1ull);
-                if (pos < t.cap) t.idx[pos] = make_int2((int)(i0 + u * kBlock + threadIdx.x), born[u]);
-            }
-        return;
-    }
     if (!__syncthreads_or(any)) return;
-    unsigned long long* base = lds_u64;                             // [nbk]
-    uint32_t* rank = reinterpret_cast<uint32_t*>(lds_u64 + t.nbk);  // [nbk]
-    for (int b = threadIdx.x; b < (int)t.nbk; b += kBlock) rank[b] = 0u;
+    unsigned long long* base = lds_u64;                               // [nwin]
+    uint32_t* rank = reinterpret_cast<uint32_t*>(lds_u64 + t.nwin);   // [nwin]
+    const int lo = bin_low(bin);
+    for (int b = threadIdx.x; b < t.nwin; b += kBlock) rank[b] = 0u;
     __syncthreads();
     uint32_t r[kRecChunk / kBlock];
 #pragma unroll
     for (int u = 0; u < kRecChunk / kBlock; ++u)
-        r[u] = bin[u] >= 0 ? atomicAdd(rank + bin[u], 1u) : 0u;
+        r[u] = bin[u] >= 0 && bin[u] - lo < t.nwin ? atomicAdd(rank + (bin[u] - lo), 1u) : 0u;
     __syncthreads();
-    for (int b = threadIdx.x; b < (int)t.nbk; b += kBlock)
-        if (rank[b]) base[b] = atomicAdd(cur + b, (unsigned long long)rank[b]);
+    for (int b = threadIdx.x; b < t.nwin; b += kBlock)
+        if (rank[b]) base[b] = atomicAdd(cur + lo + b, (unsigned long long)rank[b]);
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kRecChunk / kBlock; ++u)
         if (bin[u] >= 0) {
-            const unsigned long long pos = base[bin[u]] + r[u];
+            const int d = bin[u] - lo;
+            const unsigned long long pos = d < t.nwin ? base[d] + r[u]
+                                                      : atomicAdd(cur + bin[u], 1ull);
             if (pos < t.cap) t.idx[pos] = make_int2((int)(i0 + u * kBlock + threadIdx.x), born[u]);
         }
 }
@@ -1681,22 +1693,10 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     t.ps = rp.ps;
     t.ntx = rp.ntx; t.nty = rp.nty; t.nbx = rp.nbx; t.nby = rp.nby;
     t.nbk = rp.nbk;
-    // The bins of an output step go to LDS when the scatter pass's rank and
-    // base per bin fit one block's LDS (160 KB on gfx950: up to 13653 bins,
-    // e.g. the 10504 of a 400 x 400 grid in 16 x 4 tiles); beyond that, the
-    // passes count and place records with global atomics.
-    t.bins_lds = rp.nbk * lpm::kBinScatterLds <= (long long)device_lds() ? 1 : 0;
-    if (t.bins_lds && rp.nbk * lpm::kBinScatterLds > 65536) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(lpm::bin_scatter_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(rp.nbk * lpm::kBinScatterLds)) != hipSuccess ||
-            hipFuncSetAttribute(reinterpret_cast<const void*>(lpm::bin_count_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(rp.nbk * lpm::kBinScatterLds)) != hipSuccess) {
-            (void)hipGetLastError();
-            t.bins_lds = 0;
-        }
-    }
+    // A block counts and ranks its records in an LDS window of bins from its
+    // lowest one (24 KB: several blocks per CU); records beyond it take global
+    // atomics.
+    t.nwin = (int)std::min<long long>(rp.nbk, lpm::kBinWindow);
     t.off = (unsigned long long*)(w + rp.o_off);
     t.cur = (unsigned long long*)(w + rp.o_cur);
     t.bsum = (unsigned long long*)(w + rp.o_bsum);
@@ -1718,17 +1718,16 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     const int* last = reinterpret_cast<const int*>(rec + 4ll * n_rec * rec_stride);
     if (g.i_hi > 0) {
         const dim3 nb((unsigned)((g.i_hi + lpm::kRecChunk - 1) / lpm::kRecChunk), (unsigned)n_rec);
-        const bool lds = t.bins_lds != 0;
         hipLaunchKernelGGL(lpm::chunk_end_kernel, dim3((unsigned)rp.nchunk), bs, 0, s, last,
                            g.i_hi, (int*)(w + rp.o_cend));
-        hipLaunchKernelGGL(lpm::bin_count_kernel, nb, bs, lds ? lpm::kBinCountLds * rp.nbk : 0, s,
+        hipLaunchKernelGGL(lpm::bin_count_kernel, nb, bs, lpm::kBinCountLds * t.nwin, s,
                            g, t, r4, last, rec_stride, rec_step0, rec_every);
         hipLaunchKernelGGL(lpm::scan_sums_kernel, dim3((unsigned)rp.nscan), bs, 0, s, t.cur, rp.nb,
                            t.bsum);
         hipLaunchKernelGGL(lpm::scan_bsum_kernel, dim3(1), bs, 0, s, t.bsum, rp.nscan);
         hipLaunchKernelGGL(lpm::scan_apply_kernel, dim3((unsigned)rp.nscan), bs, 0, s, t.cur, t.off,
                            rp.nb, (const unsigned long long*)t.bsum);
-        hipLaunchKernelGGL(lpm::bin_scatter_kernel, nb, bs, lds ? lpm::kBinScatterLds * rp.nbk : 0,
+        hipLaunchKernelGGL(lpm::bin_scatter_kernel, nb, bs, lpm::kBinScatterLds * t.nwin,
                            s, g, t, r4, last, rec_stride, rec_step0, rec_every);
     } else {
         // nothing is born: every bin is empty (off = cur = 0)

@@ -34,10 +34,10 @@ def _grid(base, **kw):
 
 # (label, grid changes): the c1 grid is 200 x 200 x 30 of 250 x 250 x 40 m
 GRIDS = [
-    ("c1 grid, 16x4 tiles, bins in LDS", {}),
-    ("300x300x10 fine, 5776 bins in more than 64 KB of LDS, ragged tiles",
+    ("c1 grid, 16x4 tiles, 1352 bins in one LDS window", {}),
+    ("300x300x10 fine, 5776 bins over several LDS windows, ragged tiles",
      dict(nx=300, ny=300, nz=10, dx=100.0, dy=100.0, dz=100.0, x0=-5000.0, y0=-15000.0)),
-    ("720x720x4 finer, 33304 bins beyond one block's LDS: global atomics",
+    ("720x720x4 finer, 33304 bins: blocks spread beyond their LDS window (global atomics)",
      dict(nx=720, ny=720, nz=4, dx=40.0, dy=40.0, dz=250.0, x0=-14400.0, y0=-14400.0)),
     ("90x90x120 tall, 8x2 tiles, ragged", dict(nx=90, ny=90, nz=120, dx=300.0, dy=300.0,
                                                dz=10.0, x0=-3000.0, y0=-13500.0)),
