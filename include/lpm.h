@@ -258,7 +258,7 @@ int lpm_step_particles(const lpm_state* st, const lpm_source* src,
  * active in this window (INT_MAX if it is still active at the end, INT_MIN if
  * it was inactive on entry).  Records at or after `last` and of particles not
  * yet born are not meaningful; lpm_grid_records skips them.  All recorded
- * steps must lie in [step0, step0 + n_steps); rec_stride >= n_local.
+ * steps must lie in [step0, step0 + n_steps); n_local <= rec_stride < 2^32.
  * With every output step inside one window the whole run is one launch in
  * which all particles of the run are in flight at once. */
 int lpm_step_particles_record(const lpm_state* st, const lpm_source* src,
@@ -500,10 +500,12 @@ typedef struct {
  * compute unit -- `reps` times each (1 .. 15, after one untimed warm-up;
  * candidates that would launch alike, the same schedule and block size on
  * the same number of resident blocks, are timed once, as the first of
- * them), and keep in ens->launch the first candidate, in a fixed order, whose median
- * time is within 3 % of the smallest median (settings that time alike are
- * told apart by the order, so repeated calls pick the same setting; nothing
- * process-wide changes).  It runs release and step on the given buffers, so
+ * them), and keep in ens->launch the setting it held on entry if that
+ * launches alike with a candidate whose median time is within 6 % of the
+ * smallest median (a repeated call switches only for a clear gain), else the
+ * first candidate, in a fixed order, whose median time is within 3 % of the
+ * smallest (settings that time alike are told apart by the order, not by
+ * timing noise; nothing process-wide changes).  It runs release and step on the given buffers, so
  * state, dep, ledgers and ctrl must be reset and the particles released
  * again afterwards.  Synchronises `stream`. */
 int lpm_autotune_ensemble(const lpm_state* st, lpm_ensemble* ens,

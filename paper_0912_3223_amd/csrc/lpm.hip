@@ -1372,6 +1372,7 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
         if (!rec || ((uintptr_t)rec & 15u)) return fail(LPM_EINVAL, "null or misaligned record buffer");
         if (rec_every < 1) return fail(LPM_EINVAL, "rec_every must be >= 1");
         if (rec_stride < sch->n_local) return fail(LPM_EINVAL, "rec_stride below n_local");
+        if (rec_stride > 0xFFFFFFFFll) return fail(LPM_EINVAL, "rec_stride must be below 2^32");
         const long long last = (long long)rec_step0 + (long long)(n_rec - 1) * rec_every;
         if (rec_step0 < step0 || last >= (long long)step0 + n_steps)
             return fail(LPM_EINVAL, "recorded steps must lie inside the step window");

@@ -270,6 +270,7 @@ int lpm_autotune_ensemble(const lpm_state* st, lpm_ensemble* ens, const lpm_scen
     // Settings that launch alike (the same block size and schedule on the
     // same number of resident blocks: a wave count at or above what fits is
     // "as many as fit") are timed once, as the first of them.
+    int incumbent = -1;
     {
         unsigned grid_of[5 * 3 * 3];
         int kept = 0;
@@ -285,6 +286,20 @@ int lpm_autotune_ensemble(const lpm_state* st, lpm_ensemble* ens, const lpm_scen
             if (!rc && !dup) cand[kept++] = cand[c];
         }
         n_cand = kept;
+        // the caller's setting on entry (for instance an earlier pick): the
+        // candidate it launches alike with, if any
+        if (!rc && check_launch(ens->launch) == LPM_OK) {
+            trial.launch = ens->launch;
+            unsigned g = 0;
+            if (step_ensemble_impl(st, &trial, fld, ph, dep_grid, dep, ledgers, ctrl, stream,
+                                   &g) == LPM_OK)
+                for (int j = 0; j < n_cand && incumbent < 0; ++j)
+                    if (cand[j].refill_every == ens->launch.refill_every &&
+                        cand[j].refill_min == ens->launch.refill_min &&
+                        cand[j].block == ens->launch.block && grid_of[j] == g)
+                        incumbent = j;
+        }
+        g_msg[0] = 0;
     }
     if (rc) {
         lpm_ensemble again;
@@ -319,10 +334,12 @@ int lpm_autotune_ensemble(const lpm_state* st, lpm_ensemble* ens, const lpm_scen
         med_of[c] = reps % 2 ? t[1 + reps / 2] : 0.5 * (t[reps / 2] + t[1 + reps / 2]);
         ++tried;
     }
-    // The pick is the first candidate (in the fixed order above) whose
-    // median is within kTie of the fastest: settings that time alike are
-    // told apart by the order, not by timing noise, so the pick repeats.
-    constexpr double kTie = 0.03;
+    // The pick is the caller's setting if it times within kKeep of the
+    // fastest (a repeated call switches only for a clear gain), else the
+    // first candidate (in the fixed order above) whose median is within kTie
+    // of the fastest: settings that time alike are told apart by the order,
+    // not by timing noise, so the pick repeats.
+    constexpr double kTie = 0.03, kKeep = 0.06;
     double best = 1e300, worst = 0.0;
     for (int c = 0; c < tried; ++c) {
         best = std::min(best, med_of[c]);
@@ -330,12 +347,17 @@ int lpm_autotune_ensemble(const lpm_state* st, lpm_ensemble* ens, const lpm_scen
     }
     lpm_launch pick = ens->launch;
     double pick_ms = best;
-    for (int c = 0; c < tried; ++c)
-        if (med_of[c] <= best * (1.0 + kTie)) {
-            pick = cand[c];
-            pick_ms = med_of[c];
-            break;
-        }
+    if (incumbent >= 0 && incumbent < tried && med_of[incumbent] <= best * (1.0 + kKeep)) {
+        pick = cand[incumbent];
+        pick_ms = med_of[incumbent];
+    } else {
+        for (int c = 0; c < tried; ++c)
+            if (med_of[c] <= best * (1.0 + kTie)) {
+                pick = cand[c];
+                pick_ms = med_of[c];
+                break;
+            }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     // the caller's window back into the table (also after a failed trial)

@@ -218,12 +218,9 @@ struct Dwell {
             for (int n = 0; n < NNUC; ++n)
                 acc[n][0] = acc[n][1] = acc[n][2] = acc[n][3] = 0.0f;
         }
-        if (p.dmode == 0) {
-#pragma unroll
-            for (int n = 0; n < NNUC; ++n) acc[n][0] += d[n];
-            return;
-        }
-        const float wx = fx - ix, wy = fy - iy;
+        // nearest cell: all weight on corner 0 (the drain reads only that
+        // corner then), the same code path as cloud in cell
+        const float wx = p.dmode == 0 ? 0.0f : fx - ix, wy = p.dmode == 0 ? 0.0f : fy - iy;
         const float w00 = (1.0f - wx) * (1.0f - wy), w10 = wx * (1.0f - wy);
         const float w01 = (1.0f - wx) * wy, w11 = wx * wy;
 #pragma unroll
@@ -582,10 +579,13 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
                     p, sv, tab, plane, gid, b, s, x, y, z, m, xl, yl, led, bdep, dw);
                 if (s == next_rec) {  // state after an output step, for gridding later
                     typedef float quad __attribute__((ext_vector_type(4)));
-                    as_global(reinterpret_cast<quad*>(rec4))[(long long)krec * p.rec_stride + i] =
-                        quad{x, y, z, m};
+                    // krec, the stride and i are below 2^32: one 32 x 32 -> 64-bit
+                    // multiply-add forms the index
+                    as_global(reinterpret_cast<quad*>(rec4))[(unsigned long long)(uint32_t)krec *
+                                                                 (uint32_t)p.rec_stride +
+                                                             (uint32_t)i] = quad{x, y, z, m};
                     ++krec;
-                    next_rec = krec < p.n_rec ? p.rec_step0 + krec * p.rec_every : INT_MAX;
+                    next_rec = krec < p.n_rec ? next_rec + p.rec_every : INT_MAX;
                 }
                 ++s;
                 if (st != 0 || s >= p.step_end) {

@@ -101,6 +101,11 @@ def test_rejects_bad_arguments(args):
     # bad windows
     assert step(st, src, sch, fld, ph, -1, 1, acc, None) == L.LPM_EINVAL
     assert step(st, src, sch, fld, ph, 0, 0, acc, None) == L.LPM_EINVAL
+    # record stride: at least n_local, below 2^32
+    rec = lambda stride: code(L, "lpm_step_particles_record", st, src, sch, fld, ph, 0, 2, acc,
+                              0, 1, 2, C.c_void_p(0x10000), C.c_int64(stride), None)
+    assert rec(999) == L.LPM_EINVAL and b"rec_stride below" in L.lib().lpm_last_error()
+    assert rec(1 << 32) == L.LPM_EINVAL and b"below 2^32" in L.lib().lpm_last_error()
     # n_nuc
     ph5 = L.Physics.from_buffer_copy(ph)
     ph5.n_nuc = 5
