@@ -353,8 +353,9 @@ int lpm_grid_concentration_static(const lpm_state* st, const lpm_source* src,
 
 /* Bytes of device workspace lpm_grid_records needs for these arguments:
  * per (output step, bin of grid columns) two 64-bit offsets, one int per
- * 2048 particles, and one 8-byte entry (particle index, birth step) per
- * particle born by each recorded step (at most 8 n_rec n_local bytes).  0 when n_rec == 0.  Errors: the argument checks
+ * 2048 particles, and one 20-byte entry (the record and its birth step, in
+ * bin order) per particle born by each recorded step (at most
+ * 20 n_rec n_local bytes).  0 when n_rec == 0.  Errors: the argument checks
  * of lpm_grid_records that do not involve buffers; LPM_EINVAL also when
  * n_nuc * nz > 6144 (a full grid column of FP64 sums must fit one block's
  * LDS) or n_local >= 2^32. */

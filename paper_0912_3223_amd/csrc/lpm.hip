@@ -259,9 +259,10 @@ struct TileConst {
     unsigned long long* off;  // [n_rec nbk] first index of each bin
     unsigned long long* cur;  // [n_rec nbk] counts, then end of each bin
     unsigned long long* bsum; // per-block sums of the scan
-    int2* idx;                // particle index and birth step of each binned record
+    float4* brec;             // the binned records (x, y, z, m), in bin order
+    int* bborn;               // and the birth step of each
     const int* chunk_end;     // per chunk of kRecChunk ids: the largest `last` in it
-    unsigned long long cap;   // entries of idx
+    unsigned long long cap;   // entries of brec and bborn
     float* out;
     double inv_vol;
 };
@@ -292,18 +293,37 @@ __device__ __forceinline__ int record_bin(const GridConst& g, const TileConst& t
     return ((ay >> t.ly) * t.nbx + (ax >> t.lx)) * 4 + cls;
 }
 
-// Shared by the two binning kernels: the record of local particle i at output
-// step `step`, and its bin (-1 if it does not count).
-__device__ __forceinline__ int binned_record(const GridConst& g, const TileConst& t,
-                                             const float4* rec_k, const int* last, long long i,
-                                             int step, int& b)
+// Shared by the two binning kernels: the records of a thread's kRecChunk /
+// kBlock local particles at output step `step` (r), their birth steps (b)
+// and bins (-1 for a record that does not count).  The `last` words are
+// loaded together, then the records that count, so that a thread waits for
+// two rounds of loads, not one per record.
+constexpr int kRecPer = kRecChunk / kBlock;
+__device__ __forceinline__ void binned_records(const GridConst& g, const TileConst& t,
+                                               const float4* rec_k, const int* last,
+                                               long long i0, int step, float4 (&r)[kRecPer],
+                                               int (&b)[kRecPer], int (&bin)[kRecPer])
 {
-    if (i >= g.i_hi) return -1;
-    b = (int)birth(g.id_base + i * g.id_stride, g.s_release, g.n_total);
-    if (b > step || step >= last[i]) return -1;
-    const float4 r = rec_k[i];
-    if (!(r.w > 0.0f)) return -1;
-    return record_bin(g, t, r.x, r.y, r.z);
+    // (every load is issued, a record that does not count reading the
+    // block's first one, whose line the wave shares: conditional loads make
+    // the compiler wait for each before issuing the next)
+    int lst[kRecPer];
+#pragma unroll
+    for (int u = 0; u < kRecPer; ++u)  // i_hi >= 1: index clamped into the array
+        lst[u] = last[min(i0 + u * kBlock + threadIdx.x, g.i_hi - 1)];
+    bool live[kRecPer];
+#pragma unroll
+    for (int u = 0; u < kRecPer; ++u) {
+        const long long i = i0 + u * kBlock + threadIdx.x;
+        b[u] = i < g.i_hi ? (int)birth(g.id_base + i * g.id_stride, g.s_release, g.n_total) : 0;
+        live[u] = i < g.i_hi && b[u] <= step && step < lst[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kRecPer; ++u)  // i0 < i_hi (the chunk is not idle)
+        r[u] = rec_k[live[u] ? i0 + u * kBlock + threadIdx.x : i0];
+#pragma unroll
+    for (int u = 0; u < kRecPer; ++u)
+        bin[u] = live[u] && r[u].w > 0.0f ? record_bin(g, t, r[u].x, r[u].y, r[u].z) : -1;
 }
 
 // A chunk holds no record of an output step when its first id is born after
@@ -373,14 +393,15 @@ __global__ __launch_bounds__(kBlock) void bin_count_kernel(const GridConst g, co
     if (chunk_idle(g, t, i0, step)) return;
     const float4* rec_k = rec + (long long)k * rec_stride;
     unsigned long long* cnt = t.cur + (long long)k * t.nbk;
-    int bin[kRecChunk / kBlock];
+    int bin[kRecPer];
+    {
+        float4 r[kRecPer];
+        int born[kRecPer];
+        binned_records(g, t, rec_k, last, i0, step, r, born, bin);
+    }
     bool any = false;
 #pragma unroll
-    for (int u = 0; u < kRecChunk / kBlock; ++u) {
-        int b;
-        bin[u] = binned_record(g, t, rec_k, last, i0 + u * kBlock + threadIdx.x, step, b);
-        any |= bin[u] >= 0;
-    }
+    for (int u = 0; u < kRecPer; ++u) any |= bin[u] >= 0;
     if (!__syncthreads_or(any)) return;
     const int lo = bin_low(bin);
     for (int b = threadIdx.x; b < t.nwin; b += kBlock) hist[b] = 0u;
@@ -397,10 +418,11 @@ __global__ __launch_bounds__(kBlock) void bin_count_kernel(const GridConst g, co
         if (hist[b]) atomicAdd(cnt + lo + b, (unsigned long long)hist[b]);
 }
 
-// Pass 3: particle indices into their bins.  A block ranks its records per
-// bin in its LDS window, reserves one range per bin with a single global
-// atomic and writes the indices there; records beyond the window take one
-// global atomic each.
+// Pass 3: the records into their bins.  A block ranks its records per bin in
+// its LDS window, reserves one range per bin with a single global atomic and
+// writes the records (and birth steps) there, so that the tile pass reads
+// its records contiguously; records beyond the window take one global atomic
+// each.
 __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(const GridConst g, const TileConst t,
                                                              const float4* rec, const int* last,
                                                              long long rec_stride, int rec_step0,
@@ -413,13 +435,12 @@ __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(const GridConst g, 
     if (chunk_idle(g, t, i0, step)) return;
     const float4* rec_k = rec + (long long)k * rec_stride;
     unsigned long long* cur = t.cur + (long long)k * t.nbk;
-    int bin[kRecChunk / kBlock], born[kRecChunk / kBlock];
+    int bin[kRecPer], born[kRecPer];
+    float4 r4[kRecPer];
+    binned_records(g, t, rec_k, last, i0, step, r4, born, bin);
     bool any = false;
 #pragma unroll
-    for (int u = 0; u < kRecChunk / kBlock; ++u) {
-        bin[u] = binned_record(g, t, rec_k, last, i0 + u * kBlock + threadIdx.x, step, born[u]);
-        any |= bin[u] >= 0;
-    }
+    for (int u = 0; u < kRecPer; ++u) any |= bin[u] >= 0;
     if (!__syncthreads_or(any)) return;
     unsigned long long* base = lds_u64;                               // [nwin]
     uint32_t* rank = reinterpret_cast<uint32_t*>(lds_u64 + t.nwin);   // [nwin]
@@ -434,13 +455,20 @@ __global__ __launch_bounds__(kBlock) void bin_scatter_kernel(const GridConst g, 
     for (int b = threadIdx.x; b < t.nwin; b += kBlock)
         if (rank[b]) base[b] = atomicAdd(cur + lo + b, (unsigned long long)rank[b]);
     __syncthreads();
+    // positions first (the atomics of records beyond the window issued
+    // together), then every store: a store after each atomic would wait for
+    // the stores before it
+    unsigned long long pos[kRecPer];
 #pragma unroll
-    for (int u = 0; u < kRecChunk / kBlock; ++u)
-        if (bin[u] >= 0) {
-            const int d = bin[u] - lo;
-            const unsigned long long pos = d < t.nwin ? base[d] + r[u]
-                                                      : atomicAdd(cur + bin[u], 1ull);
-            if (pos < t.cap) t.idx[pos] = make_int2((int)(i0 + u * kBlock + threadIdx.x), born[u]);
+    for (int u = 0; u < kRecPer; ++u) {
+        const int d = bin[u] - lo;
+        pos[u] = bin[u] < 0 ? ~0ull : d < t.nwin ? base[d] + r[u] : atomicAdd(cur + bin[u], 1ull);
+    }
+#pragma unroll
+    for (int u = 0; u < kRecPer; ++u)
+        if (pos[u] < t.cap) {
+            t.brec[pos[u]] = r4[u];
+            t.bborn[pos[u]] = born[u];
         }
 }
 
@@ -696,7 +724,6 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const SortPass c)
 constexpr int kTileBatch = 4;
 template <int NNUC>
 __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, const TileConst t,
-                                                           const float4* rec, long long rec_stride,
                                                            int rec_step0, int rec_every)
 {
     extern __shared__ double tile[];
@@ -757,28 +784,27 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
     };
     // A crowded tile (the one holding the source) gets tens of thousands of
     // records: each thread takes kTileBatch of them at a time and issues
-    // their index and record loads before using any, so that the dependent
-    // gathers of one record overlap those of the others.
-    const float4* rec_k = rec + (long long)k * rec_stride;
+    // their loads before using any.  The records of the four ranges lie
+    // contiguously in bin order (written so by the scatter pass).
     for (long long j0 = threadIdx.x; j0 < total; j0 += (long long)kTileBatch * kBlock) {
-        int2 ib[kTileBatch];
+        float4 rr[kTileBatch];
+        int bb[kTileBatch];
         bool ok[kTileBatch];
 #pragma unroll
         for (int u = 0; u < kTileBatch; ++u) {
-            const long long j = j0 + (long long)u * kBlock;
-            ok[u] = j < total;
-            ib[u] = ok[u] ? t.idx[j < e0 ? lo0 + j
-                                  : j < e1 ? lo1 + (j - e0)
-                                  : j < e2 ? lo2 + (j - e1) : lo3 + (j - e2)]
-                          : make_int2(0, 0);
+            // past the end: the last entry again (every load issued, no
+            // branch around it)
+            const long long j = min(j0 + (long long)u * kBlock, total - 1);
+            ok[u] = j0 + (long long)u * kBlock < total;
+            const long long e = j < e0 ? lo0 + j
+                              : j < e1 ? lo1 + (j - e0)
+                              : j < e2 ? lo2 + (j - e1) : lo3 + (j - e2);
+            rr[u] = t.brec[e];
+            bb[u] = t.bborn[e];
         }
-        float4 rr[kTileBatch];
 #pragma unroll
         for (int u = 0; u < kTileBatch; ++u)
-            rr[u] = ok[u] ? rec_k[(uint32_t)ib[u].x] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-#pragma unroll
-        for (int u = 0; u < kTileBatch; ++u)
-            if (ok[u]) add_record(rr[u], ib[u].y);
+            if (ok[u]) add_record(rr[u], bb[u]);
     }
     __syncthreads();
     for (int c = threadIdx.x; c < NNUC * ncell; c += kBlock) {
@@ -1584,7 +1610,7 @@ struct RecordPlan {
     long long nbk, nb, nscan;
     unsigned long long cap;        // binned records at most
     long long nchunk;              // chunks of kRecChunk ids that can hold records
-    size_t o_off, o_cur, o_bsum, o_cend, o_idx, bytes;
+    size_t o_off, o_cur, o_bsum, o_cend, o_brec, o_born, bytes;
     size_t tile_lds;
 };
 
@@ -1631,8 +1657,9 @@ int plan_records(const lpm_schedule* sch, const lpm_physics* ph, const lpm_grid*
                     sch, (long long)rec_step0 + (long long)(n_rec > 0 ? n_rec - 1 : 0) * rec_every + 1) +
                 lpm::kRecChunk - 1) / lpm::kRecChunk;
     r.o_cend = r.o_bsum + align256(8 * (size_t)r.nscan);
-    r.o_idx = r.o_cend + align256(4 * (size_t)r.nchunk);
-    r.bytes = r.o_idx + align256(8 * (size_t)r.cap);
+    r.o_brec = r.o_cend + align256(4 * (size_t)r.nchunk);
+    r.o_born = r.o_brec + align256(16 * (size_t)r.cap);
+    r.bytes = r.o_born + align256(4 * (size_t)r.cap);
     r.ps = r.tx * r.ty + (r.tx * r.ty > 1 ? 1 : 0);
     r.tile_lds = column * r.ps;
     *rp = r;
@@ -1701,7 +1728,8 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     t.off = (unsigned long long*)(w + rp.o_off);
     t.cur = (unsigned long long*)(w + rp.o_cur);
     t.bsum = (unsigned long long*)(w + rp.o_bsum);
-    t.idx = (int2*)(w + rp.o_idx);
+    t.brec = (float4*)(w + rp.o_brec);
+    t.bborn = (int*)(w + rp.o_born);
     t.chunk_end = (const int*)(w + rp.o_cend);
     t.cap = rp.cap;
     t.out = out;
@@ -1737,10 +1765,10 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     }
     const dim3 tg((unsigned)((long long)rp.ntx * rp.nty), (unsigned)n_rec);
     switch (ph->n_nuc) {
-    case 1: hipLaunchKernelGGL(lpm::tile_conc_kernel<1>, tg, bs, rp.tile_lds, s, g, t, r4, rec_stride, rec_step0, rec_every); break;
-    case 2: hipLaunchKernelGGL(lpm::tile_conc_kernel<2>, tg, bs, rp.tile_lds, s, g, t, r4, rec_stride, rec_step0, rec_every); break;
-    case 3: hipLaunchKernelGGL(lpm::tile_conc_kernel<3>, tg, bs, rp.tile_lds, s, g, t, r4, rec_stride, rec_step0, rec_every); break;
-    default: hipLaunchKernelGGL(lpm::tile_conc_kernel<4>, tg, bs, rp.tile_lds, s, g, t, r4, rec_stride, rec_step0, rec_every); break;
+    case 1: hipLaunchKernelGGL(lpm::tile_conc_kernel<1>, tg, bs, rp.tile_lds, s, g, t, rec_step0, rec_every); break;
+    case 2: hipLaunchKernelGGL(lpm::tile_conc_kernel<2>, tg, bs, rp.tile_lds, s, g, t, rec_step0, rec_every); break;
+    case 3: hipLaunchKernelGGL(lpm::tile_conc_kernel<3>, tg, bs, rp.tile_lds, s, g, t, rec_step0, rec_every); break;
+    default: hipLaunchKernelGGL(lpm::tile_conc_kernel<4>, tg, bs, rp.tile_lds, s, g, t, rec_step0, rec_every); break;
     }
     return hip_status("lpm_grid_records");
 }

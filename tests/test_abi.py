@@ -210,14 +210,14 @@ def test_record_gridding_workspace_and_rejections(args):
     assert q(grid, 0, 1, 0) == L.LPM_OK and n.value == 0
     # 200 x 200 x 30, 2 nuclides: 16 x 4 column tiles, bins (200/16+1)(200/4+1)4 per record
     # step, two 64-bit words each; a 1000-particle run over 10 steps is fully born by
-    # step 9, so records at steps 4 and 9 hold at most 500 + 1000 particles (8 B each:
-    # index and birth step)
+    # step 9, so records at steps 4 and 9 hold at most 500 + 1000 particles (16 B of
+    # record and 4 B of birth step each, in two arrays)
     assert q(grid, 4, 5, 2) == L.LPM_OK
     nb = 2 * 13 * 51 * 4
     a256 = lambda b: (b + 255) // 256 * 256
     # (plus one int per chunk of 2048 particle ids: 1 chunk)
     assert n.value == (2 * a256(8 * nb) + a256(8 * ((nb + 2047) // 2048)) + a256(4 * 1)
-                       + a256(8 * 1500))
+                       + a256(16 * 1500) + a256(4 * 1500))
     tall = L.Grid.from_buffer_copy(grid)
     tall.nz = 3073  # 2 nuclides x 3073 levels x 8 B: one column exceeds the block's LDS
     assert q(tall, 0, 1, 1) == L.LPM_EINVAL

@@ -82,8 +82,10 @@ def _check_against_oracle(c, label):
     o = oracle.Oracle(c)
     for k in range(n_rec):
         s = every - 1 + k * every
-        r = recs[4 * k * stride:4 * k * stride + 4 * n].reshape(n, 4).astype(np.float64)
         live = (born <= s) & (s < last)
+        # records that are not meaningful may hold any bits (NaN included)
+        r = np.where(live[:, None], recs[4 * k * stride:4 * k * stride + 4 * n].reshape(n, 4),
+                     np.float32(0)).astype(np.float64)
         m = np.where(live, r[:, 3], 0.0)
         x, y, z = (np.where(live, r[:, j], 0.0) for j in range(3))
         ref = o.grid_concentration(s, x, y, z, m)
