@@ -259,6 +259,11 @@ int lpm_step_particles(const lpm_state* st, const lpm_source* src,
  * it was inactive on entry).  Records at or after `last` and of particles not
  * yet born are not meaningful; lpm_grid_records skips them.  All recorded
  * steps must lie in [step0, step0 + n_steps); n_local <= rec_stride < 2^32.
+ * With a work order on the state (st->order), the records and `last` word
+ * of queue entry q (particle order[q]) are stored at position q instead --
+ * index k * rec_stride + q and last[q] -- so that they follow the order's
+ * wind-node sorting; grid such records with lpm_grid_records_ordered (the
+ * receptor calls take records stored by particle index).
  * With every output step inside one window the whole run is one launch in
  * which all particles of the run are in flight at once. */
 int lpm_step_particles_record(const lpm_state* st, const lpm_source* src,
@@ -376,6 +381,24 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0,
                      const lpm_schedule* sch, const lpm_physics* ph,
                      const lpm_grid* grid, void* work, int64_t work_bytes,
                      float* out, lpm_stream stream);
+
+/* lpm_grid_records for the records of a launch that took a work order
+ * (Sec. 3.2, as lpm_grid_records): record k of queue position q, particle
+ * order[q], is the float4 at index k * rec_stride + q and its word last[q]
+ * (lpm_step_particles_record with st->order).  Consecutive positions hold
+ * particles sorted by wind node, so the binning reads and writes them
+ * together.  order: the launch's device int32 work order (4-byte aligned),
+ * n_order entries, 0 <= n_order <= n_local <= rec_stride; an entry outside
+ * [0, n_local) is skipped.  Workspace and output as for lpm_grid_records;
+ * the result equals lpm_grid_records on the same states recorded by
+ * particle index, up to the order of the FP64 sums.  Errors: those of
+ * lpm_grid_records; LPM_EINVAL for a null, misaligned or too long order. */
+int lpm_grid_records_ordered(const float* rec, int64_t rec_stride, int32_t rec_step0,
+                             int32_t rec_every, int32_t n_rec, const lpm_source* src,
+                             const lpm_schedule* sch, const lpm_physics* ph,
+                             const lpm_grid* grid, const int32_t* order, int64_t n_order,
+                             void* work, int64_t work_bytes, float* out,
+                             lpm_stream stream);
 
 /* Deposited activity so far on the deposition grid (Sec. 2: activity removed
  * from the particles to the surface by dry and wet deposition; Sec. 3.2:
@@ -564,8 +587,9 @@ typedef struct {
 } lpm_receptors;
 
 /* c_out[n] (device, FP64, overwritten) = receptor concentrations of the n_rec
- * recorded output steps rec_step0 + k rec_every (record layout as in
- * lpm_step_particles_record).  Asynchronous. */
+ * recorded output steps rec_step0 + k rec_every (records stored by particle
+ * index, as lpm_step_particles_record stores them without a work order).
+ * Asynchronous. */
 int lpm_receptor_concentration(const float* rec, int64_t rec_stride, int32_t rec_step0,
                                int32_t rec_every, int32_t n_rec, const lpm_source* src,
                                const lpm_schedule* sch, const lpm_physics* ph,

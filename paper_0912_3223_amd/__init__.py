@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+from typing import Optional
 
 import torch  # loaded first so that liblpm binds to torch's HIP runtime
 
@@ -135,6 +136,9 @@ def _load():
         "lpm_grid_records": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, P(Source),
                              P(Schedule), P(Physics), P(Grid), C.c_void_p, C.c_int64, C.c_void_p,
                              C.c_void_p],
+        "lpm_grid_records_ordered": [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                     P(Source), P(Schedule), P(Physics), P(Grid), C.c_void_p,
+                                     C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
         "lpm_grid_deposition": [P(Accum), C.c_void_p, C.c_void_p],
         "lpm_read_ledger": [P(Accum), P(C.c_double), C.c_void_p],
         "lpm_check": [P(Accum), C.c_void_p],
@@ -178,7 +182,7 @@ _lib = _load()
 EXPORTS = ("lpm_accum_reset", "lpm_release_particles", "lpm_step_particles",
            "lpm_step_particles_record",
            "lpm_grid_concentration", "lpm_grid_concentration_static",
-           "lpm_grid_records_workspace", "lpm_grid_records",
+           "lpm_grid_records_workspace", "lpm_grid_records", "lpm_grid_records_ordered",
            "lpm_grid_deposition",
            "lpm_read_ledger", "lpm_check", "lpm_set_launch", "lpm_set_launch_ex", "lpm_ensemble_prepare",
            "lpm_release_ensemble", "lpm_step_ensemble", "lpm_autotune_ensemble",
@@ -298,13 +302,23 @@ def grid_records_workspace(sch: Schedule, ph: Physics, grid: Grid, rec_step0: in
 
 def grid_records(rec: torch.Tensor, rec_stride: int, rec_step0: int, rec_every: int, n_rec: int,
                  src: Source, sch: Schedule, ph: Physics, grid: Grid, work: torch.Tensor,
-                 out: torch.Tensor, stream=None):
+                 out: torch.Tensor, stream=None, order: Optional[torch.Tensor] = None):
+    """lpm_grid_records; with ``order`` (the launch's int32 work order, the
+    records stored by queue position) lpm_grid_records_ordered."""
     assert rec.dtype == torch.float32 and out.dtype == torch.float32
     nbytes = work.numel() * work.element_size()
-    _rc(_lib.lpm_grid_records(C.c_void_p(rec.data_ptr()), rec_stride, rec_step0, rec_every, n_rec,
-                              C.byref(src), C.byref(sch), C.byref(ph), C.byref(grid),
-                              C.c_void_p(work.data_ptr()), nbytes, C.c_void_p(out.data_ptr()),
-                              _stream(stream)))
+    if order is None:
+        _rc(_lib.lpm_grid_records(C.c_void_p(rec.data_ptr()), rec_stride, rec_step0, rec_every,
+                                  n_rec, C.byref(src), C.byref(sch), C.byref(ph), C.byref(grid),
+                                  C.c_void_p(work.data_ptr()), nbytes, C.c_void_p(out.data_ptr()),
+                                  _stream(stream)))
+        return
+    assert order.dtype == torch.int32
+    _rc(_lib.lpm_grid_records_ordered(C.c_void_p(rec.data_ptr()), rec_stride, rec_step0,
+                                      rec_every, n_rec, C.byref(src), C.byref(sch), C.byref(ph),
+                                      C.byref(grid), C.c_void_p(order.data_ptr()), order.numel(),
+                                      C.c_void_p(work.data_ptr()), nbytes,
+                                      C.c_void_p(out.data_ptr()), _stream(stream)))
 
 
 def grid_deposition(acc: Accum, out: torch.Tensor, stream=None):

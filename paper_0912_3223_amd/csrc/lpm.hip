@@ -145,6 +145,11 @@ struct GridConst {
     double x0, y0, z0, inv_dx, inv_dy, inv_dz;
     long long cells;
     double* acc;
+    // record gridding: positions recorded (n_pos) and, for records of a
+    // launch with a work order, the particle of each position (else the
+    // position is the particle); i_hi then bounds the particle indices
+    const int* order;
+    long long n_pos;
 };
 
 // Activities of the nuclides at age t, scaled by f.
@@ -294,10 +299,10 @@ __device__ __forceinline__ int record_bin(const GridConst& g, const TileConst& t
 }
 
 // Shared by the two binning kernels: the records of a thread's kRecChunk /
-// kBlock local particles at output step `step` (r), their birth steps (b)
-// and bins (-1 for a record that does not count).  The `last` words are
-// loaded together, then the records that count, so that a thread waits for
-// two rounds of loads, not one per record.
+// kBlock positions at output step `step` (r), the birth steps of their
+// particles (b) and their bins (-1 for a record that does not count).  The
+// `last` words (and order entries) are loaded together, then the records,
+// so that a thread waits for two rounds of loads, not one per record.
 constexpr int kRecPer = kRecChunk / kBlock;
 __device__ __forceinline__ void binned_records(const GridConst& g, const TileConst& t,
                                                const float4* rec_k, const int* last,
@@ -308,32 +313,37 @@ __device__ __forceinline__ void binned_records(const GridConst& g, const TileCon
     // block's first one, whose line the wave shares: conditional loads make
     // the compiler wait for each before issuing the next)
     int lst[kRecPer];
+    long long pi[kRecPer];  // particle of each position
 #pragma unroll
-    for (int u = 0; u < kRecPer; ++u)  // i_hi >= 1: index clamped into the array
-        lst[u] = last[min(i0 + u * kBlock + threadIdx.x, g.i_hi - 1)];
+    for (int u = 0; u < kRecPer; ++u) {  // n_pos >= 1: position clamped into the arrays
+        const long long q = min(i0 + u * kBlock + threadIdx.x, g.n_pos - 1);
+        lst[u] = last[q];
+        pi[u] = g.order ? (long long)g.order[q] : q;
+    }
     bool live[kRecPer];
 #pragma unroll
     for (int u = 0; u < kRecPer; ++u) {
-        const long long i = i0 + u * kBlock + threadIdx.x;
-        b[u] = i < g.i_hi ? (int)birth(g.id_base + i * g.id_stride, g.s_release, g.n_total) : 0;
-        live[u] = i < g.i_hi && b[u] <= step && step < lst[u];
+        const bool ok = i0 + u * kBlock + threadIdx.x < g.n_pos &&
+                        (unsigned long long)pi[u] < (unsigned long long)g.i_hi;
+        b[u] = ok ? (int)birth(g.id_base + pi[u] * g.id_stride, g.s_release, g.n_total) : 0;
+        live[u] = ok && b[u] <= step && step < lst[u];
     }
 #pragma unroll
-    for (int u = 0; u < kRecPer; ++u)  // i0 < i_hi (the chunk is not idle)
+    for (int u = 0; u < kRecPer; ++u)  // i0 < n_pos (the chunk is not idle)
         r[u] = rec_k[live[u] ? i0 + u * kBlock + threadIdx.x : i0];
 #pragma unroll
     for (int u = 0; u < kRecPer; ++u)
         bin[u] = live[u] && r[u].w > 0.0f ? record_bin(g, t, r[u].x, r[u].y, r[u].z) : -1;
 }
 
-// A chunk holds no record of an output step when its first id is born after
-// the step (local ids are born in increasing order) or when all of its
-// particles stopped by then.
+// A chunk of positions holds no record of an output step when all of its
+// particles stopped by then, or (positions that are particles: local ids
+// are born in increasing order) when its first id is born after the step.
 __device__ __forceinline__ bool chunk_idle(const GridConst& g, const TileConst& t, long long i0,
                                            int step)
 {
-    return i0 >= g.i_hi || step >= t.chunk_end[blockIdx.x] ||
-           birth(g.id_base + i0 * g.id_stride, g.s_release, g.n_total) > step;
+    return i0 >= g.n_pos || step >= t.chunk_end[blockIdx.x] ||
+           (!g.order && birth(g.id_base + i0 * g.id_stride, g.s_release, g.n_total) > step);
 }
 
 // Pass 0: the largest `last` of each chunk (one block per chunk).
@@ -795,12 +805,17 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
             // past the end: the last entry again (every load issued, no
             // branch around it)
             const long long j = min(j0 + (long long)u * kBlock, total - 1);
-            ok[u] = j0 + (long long)u * kBlock < total;
             const long long e = j < e0 ? lo0 + j
                               : j < e1 ? lo1 + (j - e0)
                               : j < e2 ? lo2 + (j - e1) : lo3 + (j - e2);
-            rr[u] = t.brec[e];
-            bb[u] = t.bborn[e];
+            // (entries past the workspace -- only a work order listing a
+            // particle twice could count more records than were born -- were
+            // not written by the scatter and are skipped; total > 0 implies
+            // cap >= 1)
+            ok[u] = j0 + (long long)u * kBlock < total && (unsigned long long)e < t.cap;
+            const long long ec = min(e, (long long)t.cap - 1);
+            rr[u] = t.brec[ec];
+            bb[u] = t.bborn[ec];
         }
 #pragma unroll
         for (int u = 0; u < kTileBatch; ++u)
@@ -1653,9 +1668,8 @@ int plan_records(const lpm_schedule* sch, const lpm_physics* ph, const lpm_grid*
     r.o_off = 0;
     r.o_cur = r.o_off + align256(8 * (size_t)r.nb);
     r.o_bsum = r.o_cur + align256(8 * (size_t)r.nb);
-    r.nchunk = (first_local_born_at_or_after(
-                    sch, (long long)rec_step0 + (long long)(n_rec > 0 ? n_rec - 1 : 0) * rec_every + 1) +
-                lpm::kRecChunk - 1) / lpm::kRecChunk;
+    // one word per chunk of recorded positions: at most n_local of them
+    r.nchunk = (sch->n_local + lpm::kRecChunk - 1) / lpm::kRecChunk;
     r.o_cend = r.o_bsum + align256(8 * (size_t)r.nscan);
     r.o_brec = r.o_cend + align256(4 * (size_t)r.nchunk);
     r.o_born = r.o_brec + align256(16 * (size_t)r.cap);
@@ -1681,16 +1695,21 @@ int lpm_grid_records_workspace(const lpm_schedule* sch, const lpm_physics* ph,
     return LPM_OK;
 }
 
-int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, int32_t rec_every,
-                     int32_t n_rec, const lpm_source* src, const lpm_schedule* sch,
-                     const lpm_physics* ph, const lpm_grid* grid, void* work, int64_t work_bytes,
-                     float* out, lpm_stream stream)
+// lpm_grid_records (order == nullptr: records by particle index) and
+// lpm_grid_records_ordered (records by position in `order`).
+static int grid_records_impl(const float* rec, int64_t rec_stride, int32_t rec_step0,
+                             int32_t rec_every, int32_t n_rec, const lpm_source* src,
+                             const lpm_schedule* sch, const lpm_physics* ph, const lpm_grid* grid,
+                             const int32_t* order, int64_t n_order, void* work,
+                             int64_t work_bytes, float* out, lpm_stream stream)
 {
     g_msg[0] = 0;
     if (!src) return fail(LPM_EINVAL, "null source");
     RecordPlan rp;
     int rc = plan_records(sch, ph, grid, rec_step0, rec_every, n_rec, &rp);
     if (rc) return rc;
+    if (order && (!aligned4(order) || n_order < 0 || n_order > sch->n_local))
+        return fail(LPM_EINVAL, "work order: 4-byte aligned, n_order in [0, n_local]");
     if (n_rec == 0) return LPM_OK;
     if (!rec || ((uintptr_t)rec & 15u)) return fail(LPM_EINVAL, "null or misaligned record buffer");
     if (rec_stride < sch->n_local) return fail(LPM_EINVAL, "rec_stride below n_local");
@@ -1712,8 +1731,12 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     g.x0 = grid->x0; g.y0 = grid->y0; g.z0 = grid->z0;
     g.inv_dx = 1.0 / grid->dx; g.inv_dy = 1.0 / grid->dy; g.inv_dz = 1.0 / grid->dz;
     g.cells = (long long)grid->nx * grid->ny * grid->nz;
-    // every particle that can be born by the last recorded step
+    // every particle that can be born by the last recorded step; recorded
+    // positions: those particles, or the entries of the work order
     g.i_hi = first_local_born_at_or_after(sch, (long long)rec_step0 + (long long)(n_rec - 1) * rec_every + 1);
+    g.order = order;
+    g.n_pos = order ? n_order : g.i_hi;
+    if (order) g.i_hi = sch->n_local;
     char* w = (char*)work;
     lpm::TileConst t;
     t.tx = rp.tx; t.ty = rp.ty;
@@ -1745,10 +1768,11 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
                        (uint32_t*)t.cur, 2 * rp.nb);
     const float4* r4 = reinterpret_cast<const float4*>(rec);
     const int* last = reinterpret_cast<const int*>(rec + 4ll * n_rec * rec_stride);
-    if (g.i_hi > 0) {
-        const dim3 nb((unsigned)((g.i_hi + lpm::kRecChunk - 1) / lpm::kRecChunk), (unsigned)n_rec);
-        hipLaunchKernelGGL(lpm::chunk_end_kernel, dim3((unsigned)rp.nchunk), bs, 0, s, last,
-                           g.i_hi, (int*)(w + rp.o_cend));
+    if (g.n_pos > 0) {
+        const long long nchunk = (g.n_pos + lpm::kRecChunk - 1) / lpm::kRecChunk;  // <= rp.nchunk
+        const dim3 nb((unsigned)nchunk, (unsigned)n_rec);
+        hipLaunchKernelGGL(lpm::chunk_end_kernel, dim3((unsigned)nchunk), bs, 0, s, last,
+                           g.n_pos, (int*)(w + rp.o_cend));
         hipLaunchKernelGGL(lpm::bin_count_kernel, nb, bs, lpm::kBinCountLds * t.nwin, s,
                            g, t, r4, last, rec_stride, rec_step0, rec_every);
         hipLaunchKernelGGL(lpm::scan_sums_kernel, dim3((unsigned)rp.nscan), bs, 0, s, t.cur, rp.nb,
@@ -1770,7 +1794,30 @@ int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, in
     case 3: hipLaunchKernelGGL(lpm::tile_conc_kernel<3>, tg, bs, rp.tile_lds, s, g, t, rec_step0, rec_every); break;
     default: hipLaunchKernelGGL(lpm::tile_conc_kernel<4>, tg, bs, rp.tile_lds, s, g, t, rec_step0, rec_every); break;
     }
-    return hip_status("lpm_grid_records");
+    return hip_status(order ? "lpm_grid_records_ordered" : "lpm_grid_records");
+}
+
+int lpm_grid_records(const float* rec, int64_t rec_stride, int32_t rec_step0, int32_t rec_every,
+                     int32_t n_rec, const lpm_source* src, const lpm_schedule* sch,
+                     const lpm_physics* ph, const lpm_grid* grid, void* work, int64_t work_bytes,
+                     float* out, lpm_stream stream)
+{
+    return grid_records_impl(rec, rec_stride, rec_step0, rec_every, n_rec, src, sch, ph, grid,
+                             nullptr, 0, work, work_bytes, out, stream);
+}
+
+int lpm_grid_records_ordered(const float* rec, int64_t rec_stride, int32_t rec_step0,
+                             int32_t rec_every, int32_t n_rec, const lpm_source* src,
+                             const lpm_schedule* sch, const lpm_physics* ph,
+                             const lpm_grid* grid, const int32_t* order, int64_t n_order,
+                             void* work, int64_t work_bytes, float* out, lpm_stream stream)
+{
+    if (!order) {
+        g_msg[0] = 0;
+        return fail(LPM_EINVAL, "null work order");
+    }
+    return grid_records_impl(rec, rec_stride, rec_step0, rec_every, n_rec, src, sch, ph, grid,
+                             order, n_order, work, work_bytes, out, stream);
 }
 
 int lpm_grid_deposition(const lpm_accum* acc, float* out, lpm_stream stream)

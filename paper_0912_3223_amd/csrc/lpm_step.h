@@ -480,6 +480,10 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
     long long i = 0;
     uint32_t gid = 0;
     int b = 0, s = 0, krec = 0, next_rec = INT_MAX, s_take = 0;
+    // where the lane's particle is recorded: its queue position with a work
+    // order (records then follow the order's wind-node sorting), else its
+    // index; below 2^32 either way
+    uint32_t rq = 0;
     float x = 0.0f, y = 0.0f, z = 0.0f, m = 0.0f;
     float xl = 0.0f, yl = 0.0f;  // rounding residuals of x, y
     float bdep[NNUC];  // deposited by the lane's particle in this window (light kernels)
@@ -537,6 +541,7 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
                         b = (int)birth(g, p.s_release, p.n_total);
                     }
                     gid = (uint32_t)g;
+                    rq = (uint32_t)(p.order ? q : i);
                     m = i >= 0 ? as_global(p.M)[i] : 0.0f;
                     if (m > 0.0f) {
                         x = as_global(p.X)[i];
@@ -560,8 +565,10 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
                                     __builtin_amdgcn_exp2f(-p.lam_l2e[n] * age0)));
                             }
                         }
-                    } else if (p.n_rec > 0 && i >= 0) {
-                        as_global(rec_exit)[i] = INT_MIN;  // inactive before this window
+                    } else if (p.n_rec > 0 && (i >= 0 || p.order)) {
+                        // inactive before this window (or, with a work order,
+                        // an entry outside the launch: every position gets a word)
+                        as_global(rec_exit)[rq] = INT_MIN;
                     }
                 }
             }
@@ -579,11 +586,11 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
                     p, sv, tab, plane, gid, b, s, x, y, z, m, xl, yl, led, bdep, dw);
                 if (s == next_rec) {  // state after an output step, for gridding later
                     typedef float quad __attribute__((ext_vector_type(4)));
-                    // krec, the stride and i are below 2^32: one 32 x 32 -> 64-bit
+                    // krec, the stride and rq are below 2^32: one 32 x 32 -> 64-bit
                     // multiply-add forms the index
                     as_global(reinterpret_cast<quad*>(rec4))[(unsigned long long)(uint32_t)krec *
                                                                  (uint32_t)p.rec_stride +
-                                                             (uint32_t)i] = quad{x, y, z, m};
+                                                             rq] = quad{x, y, z, m};
                     ++krec;
                     next_rec = krec < p.n_rec ? next_rec + p.rec_every : INT_MAX;
                 }
@@ -599,7 +606,7 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
                         as_global(p.XL)[i] = xl;
                         as_global(p.YL)[i] = yl;
                     }
-                    if (p.n_rec > 0) as_global(rec_exit)[i] = st != 0 ? s - 1 : INT_MAX;
+                    if (p.n_rec > 0) as_global(rec_exit)[rq] = st != 0 ? s - 1 : INT_MAX;
                     if (st == 2) atomicOr(p.ctrl + LPM_CTRL_ERR, 1u);
                     have = false;
                     if constexpr (KZ != 4) {

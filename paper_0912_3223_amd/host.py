@@ -214,8 +214,10 @@ class DeviceRun:
         after each of its output steps (every ``every``-th step), gridded right
         after into ``out[k]`` for output step k.  Windows inside one field
         interval keep every particle of a launch on the same pair of hourly
-        wind fields.  ``on_window(w0, rec, n_rec)`` sees each window's record buffer before
-        it is reused; ``step_events`` (a list) receives a pair of timing events
+        wind fields.  ``on_window(w0, rec, n_rec, order)`` sees each window's record buffer
+        before it is reused, with the window's work order (int32, queue position to
+        particle; None without ``order``): with a work order the records are stored by
+        queue position (lpm_step_particles_record); ``step_events`` (a list) receives a pair of timing events
         around each step launch, recorded on the current stream.  With
         ``time_pairs`` a window whose steps all interpolate in one interval
         of a time-dependent wind steps on the time-pair copy of that interval
@@ -242,6 +244,7 @@ class DeviceRun:
                 if self.time_node(w0 + window - 1) == k:
                     fld = self.interval_field(k)
             st = self.work_order(w0, window) if order else None
+            worder = self._order[:st.n_order] if st is not None else None
             if step_events is not None:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
@@ -252,9 +255,9 @@ class DeviceRun:
                 step_events.append((e0, e1))
             k0 = w0 // every
             grid_records(rec, self.rec_stride, w0 + every - 1, every, n_rec, self.src, self.sch,
-                         self.ph, self.cgrid, work, out[k0:k0 + n_rec])
+                         self.ph, self.cgrid, work, out[k0:k0 + n_rec], order=worder)
             if on_window is not None:
-                on_window(w0, rec, n_rec)
+                on_window(w0, rec, n_rec, worder)
         return out
 
     def _rec_buf(self, n_rec: int) -> torch.Tensor:

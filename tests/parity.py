@@ -39,6 +39,26 @@ def run_gpu(case, steps_per_launch=60, snaps=(), state=None, s_begin=0, s_end=No
     return res
 
 
+def records_by_particle(rec, n_rec, stride, order):
+    """A window's record buffer (n_rec records of `stride` entries, then the
+    `last` words) in particle order, as (records [n_rec][stride][4], last
+    [stride]) device tensors.  With a work order the library stores queue
+    position q (particle order[q]) at q; particles the order does not list
+    get last = INT_MIN (no meaningful record)."""
+    import torch
+    recs = rec[: 4 * n_rec * stride].view(n_rec, stride, 4)
+    last = rec[4 * n_rec * stride: (4 * n_rec + 1) * stride].view(torch.int32)
+    if order is None:
+        return recs.clone(), last.clone()
+    idx = order.long()
+    m = idx.numel()
+    r2 = torch.zeros_like(recs)
+    l2 = torch.full_like(last, -2 ** 31)
+    r2[:, idx] = recs[:, :m]
+    l2[idx] = last[:m]
+    return r2, l2
+
+
 def run_oracle(case, snaps=(), state=None, s_begin=0, s_end=None, nthreads=0):
     o = oracle.Oracle(case)
     t = time.time()

@@ -234,6 +234,14 @@ def test_record_gridding_workspace_and_rejections(args):
     assert call(C.c_void_p(0x10010), n.value, fake) == L.LPM_EINVAL  # not 256-byte aligned
     assert call(None, n.value, fake) == L.LPM_EINVAL
     assert call(fake, n.value, None) == L.LPM_EINVAL
+    # records stored by work-order position: the order is checked too
+    ordered = lambda order, n_order: code(L, "lpm_grid_records_ordered", rec, 1000, 4, 5, 2, src,
+                                          sch, ph, grid, order, n_order, fake, n.value, fake,
+                                          None)
+    assert ordered(None, 10) == L.LPM_EINVAL and b"null work order" in L.lib().lpm_last_error()
+    assert ordered(C.c_void_p(0x10002), 10) == L.LPM_EINVAL       # misaligned
+    assert ordered(fake, 1001) == L.LPM_EINVAL                     # beyond n_local
+    assert ordered(fake, -1) == L.LPM_EINVAL
 
 
 def test_time_pair_fields_are_checked(args):

@@ -46,7 +46,7 @@ import numpy as np
 import pytest
 
 import synth
-from parity import distances, ledger_ok, log, rel_l2_masked
+from parity import distances, ledger_ok, log, records_by_particle, rel_l2_masked
 
 pytestmark = pytest.mark.gpu
 
@@ -65,13 +65,14 @@ def _recorded_run(case):
     run = L.DeviceRun(case)
     kept = {}
 
-    def on_window(w0, rec, n_rec):
-        n = run.rec_stride
-        for s in COMPARE:
-            if w0 <= s < w0 + WINDOW:
-                k = (s - (w0 + EVERY - 1)) // EVERY
-                kept[s] = (rec[: 4 * n_rec * n].view(n_rec, n, 4)[k].clone(),
-                           rec[4 * n_rec * n: 4 * n_rec * n + n].view(torch.int32).clone())
+    def on_window(w0, rec, n_rec, order):
+        need = [s for s in COMPARE if w0 <= s < w0 + WINDOW]
+        if not need:
+            return
+        recs, last = records_by_particle(rec, n_rec, run.rec_stride, order)
+        for s in need:
+            k = (s - (w0 + EVERY - 1)) // EVERY
+            kept[s] = (recs[k].clone(), last.clone())
 
     grids = run.run_recorded(EVERY, WINDOW, on_window=on_window)
     run.check()

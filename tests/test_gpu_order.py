@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from parity import log
+from parity import log, records_by_particle
 
 pytestmark = pytest.mark.gpu
 
@@ -81,8 +81,10 @@ def test_windows_in_work_order_equal_index_order(kind):
     for order in (False, True):
         run = L.DeviceRun(case)
         recs = []
-        grids = run.run_recorded(60, window, order=order,
-                                 on_window=lambda w0, rec, n_rec: recs.append(rec.clone()))
+        grids = run.run_recorded(
+            60, window, order=order,
+            on_window=lambda w0, rec, n_rec, o: recs.append(
+                records_by_particle(rec, n_rec, run.rec_stride, o)))
         run.check()
         out[order] = dict(state=run.state(), grids=grids.double().cpu().numpy(), recs=recs,
                           dep=run.grid_deposition().double().cpu().numpy(), led=run.ledger())
@@ -93,18 +95,16 @@ def test_windows_in_work_order_equal_index_order(kind):
     n_rec = window // 60
     birth = torch.from_numpy((sch.id_base + np.arange(n) * sch.id_stride) * sch.s_release
                              // sch.n_total).cuda()
-    for w, (ra, rb) in enumerate(zip(a["recs"], b["recs"])):
-        la = ra[4 * n_rec * n: (4 * n_rec + 1) * n].view(torch.int32)
-        lb = rb[4 * n_rec * n: (4 * n_rec + 1) * n].view(torch.int32)
+    # records by particle (the ordered run stores them by queue position)
+    for w, ((ra, la), (rb, lb)) in enumerate(zip(a["recs"], b["recs"])):
+        la, lb = la[:n], lb[:n]
         w_end = (w + 1) * window
         born = birth < w_end
         assert torch.equal(la[born], lb[born])
         for k in range(n_rec):
             s = window * w + 60 * k + 59
             use = (birth <= s) & (s < la)
-            va = ra[: 4 * n_rec * n].view(n_rec, n, 4)[k]
-            vb = rb[: 4 * n_rec * n].view(n_rec, n, 4)[k]
-            assert torch.equal(va[use], vb[use]), (w, k)
+            assert torch.equal(ra[k, :n][use], rb[k, :n][use]), (w, k)
     np.testing.assert_allclose(b["grids"], a["grids"], rtol=1e-6, atol=0)
     np.testing.assert_allclose(b["dep"], a["dep"], rtol=1e-6, atol=0)
     np.testing.assert_allclose(b["led"], a["led"], rtol=1e-12, atol=0)

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from parity import log
+from parity import log, records_by_particle
 
 pytestmark = pytest.mark.gpu
 
@@ -67,8 +67,10 @@ def test_windows_on_time_pairs_equal_the_field(ncomp):
     for tp in (False, True):
         run = L.DeviceRun(case)
         recs = []
-        grids = run.run_recorded(60, 720, time_pairs=tp,
-                                 on_window=lambda w0, rec, n_rec: recs.append(rec.clone()))
+        grids = run.run_recorded(
+            60, 720, time_pairs=tp,
+            on_window=lambda w0, rec, n_rec, o: recs.append(
+                records_by_particle(rec, n_rec, run.rec_stride, o)))
         run.check()
         out[tp] = dict(state=run.state(), grids=grids.double().cpu().numpy(), recs=recs,
                        dep=run.grid_deposition().double().cpu().numpy(), led=run.ledger(),
@@ -82,14 +84,14 @@ def test_windows_on_time_pairs_equal_the_field(ncomp):
     n, sch = case.schedule.local_count, case.schedule
     birth = torch.from_numpy((sch.id_base + np.arange(n) * sch.id_stride) * sch.s_release
                              // sch.n_total).cuda()
-    for w, (ra, rb) in enumerate(zip(a["recs"], b["recs"])):
-        la, lb = ra[48 * n: 49 * n].view(torch.int32), rb[48 * n: 49 * n].view(torch.int32)
-        assert torch.equal(la, lb)
+    for w, ((ra, la), (rb, lb)) in enumerate(zip(a["recs"], b["recs"])):
+        la, lb = la[:n], lb[:n]
+        born = birth < 720 * (w + 1)  # particles of the window's launch
+        assert torch.equal(la[born], lb[born])
         for k in range(12):
             s = 720 * w + 60 * k + 59
             use = (birth <= s) & (s < la)
-            va, vb = ra[: 48 * n].view(12, n, 4)[k], rb[: 48 * n].view(12, n, 4)[k]
-            assert torch.equal(va[use], vb[use]), (w, k)
+            assert torch.equal(ra[k, :n][use], rb[k, :n][use]), (w, k)
     # grids and deposition: the same float32 contributions, FP64 sums in
     # the order the atomics arrive
     np.testing.assert_allclose(b["grids"], a["grids"], rtol=1e-6, atol=0)
