@@ -732,6 +732,13 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const SortPass c)
 // Pass 4: one block per (owner tile, output step).  LDS: the tile's cells,
 // double [NNUC][nz][ps] (ty tx cells per level, padded).
 constexpr int kTileBatch = 4;
+// A tile holding more than kSplitMin records of an output step (the ones
+// near the source) is shared by up to kTileSplit blocks, each summing a
+// slice of its records; their FP64 tile sums are added to the output (zeroed
+// beforehand) with FP32 atomics.  Other tiles keep one block, which writes
+// its cells once.
+constexpr int kTileSplit = 4;
+constexpr long long kSplitMin = 16384;
 template <int NNUC>
 __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, const TileConst t,
                                                            int rec_step0, int rec_every)
@@ -758,6 +765,11 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
     // most tiles hold no record (the plume covers a few per output step):
     // their cells were cleared by one coalesced fill before this pass
     if (total == 0) return;
+    const int nsplit = total <= kSplitMin
+                           ? 1
+                           : (int)min((long long)kTileSplit, (total + kSplitMin - 1) / kSplitMin);
+    if ((int)blockIdx.z >= nsplit) return;
+    const long long jb = total * blockIdx.z / nsplit, je = total * (blockIdx.z + 1) / nsplit;
     const int ps = t.ps;
     for (int c = threadIdx.x; c < NNUC * g.nz * ps; c += kBlock) tile[c] = 0.0;
     __syncthreads();
@@ -796,15 +808,15 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
     // records: each thread takes kTileBatch of them at a time and issues
     // their loads before using any.  The records of the four ranges lie
     // contiguously in bin order (written so by the scatter pass).
-    for (long long j0 = threadIdx.x; j0 < total; j0 += (long long)kTileBatch * kBlock) {
+    for (long long j0 = jb + threadIdx.x; j0 < je; j0 += (long long)kTileBatch * kBlock) {
         float4 rr[kTileBatch];
         int bb[kTileBatch];
         bool ok[kTileBatch];
 #pragma unroll
         for (int u = 0; u < kTileBatch; ++u) {
-            // past the end: the last entry again (every load issued, no
+            // past the slice: its last entry again (every load issued, no
             // branch around it)
-            const long long j = min(j0 + (long long)u * kBlock, total - 1);
+            const long long j = min(j0 + (long long)u * kBlock, je - 1);
             const long long e = j < e0 ? lo0 + j
                               : j < e1 ? lo1 + (j - e0)
                               : j < e2 ? lo2 + (j - e1) : lo3 + (j - e2);
@@ -812,7 +824,7 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
             // particle twice could count more records than were born -- were
             // not written by the scatter and are skipped; total > 0 implies
             // cap >= 1)
-            ok[u] = j0 + (long long)u * kBlock < total && (unsigned long long)e < t.cap;
+            ok[u] = j0 + (long long)u * kBlock < je && (unsigned long long)e < t.cap;
             const long long ec = min(e, (long long)t.cap - 1);
             rr[u] = t.brec[ec];
             bb[u] = t.bborn[ec];
@@ -824,9 +836,12 @@ __global__ __launch_bounds__(kBlock) void tile_conc_kernel(const GridConst g, co
     __syncthreads();
     for (int c = threadIdx.x; c < NNUC * ncell; c += kBlock) {
         const int xx = c & (t.tx - 1), yy = (c >> t.lx) & (t.ty - 1), zn = c >> (t.lx + t.ly);
-        if (xx < wx_n && yy < wy_n)
-            out[((long long)zn * g.ny + ya + yy) * g.nx + xa + xx] =
-                (float)(tile[zn * ps + (c & (t.tx * t.ty - 1))] * t.inv_vol);
+        if (xx < wx_n && yy < wy_n) {
+            const float v = (float)(tile[zn * ps + (c & (t.tx * t.ty - 1))] * t.inv_vol);
+            float* o = out + ((long long)zn * g.ny + ya + yy) * g.nx + xa + xx;
+            if (nsplit == 1) *o = v;
+            else if (v != 0.0f) atomicAdd(o, v);
+        }
     }
 }
 
@@ -1787,7 +1802,7 @@ static int grid_records_impl(const float* rec, int64_t rec_stride, int32_t rec_s
         hipLaunchKernelGGL(lpm::fill_u32, dim3(std::min(blocks_for(2 * rp.nb), 16384u)), bs, 0, s,
                            (uint32_t*)t.off, 2 * rp.nb);
     }
-    const dim3 tg((unsigned)((long long)rp.ntx * rp.nty), (unsigned)n_rec);
+    const dim3 tg((unsigned)((long long)rp.ntx * rp.nty), (unsigned)n_rec, lpm::kTileSplit);
     switch (ph->n_nuc) {
     case 1: hipLaunchKernelGGL(lpm::tile_conc_kernel<1>, tg, bs, rp.tile_lds, s, g, t, rec_step0, rec_every); break;
     case 2: hipLaunchKernelGGL(lpm::tile_conc_kernel<2>, tg, bs, rp.tile_lds, s, g, t, rec_step0, rec_every); break;
