@@ -373,7 +373,7 @@ int lpm_grid_records_workspace(const lpm_schedule* sch, const lpm_physics* ph,
  * rec_stride): out[k] = the grid of lpm_grid_concentration after step s_k
  * (Sec. 3.2: activities summed on a rectangular grid every n-th step), the
  * same FP32 contributions summed in FP64 (where one column tile holds more
- * than 16384 records of an output step, in up to four FP64 partial sums
+ * than 8192 records of an output step, in up to eight FP64 partial sums
  * that are added in FP32).  work: caller-owned device
  * scratch, 256-byte aligned, of at least lpm_grid_records_workspace bytes,
  * overwritten; out: device float [n_rec][n_nuc][nz][ny][nx], overwritten
