@@ -737,7 +737,7 @@ constexpr int kTileBatch = 4;
 // slice of its records; their FP64 tile sums are added to the output (zeroed
 // beforehand) with FP32 atomics.  Other tiles keep one block, which writes
 // its cells once.  (24 h run, gridding time per run outside the step
-// kernel: 88 ms unsplit, 70 ms with 4 x 16384, 68.5 ms with 8 x 8192.)
+// kernel: 94 ms unsplit, 70 ms with 4 x 16384, 68.5 ms with 8 x 8192.)
 constexpr int kTileSplit = 8;
 constexpr long long kSplitMin = 8192;
 template <int NNUC>
