@@ -172,21 +172,27 @@ struct WaveTable {
     }
 };
 
-template <int NNUC>
-using DepTable = WaveTable<NNUC, 7>;
+// 2^TL cells per wave: 128, or 256 in the variants that run at three waves
+// per SIMD, whose blocks have the LDS for it.  A wave empties its table into
+// the FP64 grid when half of it is taken; where the plume is under rain
+// every particle deposits every step and those global atomics, on the same
+// cells from every wave, are what the step waits for -- a larger table
+// flushes less often.
+template <int NNUC, int TL = 7>
+using DepTable = WaveTable<NNUC, TL>;
 
 // Per-thread deposition while the particle stays in one grid cell (nearest
 // cell) or above one cell quad (cloud-in-cell): partial sums of the corner
 // weights times the deposited activity, flushed to the wave's table when the
 // cell changes and when the particle stops.
-template <int NNUC>
+template <int NNUC, int TL = 7>
 struct Dwell {
     int i0 = INT_MIN, j0 = 0;
     float acc[NNUC][4];
 
     int key_base = 0;  // scenario * plane in an ensemble launch
 
-    __device__ void flush(const StepConst& p, DepTable<NNUC>& tab, long long plane)
+    __device__ void flush(const StepConst& p, DepTable<NNUC, TL>& tab, long long plane)
     {
         // A lane stages at most one quad between two drain points of its wave
         // (the kernel drains whenever 64 free entries are not left), so the
@@ -201,7 +207,7 @@ struct Dwell {
     // weights in float: one FMA per axis (the grid origin folded into the
     // offset), accurate to ~3e-5 of a cell 50 km from the origin, where the
     // float position itself is already uncertain by more (4 mm of 250 m).
-    __device__ void add(const StepConst& p, DepTable<NNUC>& tab, long long plane, float x,
+    __device__ void add(const StepConst& p, DepTable<NNUC, TL>& tab, long long plane, float x,
                         float y, const float (&d)[NNUC])
     {
         const float fx = fmaf(x, p.d_inv_dx, p.d_cx);
@@ -291,13 +297,13 @@ struct LedgerAcc {
 // K_z kind at run time (including Eq. 3 with stability), decay chains and
 // stochastic deposition.
 // ---------------------------------------------------------------------------
-template <int NCOMP, int TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS>
+template <int NCOMP, int TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS, int TL>
 __device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
-                                       DepTable<NNUC>& tab, long long plane, uint32_t gid,
+                                       DepTable<NNUC, TL>& tab, long long plane, uint32_t gid,
                                        int b, int s, float& x, float& y, float& z, float& m,
                                        float& xl, float& yl,
                                        LedgerAcc<NNUC, KZ, KZ != 4 && !ENS>& led,
-                                       float (&bdep)[NNUC], Dwell<NNUC>& dw)
+                                       float (&bdep)[NNUC], Dwell<NNUC, TL>& dw)
 {
     const float age = (float)(s - b) * p.dt;
     // wind sample, random numbers, diffusivity, move and fold
@@ -444,14 +450,16 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
     }
     __syncthreads();
     const StepConst& p = pc;
-    __shared__ int tab_key[kWaves][DepTable<NNUC>::kSlots];
-    __shared__ double tab_val[kWaves][NNUC * DepTable<NNUC>::kSlots];
+    constexpr int kTL = step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP, ENS>() == 4 ? 7 : 8;
+    using Tab = DepTable<NNUC, kTL>;
+    __shared__ int tab_key[kWaves][Tab::kSlots];
+    __shared__ double tab_val[kWaves][NNUC * Tab::kSlots];
     __shared__ int tab_used[kWaves];
-    __shared__ int stage_key[kWaves][DEP ? 3 * DepTable<NNUC>::kStage : 1];
-    __shared__ float stage_val[kWaves][DEP ? 4 * NNUC * DepTable<NNUC>::kStage : 1];
+    __shared__ int stage_key[kWaves][DEP ? 3 * Tab::kStage : 1];
+    __shared__ float stage_val[kWaves][DEP ? 4 * NNUC * Tab::kStage : 1];
     __shared__ int stage_n[kWaves];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    DepTable<NNUC> tab{tab_key[wv], tab_val[wv], &tab_used[wv], stage_key[wv], stage_val[wv],
+    Tab tab{tab_key[wv], tab_val[wv], &tab_used[wv], stage_key[wv], stage_val[wv],
                        &stage_n[wv]};
     const long long plane = (long long)p.dnx * p.dny;
     if constexpr (DEP) tab.init(lane);
@@ -489,7 +497,7 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
     float bdep[NNUC];  // deposited by the lane's particle in this window (light kernels)
 #pragma unroll
     for (int n = 0; n < NNUC; ++n) bdep[n] = 0.0f;
-    Dwell<NNUC> dw;
+    Dwell<NNUC, kTL> dw;
 
     while (true) {
         // hand the next queue entries to the lanes without a particle
@@ -575,14 +583,14 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
         }
         // refills may have staged a quad per lane (ensembles: scenario change)
         if constexpr (DEP && ENS) {
-            if (tab.drain(lane, p.dep, plane, DepTable<NNUC>::kDrainAt, p.dmode == 0 ? 1 : 4,
+            if (tab.drain(lane, p.dep, plane, Tab::kDrainAt, p.dmode == 0 ? 1 : 4,
                           p.dnx, p.dny))
                 tab.flush_if_half_full(lane, p.dep, plane);
         }
         if (!__any(have)) break;
         for (int j = 0; j < p.refill_every; ++j) {
             if (have) {
-                const int st = advance<NCOMP, TIME, LEVELS, NNUC, KZ, DEP, ENS>(
+                const int st = advance<NCOMP, TIME, LEVELS, NNUC, KZ, DEP, ENS, kTL>(
                     p, sv, tab, plane, gid, b, s, x, y, z, m, xl, yl, led, bdep, dw);
                 if (s == next_rec) {  // state after an output step, for gridding later
                     typedef float quad __attribute__((ext_vector_type(4)));
@@ -625,7 +633,7 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
             }
             if constexpr (DEP) {
                 // a drain fills the table: move it out before it overflows
-                if (tab.drain(lane, p.dep, plane, DepTable<NNUC>::kDrainAt,
+                if (tab.drain(lane, p.dep, plane, Tab::kDrainAt,
                               p.dmode == 0 ? 1 : 4, p.dnx, p.dny))
                     tab.flush_if_half_full(lane, p.dep, plane);
             }
