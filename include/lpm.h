@@ -197,7 +197,12 @@ typedef struct {
 } lpm_grid;
 
 /* Accumulators of a run, all device memory owned by the caller:
- *  dep:    double [n_nuc][dep_grid.ny][dep_grid.nx], deposited activity;
+ *  dep:    double [copies][n_nuc][dep_grid.ny][dep_grid.nx], deposited
+ *          activity: copies = dep_copies (1 when 0), up to
+ *          LPM_MAX_DEP_COPIES.  The step kernels spread their atomics over
+ *          the copies (block b adds into copy b mod copies), so that the
+ *          many waves depositing into the same cells under rain do not all
+ *          meet on one address; lpm_grid_deposition adds the copies up;
  *  ledger: double [LPM_LEDGER_SLOTS][LPM_LEDGER_STRIDE]: entries
  *          4 n + e hold nuclide n's released (e = 0), deposited (1), decayed
  *          (2) and exited (3) activity, entry LPM_LEDGER_PSTEPS the number of
@@ -207,16 +212,18 @@ typedef struct {
  *          the error flags (bit 0: a particle became non-finite), the other
  *          words are working counters of the kernels (calls on one accum
  *          must therefore be ordered on one stream). */
+#define LPM_MAX_DEP_COPIES 64
+
 typedef struct {
     double* dep;
     double* ledger;
     uint32_t* ctrl;
     int32_t n_nuc;
-    int32_t reserved;
+    int32_t dep_copies; /* copies of the deposition grid in dep (0 or 1: one) */
     lpm_grid dep_grid;
 } lpm_accum;
 
-/* Zero dep, ledger and ctrl.  Stream-ordered. */
+/* Zero dep (every copy), ledger and ctrl.  Stream-ordered. */
 int lpm_accum_reset(const lpm_accum* acc, lpm_stream stream);
 
 /* Release (Sec. 2: particles released from a point source in each time step;

@@ -109,7 +109,7 @@ class Receptors(C.Structure):
 
 class Accum(C.Structure):
     _fields_ = [("dep", C.c_void_p), ("ledger", C.c_void_p), ("ctrl", C.c_void_p),
-                ("n_nuc", C.c_int32), ("reserved", C.c_int32), ("dep_grid", Grid)]
+                ("n_nuc", C.c_int32), ("dep_copies", C.c_int32), ("dep_grid", Grid)]
 
 
 def _load():

@@ -895,6 +895,18 @@ __global__ __launch_bounds__(kBlock) void to_f32(const double* __restrict__ src,
         dst[i] = (float)(src[i] * scale);
 }
 
+// dst[i] = the sum of the `copies` grids of n doubles at src, as float.
+__global__ __launch_bounds__(kBlock) void copies_to_f32(const double* __restrict__ src,
+                                                        int copies, float* dst, long long n)
+{
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        double v = 0.0;
+        for (int c = 0; c < copies; ++c) v += src[(long long)c * n + i];
+        dst[i] = (float)v;
+    }
+}
+
 }  // namespace lpm
 
 // ===========================================================================
@@ -1030,8 +1042,12 @@ int check_accum(const lpm_accum* acc)
         return fail(LPM_EINVAL, "misaligned accumulator");
     if ((double)acc->dep_grid.nx * acc->dep_grid.ny >= 2147483647.0)
         return fail(LPM_EINVAL, "deposition grid must have fewer than 2^31 - 1 cells");
+    if (acc->dep_copies < 0 || acc->dep_copies > LPM_MAX_DEP_COPIES)
+        return fail(LPM_EINVAL, "dep_copies must be in [0, %d]", LPM_MAX_DEP_COPIES);
     return check_grid(&acc->dep_grid, true);
 }
+
+static int dep_copies(const lpm_accum* acc) { return acc->dep_copies > 1 ? acc->dep_copies : 1; }
 
 double a0_of(const lpm_source* src, const lpm_schedule* sch, const lpm_physics* ph)
 {
@@ -1116,7 +1132,8 @@ int lpm_accum_reset(const lpm_accum* acc, lpm_stream stream)
     int rc = check_accum(acc);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const long long dn = (long long)acc->n_nuc * acc->dep_grid.nx * acc->dep_grid.ny;
+    const long long dn =
+        (long long)dep_copies(acc) * acc->n_nuc * acc->dep_grid.nx * acc->dep_grid.ny;
     hipLaunchKernelGGL(lpm::fill_f64, dim3(blocks_for(dn) < 4096 ? blocks_for(dn) : 4096),
                        dim3(lpm::kBlock), 0, s, acc->dep, dn);
     hipLaunchKernelGGL(lpm::fill_f64, dim3(blocks_for(LPM_LEDGER_SLOTS * LPM_LEDGER_STRIDE)),
@@ -1465,6 +1482,7 @@ static int step_impl(const lpm_state* st, const lpm_source* src, const lpm_sched
     if ((rc = check_field_steps(p, fld, step0, n_steps))) return rc;
     fill_depgrid(p, acc->dep_grid);
     p.dep = acc->dep; p.ledger = acc->ledger; p.ctrl = acc->ctrl;
+    p.dep_copies = dep_copies(acc);
 
     if (p.i_hi <= 0) return LPM_OK;
     const unsigned nb = blocks_for(p.i_hi);
@@ -1844,8 +1862,8 @@ int lpm_grid_deposition(const lpm_accum* acc, float* out, lpm_stream stream)
     if (!out || !aligned4(out)) return fail(LPM_EINVAL, "null or misaligned output");
     const long long total = (long long)acc->n_nuc * acc->dep_grid.nx * acc->dep_grid.ny;
     const unsigned fb = blocks_for(total) < 8192 ? blocks_for(total) : 8192;
-    hipLaunchKernelGGL(lpm::to_f32, dim3(fb), dim3(lpm::kBlock), 0, (hipStream_t)stream, acc->dep,
-                       out, total, 1.0);
+    hipLaunchKernelGGL(lpm::copies_to_f32, dim3(fb), dim3(lpm::kBlock), 0, (hipStream_t)stream,
+                       acc->dep, dep_copies(acc), out, total);
     return hip_status("lpm_grid_deposition");
 }
 

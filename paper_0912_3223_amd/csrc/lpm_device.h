@@ -94,7 +94,8 @@ struct StepConst {
     double* dep;
     double* ledger;
     uint32_t* ctrl;
-    int dnx, dny, dmode, pad2;
+    int dnx, dny, dmode;
+    int dep_copies;  // copies of the deposition grid one after another (>= 1)
     // deposition cell (quad) coordinate of x: x d_inv_dx + d_cx, d_cx =
     // -x0/dx (nearest cell) or -x0/dx - 1/2 (cloud in cell); the same in y
     float d_cx, d_cy, d_inv_dx, d_inv_dy, d_fnx, d_fny;

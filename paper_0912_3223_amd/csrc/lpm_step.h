@@ -462,6 +462,9 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
     Tab tab{tab_key[wv], tab_val[wv], &tab_used[wv], stage_key[wv], stage_val[wv],
                        &stage_n[wv]};
     const long long plane = (long long)p.dnx * p.dny;
+    // this block's copy of the deposition grid (ensembles keep one per scenario)
+    double* const depg =
+        ENS ? p.dep : p.dep + (long long)(blockIdx.x % (unsigned)p.dep_copies) * p.n_nuc * plane;
     if constexpr (DEP) tab.init(lane);
     __builtin_amdgcn_wave_barrier();
 
@@ -583,9 +586,9 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
         }
         // refills may have staged a quad per lane (ensembles: scenario change)
         if constexpr (DEP && ENS) {
-            if (tab.drain(lane, p.dep, plane, Tab::kDrainAt, p.dmode == 0 ? 1 : 4,
+            if (tab.drain(lane, depg, plane, Tab::kDrainAt, p.dmode == 0 ? 1 : 4,
                           p.dnx, p.dny))
-                tab.flush_if_half_full(lane, p.dep, plane);
+                tab.flush_if_half_full(lane, depg, plane);
         }
         if (!__any(have)) break;
         for (int j = 0; j < p.refill_every; ++j) {
@@ -633,16 +636,16 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
             }
             if constexpr (DEP) {
                 // a drain fills the table: move it out before it overflows
-                if (tab.drain(lane, p.dep, plane, Tab::kDrainAt,
+                if (tab.drain(lane, depg, plane, Tab::kDrainAt,
                               p.dmode == 0 ? 1 : 4, p.dnx, p.dny))
-                    tab.flush_if_half_full(lane, p.dep, plane);
+                    tab.flush_if_half_full(lane, depg, plane);
             }
         }
     }
     if constexpr (DEP) {
         dw.flush(p, tab, plane);  // every lane: its last particle's sums
-        tab.drain(lane, p.dep, plane, 1, p.dmode == 0 ? 1 : 4, p.dnx, p.dny);
-        tab.flush(lane, p.dep, plane);
+        tab.drain(lane, depg, plane, 1, p.dmode == 0 ? 1 : 4, p.dnx, p.dny);
+        tab.flush(lane, depg, plane);
     }
 
     // ledger slot: [nuclide][released, deposited, decayed, exited], steps

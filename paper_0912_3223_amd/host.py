@@ -41,6 +41,10 @@ def make_grid(g) -> Grid:
     return Grid(g.nx, g.ny, g.nz, g.mode, int(g.density), 0, g.x0, g.y0, g.z0, g.dx, g.dy, g.dz)
 
 
+#: copies of the deposition grid a DeviceRun keeps (lpm_accum.dep_copies)
+DEP_COPIES = 8
+
+
 class DeviceRun:
     """Device buffers and structs for one workload (a ``synth.Case``)."""
 
@@ -73,11 +77,13 @@ class DeviceRun:
         self.ph = make_physics(ph)
         dg, cg = case.dep_grid, case.conc_grid
         nn = ph.n_nuc
-        self.dep = torch.zeros((nn, dg.ny, dg.nx), **f64)
+        # copies of the deposition grid: the step kernels spread their
+        # flushes over them (fewer waves meet on one address under rain)
+        self._dep = torch.zeros((DEP_COPIES, nn, dg.ny, dg.nx), **f64)
         self.ledger_buf = torch.zeros((LEDGER_SLOTS, LEDGER_STRIDE, 4, 4), **f64)
         self.ctrl = torch.zeros(CTRL_WORDS, dtype=torch.int32, device=self.device)
-        self.acc = Accum(self.dep.data_ptr(), self.ledger_buf.data_ptr(), self.ctrl.data_ptr(),
-                         nn, 0, make_grid(dg))
+        self.acc = Accum(self._dep.data_ptr(), self.ledger_buf.data_ptr(), self.ctrl.data_ptr(),
+                         nn, DEP_COPIES, make_grid(dg))
         self.cgrid = make_grid(cg)
         self.conc_scratch = torch.empty((nn, cg.nz, cg.ny, cg.nx), **f64)
         self.conc = torch.empty((nn, cg.nz, cg.ny, cg.nx), **f32)
@@ -113,6 +119,12 @@ class DeviceRun:
     def grid_deposition(self) -> torch.Tensor:
         grid_deposition(self.acc, self.dep_out)
         return self.dep_out
+
+    @property
+    def dep(self) -> torch.Tensor:
+        """The FP64 deposition grid [n_nuc][ny][nx]: its copies added up
+        (for inspection; lpm_grid_deposition gives it as float)."""
+        return self._dep.sum(0)
 
     def ledger(self) -> np.ndarray:
         """[n_nuc][4]: released, deposited, decayed, exited (synchronises)."""

@@ -151,6 +151,12 @@ def test_rejects_bad_arguments(args):
     assert code(L, "lpm_grid_concentration", st, src, sch, ph, grid, 0, None,
                 C.c_void_p(0x10000), None) == L.LPM_EINVAL
     assert code(L, "lpm_grid_deposition", acc, None, None) == L.LPM_EINVAL
+    many = L.Accum.from_buffer_copy(acc)
+    many.dep_copies = 65  # above LPM_MAX_DEP_COPIES
+    assert code(L, "lpm_grid_deposition", many, C.c_void_p(0x10000), None) == L.LPM_EINVAL
+    assert b"dep_copies" in L.lib().lpm_last_error()
+    many.dep_copies = -1
+    assert step(st, src, sch, fld, ph, 0, 1, many, None) == L.LPM_EINVAL
     assert code(L, "lpm_release_particles", small, src, sch, ph, 0, 1, acc, None) == L.LPM_ECAPACITY
     assert L.lib().lpm_check(None, None) == L.LPM_EINVAL
 
