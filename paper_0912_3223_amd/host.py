@@ -42,7 +42,7 @@ def make_grid(g) -> Grid:
 
 
 #: copies of the deposition grid a DeviceRun keeps (lpm_accum.dep_copies)
-DEP_COPIES = 8
+DEP_COPIES = 16
 
 
 class DeviceRun:
