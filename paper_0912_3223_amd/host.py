@@ -48,7 +48,8 @@ DEP_COPIES = 16
 class DeviceRun:
     """Device buffers and structs for one workload (a ``synth.Case``)."""
 
-    def __init__(self, case, device: str = "cuda", capacity: Optional[int] = None):
+    def __init__(self, case, device: str = "cuda", capacity: Optional[int] = None,
+                 dep_copies: int = DEP_COPIES):
         self.case = case
         self.device = torch.device(device)
         sch, ph, fld = case.schedule, case.physics, case.field
@@ -79,11 +80,11 @@ class DeviceRun:
         nn = ph.n_nuc
         # copies of the deposition grid: the step kernels spread their
         # flushes over them (fewer waves meet on one address under rain)
-        self._dep = torch.zeros((DEP_COPIES, nn, dg.ny, dg.nx), **f64)
+        self._dep = torch.zeros((max(dep_copies, 1), nn, dg.ny, dg.nx), **f64)
         self.ledger_buf = torch.zeros((LEDGER_SLOTS, LEDGER_STRIDE, 4, 4), **f64)
         self.ctrl = torch.zeros(CTRL_WORDS, dtype=torch.int32, device=self.device)
         self.acc = Accum(self._dep.data_ptr(), self.ledger_buf.data_ptr(), self.ctrl.data_ptr(),
-                         nn, DEP_COPIES, make_grid(dg))
+                         nn, dep_copies, make_grid(dg))
         self.cgrid = make_grid(cg)
         self.conc_scratch = torch.empty((nn, cg.nz, cg.ny, cg.nx), **f64)
         self.conc = torch.empty((nn, cg.nz, cg.ny, cg.nx), **f32)

@@ -145,6 +145,30 @@ def test_launch_split_is_bitwise():
         np.testing.assert_allclose(a["ledger"], r["ledger"], rtol=1e-7, atol=1e-12)
 
 
+def test_deposition_grid_copies_change_no_result():
+    """One copy of the deposition grid or sixteen (block b adds into copy
+    b mod 16; lpm_grid_deposition adds them up): the same states, and the
+    same deposition up to the order of the FP64 sums."""
+    import paper_0912_3223_amd as L
+    c = synth.c1(n_total=40_000, n_steps=720)  # rain and dry deposition
+    out = {}
+    for copies in (1, 16):
+        r = L.DeviceRun(c, dep_copies=copies)
+        r.release(0, c.n_steps)
+        r.step(0, c.n_steps)
+        r.check()
+        out[copies] = (r.state(), r.grid_deposition().double().cpu().numpy(),
+                       r.dep.cpu().numpy(), r.ledger())
+    (sa, da, fa, la), (sb, db, fb, lb) = out[1], out[16]
+    for k in "xyzm":
+        np.testing.assert_array_equal(sa[k], sb[k])
+    assert fa.max() > 0.0
+    np.testing.assert_allclose(fb, fa, rtol=1e-12, atol=1e-15 * fa.max())
+    np.testing.assert_allclose(db, da, rtol=1e-6, atol=0)
+    np.testing.assert_allclose(lb, la, rtol=1e-12, atol=0)
+    log("deposition copies: %d cells with deposit, sums agree" % int((fa > 0).sum()))
+
+
 def test_subset_ids_reproduce_full_run():
     c = synth.c1(n_total=30_000, n_steps=400)
     full = run_gpu(c)
