@@ -410,8 +410,8 @@ def adjoint_bench(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only (no multi-GPU path); "
-                                   "run with --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (the library has no "
+                                   "multi-GPU path); run with --gpus 1"}))
         sys.exit(2)
     import torch  # noqa: F401
     import paper_0912_3223_amd  # noqa: F401  (fails loudly without liblpm.so)
