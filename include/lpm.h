@@ -492,6 +492,11 @@ typedef struct {
     lpm_launch launch;   /* settings of lpm_step_ensemble: the defaults (24, 56, 0,
                             256) after lpm_ensemble_prepare, the autotuner's pick
                             after lpm_autotune_ensemble; the caller may set them */
+    int32_t dep_copies;  /* copies of the scenarios' deposition grids in `dep`
+                            (as lpm_accum.dep_copies): 1 after
+                            lpm_ensemble_prepare; the caller may set it, up to
+                            LPM_MAX_DEP_COPIES */
+    int32_t reserved;
 } lpm_ensemble;
 
 /* Check the scenarios (n_scen <= LPM_MAX_SCENARIOS, disjoint state ranges
@@ -510,8 +515,9 @@ int lpm_release_ensemble(const lpm_state* st, const lpm_ensemble* ens, double* l
                          lpm_stream stream);
 
 /* lpm_step_particles for every scenario of a prepared window, in one
- * persistent launch.  dep: device double [n_scen][n_nuc][ny][nx] on
- * dep_grid; ledgers as for lpm_release_ensemble; ctrl: device uint32
+ * persistent launch.  dep: device double [copies][n_scen][n_nuc][ny][nx] on
+ * dep_grid, copies = ens->dep_copies (block b adds into copy b mod copies;
+ * the caller adds the copies up); ledgers as for lpm_release_ensemble; ctrl: device uint32
  * [LPM_CTRL_WORDS].  Wind field and physics (K, decay, rain) are shared; the
  * source (rate, wind scale, v_d, key) is per scenario.  n_nuc <= 2. */
 int lpm_step_ensemble(const lpm_state* st, const lpm_ensemble* ens, const lpm_field* fld,

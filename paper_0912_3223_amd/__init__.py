@@ -94,7 +94,8 @@ class Launch(C.Structure):
 class Ensemble(C.Structure):
     _fields_ = [("table", C.c_void_p), ("n_scen", C.c_int32), ("n_nuc", C.c_int32),
                 ("step0", C.c_int32), ("n_steps", C.c_int32), ("queue_len", C.c_int64),
-                ("max_release", C.c_int64), ("launch", Launch)]
+                ("max_release", C.c_int64), ("launch", Launch), ("dep_copies", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Tuning(C.Structure):

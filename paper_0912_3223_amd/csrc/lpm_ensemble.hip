@@ -142,6 +142,8 @@ int lpm_ensemble_prepare(const lpm_scenario* scen, int32_t n_scen, const lpm_sta
     out->queue_len = q;
     out->max_release = max_rel;
     out->launch = kDefaultLaunch;
+    out->dep_copies = 1;
+    out->reserved = 0;
     return LPM_OK;
 }
 
@@ -175,6 +177,8 @@ static int step_ensemble_impl(const lpm_state* st, const lpm_ensemble* ens,
     if ((rc = check_physics(ph)) || (rc = check_grid(dep_grid, true)) ||
         (rc = check_launch(ens->launch)))
         return rc;
+    if (ens->dep_copies < 0 || ens->dep_copies > LPM_MAX_DEP_COPIES)
+        return fail(LPM_EINVAL, "dep_copies must be in [0, %d]", LPM_MAX_DEP_COPIES);
     if (ph->n_nuc != ens->n_nuc) return fail(LPM_EINVAL, "physics and ensemble n_nuc differ");
     if (ph->n_nuc > 2) return fail(LPM_EINVAL, "ensemble launches support one or two nuclides");
     if (ph->chain || ph->dep_mode || ph->kz_kind == 3)
@@ -202,6 +206,7 @@ static int step_ensemble_impl(const lpm_state* st, const lpm_ensemble* ens,
     p.scen = (const lpm::DevScen*)ens->table;
     p.n_scen = ens->n_scen;
     p.dep = dep; p.ledger = ledgers; p.ctrl = ctrl;
+    p.dep_copies = ens->dep_copies > 1 ? ens->dep_copies : 1;
     if (plan) *plan = 0;
     if (p.i_hi <= 0) return LPM_OK;
     // wet deposition, or dry deposition of any scenario (v_d is per scenario
@@ -267,6 +272,7 @@ int lpm_autotune_ensemble(const lpm_state* st, lpm_ensemble* ens, const lpm_scen
     int rc = lpm_ensemble_prepare(scen, ens->n_scen, st, ph, ens->step0, trial_steps, ens->table,
                                   (int64_t)ens->n_scen * LPM_SCENARIO_BYTES, &trial, stream);
     if (rc) return rc;
+    trial.dep_copies = ens->dep_copies;  // the trials deposit like the real launches
     // Settings that launch alike (the same block size and schedule on the
     // same number of resident blocks: a wave count at or above what fits is
     // "as many as fit") are timed once, as the first of them.

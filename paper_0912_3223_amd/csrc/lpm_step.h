@@ -462,9 +462,10 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
     Tab tab{tab_key[wv], tab_val[wv], &tab_used[wv], stage_key[wv], stage_val[wv],
                        &stage_n[wv]};
     const long long plane = (long long)p.dnx * p.dny;
-    // this block's copy of the deposition grid (ensembles keep one per scenario)
-    double* const depg =
-        ENS ? p.dep : p.dep + (long long)(blockIdx.x % (unsigned)p.dep_copies) * p.n_nuc * plane;
+    // this block's copy of the deposition grid(s): one grid per nuclide, or
+    // in an ensemble launch one per scenario and nuclide
+    double* const depg = p.dep + (long long)(blockIdx.x % (unsigned)p.dep_copies) *
+                                     (ENS ? p.n_scen : 1) * p.n_nuc * plane;
     if constexpr (DEP) tab.init(lane);
     __builtin_amdgcn_wave_barrier();
 

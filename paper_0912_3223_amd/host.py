@@ -389,7 +389,9 @@ class EnsembleRun:
         dg = base.dep_grid
         nn = base.physics.n_nuc
         self.dgrid = make_grid(dg)
-        self.dep = torch.zeros((n_scen, nn, dg.ny, dg.nx), dtype=torch.float64, device=self.device)
+        # copies of the scenarios' deposition grids, as for DeviceRun
+        self._dep = torch.zeros((DEP_COPIES, n_scen, nn, dg.ny, dg.nx), dtype=torch.float64,
+                                device=self.device)
         self.ledgers = torch.zeros((n_scen, LEDGER_SLOTS, LEDGER_STRIDE), dtype=torch.float64,
                                    device=self.device)
         self.ctrl = torch.zeros(CTRL_WORDS, dtype=torch.int32, device=self.device)
@@ -401,11 +403,17 @@ class EnsembleRun:
         n_steps = self.base.n_steps - step0 if n_steps is None else n_steps
         self.ens = ensemble_prepare(self.scen, self.n_scen, self.st, self.ph, step0, n_steps,
                                     self.table)
+        self.ens.dep_copies = DEP_COPIES
         return self.ens
+
+    @property
+    def dep(self) -> torch.Tensor:
+        """The FP64 deposition grids [n_scen][n_nuc][ny][nx]: their copies added up."""
+        return self._dep.sum(0)
 
     def reset(self):
         self.m.zero_()
-        self.dep.zero_()
+        self._dep.zero_()
         self.ledgers.zero_()
         self.ctrl.zero_()
 
@@ -413,13 +421,13 @@ class EnsembleRun:
         release_ensemble(self.st, self.ens, self.ledgers)
 
     def step(self):
-        step_ensemble(self.st, self.ens, self.fld, self.ph, self.dgrid, self.dep, self.ledgers,
+        step_ensemble(self.st, self.ens, self.fld, self.ph, self.dgrid, self._dep, self.ledgers,
                       self.ctrl)
 
     def autotune(self, trial_steps: int, reps: int = 3):
         """Pick the launch settings of this ensemble (kept in ``self.ens``)."""
         t = autotune_ensemble(self.st, self.ens, self.scen, self.fld, self.ph, self.dgrid,
-                              self.dep, self.ledgers, self.ctrl, trial_steps, reps)
+                              self._dep, self.ledgers, self.ctrl, trial_steps, reps)
         self.reset()
         return t
 
