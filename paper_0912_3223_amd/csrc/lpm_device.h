@@ -337,9 +337,27 @@ __device__ __forceinline__ void trilinear(const float (&c)[8][NCOMP], float wx, 
 
 // Issue the loads of the wind stencil at (x, y, z) at the start of step s
 // (Sec. 3.2: linear in x, y, z and t).
+// Time weight of step s: time nodes sit at t0 + k dt_field (not
+// cell-centred).  The weight is the same for every particle of a step; in
+// FP32 the rounding of 1/dt_field and of the fractional node index would
+// bias it by up to ~1e-7 for a whole field interval, a coherent wind error
+// that moves every trajectory the same way, so it is taken in FP64.
+__device__ __forceinline__ float time_weight(const StepConst& p, int s, int& t0)
+{
+    const double ft = fmin(fmax(fma((double)s, p.ft_step, p.ft_zero), 0.0), (double)p.ftmax);
+    t0 = min((int)ft, p.tmaxi);
+    return (float)(ft - (double)t0);
+}
+
+// Launches on a time-pair copy over at most kWtTable steps tabulate the time
+// weight per block (the same FP64 expression, rounded once): a lookup per
+// step instead of eight FP64 operations.
+constexpr int kWtTable = 1024;
+
 template <int NCOMP, int TIME, bool LEVELS>
 __device__ __forceinline__ void wind_gather(const StepConst& p, float x, float y, float z,
-                                            int s, WindTap<NCOMP, TIME>& w)
+                                            int s, WindTap<NCOMP, TIME>& w,
+                                            const float* wt_tab = nullptr)
 {
     int i0, j0, k0;
     axis(x, p.fcx, p.inv_dx, p.fxmax, p.imax, i0, w.wx);
@@ -347,20 +365,16 @@ __device__ __forceinline__ void wind_gather(const StepConst& p, float x, float y
     if constexpr (LEVELS) levels(p.lev, p.nz, z, k0, w.wz);
     else axis(z, -0.5f, p.inv_dz, p.fzmax, p.kmax, k0, w.wz);
     int base = k0 * p.sk + j0 * p.sj + i0 * p.si;
-    if constexpr (TIME) {
-        // time nodes sit at t0 + k dt_field (not cell-centred).  The time
-        // weight is the same for every particle of a step; in FP32 the
-        // rounding of 1/dt_field and of the fractional node index would bias
-        // it by up to ~1e-7 for a whole field interval, a coherent wind error
-        // that moves every trajectory the same way, so it is taken in FP64.
-        const double ft = fmin(fmax(fma((double)s, p.ft_step, p.ft_zero), 0.0), (double)p.ftmax);
-        const int t0 = min((int)ft, p.tmaxi);
-        w.wt = (float)(ft - (double)t0);
+    if constexpr (NCOMP == 2 && TIME == 2) {  // a time-pair copy, known at compile time
+        // (one interval: the time stride is 0, only the weight changes)
+        int t0;
+        w.wt = wt_tab ? wt_tab[s - p.step0] : time_weight(p, s, t0);
+        gather8_tpair(p.f, base, p.di, p.dj, p.dk, w.c);
+    } else if constexpr (TIME) {
+        int t0;
+        w.wt = time_weight(p, s, t0);
         base += t0 * p.st;
-        if constexpr (NCOMP == 2 && TIME == 2) {  // a time-pair copy, known at compile time
-            gather8_tpair(p.f, base, p.di, p.dj, p.dk, w.c);
-            return;
-        } else if constexpr (NCOMP == 2) {
+        if constexpr (NCOMP == 2) {
             if (p.tpair) {
                 gather8_tpair(p.f, base, p.di, p.dj, p.dk, w.c);
                 return;
@@ -504,10 +518,11 @@ __device__ __forceinline__ float comp_add(float hi, float& lo, float d)
 template <int NCOMP, int TIME, bool LEVELS, int KZ, bool UNIFORM_KEY>
 __device__ __forceinline__ float motion(const StepConst& p, float wscale, uint32_t key1,
                                         uint32_t gid, int s, float x, float y, float z,
-                                        float& xl, float& yl, float& xn, float& yn, float& zn)
+                                        float& xl, float& yl, float& xn, float& yn, float& zn,
+                                        const float* wt_tab = nullptr)
 {
     WindTap<NCOMP, TIME> tap;
-    wind_gather<NCOMP, TIME, LEVELS>(p, x, y, z, s, tap);
+    wind_gather<NCOMP, TIME, LEVELS>(p, x, y, z, s, tap, wt_tab);
     float xi0, xi1, xi2;
     normals3<UNIFORM_KEY>(gid, (uint32_t)s, p.key0, key1, xi0, xi1, xi2);
     float K, dK, Km, dKm;

@@ -298,7 +298,8 @@ struct LedgerAcc {
 // stochastic deposition.
 // ---------------------------------------------------------------------------
 template <int NCOMP, int TIME, bool LEVELS, int NNUC, int KZ, bool DEP, bool ENS, int TL>
-__device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
+__device__ __forceinline__ int advance(const StepConst& p, const float* wt_tab,
+                                       const SrcVals& sv,
                                        DepTable<NNUC, TL>& tab, long long plane, uint32_t gid,
                                        int b, int s, float& x, float& y, float& z, float& m,
                                        float& xl, float& yl,
@@ -309,7 +310,7 @@ __device__ __forceinline__ int advance(const StepConst& p, const SrcVals& sv,
     // wind sample, random numbers, diffusivity, move and fold
     float xn, yn, zn;
     motion<NCOMP, TIME, LEVELS, KZ, !ENS>(p, sv.wscale, sv.key1, gid, s, x, y, z, xl, yl, xn, yn,
-                                          zn);
+                                          zn, wt_tab);
     // decay factors at the start of the step
     float D[NNUC];
 #pragma unroll
@@ -448,8 +449,20 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
         for (int c = threadIdx.x; c <= pk.n_scen; c += BLOCK)
             scen_qbase[c] = c < pk.n_scen ? pk.scen[c].qbase : pk.i_hi;
     }
+    // time weights of the launch's steps on a time-pair copy (one interval)
+    constexpr bool kWtTab = TIME == 2 && NCOMP == 2;
+    __shared__ float wt_lds[kWtTab ? kWtTable : 1];
+    const bool use_tab = kWtTab && pk.step_end - pk.step0 <= kWtTable;
+    if constexpr (kWtTab) {
+        if (use_tab)
+            for (int j = threadIdx.x; j < pk.step_end - pk.step0; j += BLOCK) {
+                int t0;
+                wt_lds[j] = time_weight(pk, pk.step0 + j, t0);
+            }
+    }
     __syncthreads();
     const StepConst& p = pc;
+    const float* const wt_tab = use_tab ? wt_lds : nullptr;
     constexpr int kTL = step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP, ENS>() == 4 ? 7 : 8;
     using Tab = DepTable<NNUC, kTL>;
     __shared__ int tab_key[kWaves][Tab::kSlots];
@@ -595,7 +608,7 @@ __global__ __launch_bounds__(BLOCK, (step_min_blocks<NCOMP, TIME, NNUC, KZ, DEP,
         for (int j = 0; j < p.refill_every; ++j) {
             if (have) {
                 const int st = advance<NCOMP, TIME, LEVELS, NNUC, KZ, DEP, ENS, kTL>(
-                    p, sv, tab, plane, gid, b, s, x, y, z, m, xl, yl, led, bdep, dw);
+                    p, wt_tab, sv, tab, plane, gid, b, s, x, y, z, m, xl, yl, led, bdep, dw);
                 if (s == next_rec) {  // state after an output step, for gridding later
                     typedef float quad __attribute__((ext_vector_type(4)));
                     // krec, the stride and rq are below 2^32: one 32 x 32 -> 64-bit
