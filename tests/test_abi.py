@@ -325,3 +325,21 @@ def test_work_order_is_checked(args):
     ordered.order = 0x10002
     assert code(L, "lpm_step_particles", ordered, src, sch, fld, ph, 0, 10, acc,
                 None) == L.LPM_EINVAL
+
+
+def test_ensemble_step_arguments_are_checked(args):
+    """lpm_step_ensemble rejects bad deposition copies and launch settings on
+    the host, before anything is launched (fake device pointers)."""
+    L, st, src, sch, ph, fld, acc, grid = args
+    fake = C.c_void_p(0x10000)
+    ens = L.Ensemble(0x10000, 1, 2, 0, 10, 1000, 1000, L.Launch(24, 56, 0, 256), 1, 0)
+    dg = acc.dep_grid
+    step = lambda e: code(L, "lpm_step_ensemble", st, e, fld, ph, dg, fake, fake, fake, None)
+    bad = L.Ensemble.from_buffer_copy(ens)
+    bad.dep_copies = 65  # above LPM_MAX_DEP_COPIES
+    assert step(bad) == L.LPM_EINVAL and b"dep_copies" in L.lib().lpm_last_error()
+    bad.dep_copies = -1
+    assert step(bad) == L.LPM_EINVAL
+    bad = L.Ensemble.from_buffer_copy(ens)
+    bad.launch.block = 192  # not one of the instantiated block sizes
+    assert step(bad) == L.LPM_EINVAL
