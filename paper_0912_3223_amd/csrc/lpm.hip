@@ -576,15 +576,15 @@ struct OrderConst {
     int* order;
 };
 
-// Node (j nx + i) nz + k of particle i, or -1 when it is inactive.
-__device__ __forceinline__ long long order_node(const OrderConst& o, long long i)
+// Node (j nx + i) nz + k of a particle with mass m at (x, y, z), or -1 when
+// it is inactive.
+__device__ __forceinline__ long long order_node(const OrderConst& o, float m, float x, float y,
+                                                float z)
 {
-    if (!(as_global(o.M)[i] > 0.0f)) return -1;
-    const int ix = min(max((int)floorf(fmaf(as_global(o.X)[i], o.inv_dx, o.fcx)), 0), o.nx - 1);
-    const int iy = min(max((int)floorf(fmaf(as_global(o.Y)[i], o.inv_dy, o.fcy)), 0), o.ny - 1);
-    const int iz = o.inv_dz > 0.0f
-                       ? min(max((int)floorf(as_global(o.Z)[i] * o.inv_dz), 0), o.nz - 1)
-                       : 0;
+    if (!(m > 0.0f)) return -1;
+    const int ix = min(max((int)floorf(fmaf(x, o.inv_dx, o.fcx)), 0), o.nx - 1);
+    const int iy = min(max((int)floorf(fmaf(y, o.inv_dy, o.fcy)), 0), o.ny - 1);
+    const int iz = o.inv_dz > 0.0f ? min(max((int)floorf(z * o.inv_dz), 0), o.nz - 1) : 0;
     return ((long long)iy * o.nx + ix) * o.nz + iz;
 }
 
@@ -602,12 +602,25 @@ __global__ __launch_bounds__(kBlock) void order_keys_kernel(const OrderConst o)
     __shared__ unsigned long long base_s[2];
     for (long long a = (long long)blockIdx.x * kSortTile; a < o.n_old;
          a += (long long)gridDim.x * kSortTile) {
+        // every load of the tile issued before any is used (the state of an
+        // index past n_old is that of the last one, and not used): reading
+        // m first and the position only for live particles made each thread
+        // wait for its loads one particle at a time
+        float m4[kPer][4];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const long long e = min(a + (long long)j * kBlock + threadIdx.x, o.n_old - 1);
+            m4[j][0] = as_global(o.M)[e];
+            m4[j][1] = as_global(o.X)[e];
+            m4[j][2] = as_global(o.Y)[e];
+            m4[j][3] = as_global(o.Z)[e];
+        }
         long long node[kPer];
         unsigned n_act = 0u, n_off = 0u;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const long long e = a + (long long)j * kBlock + threadIdx.x;
-            node[j] = e < o.n_old ? order_node(o, e) : -2;
+            node[j] = e < o.n_old ? order_node(o, m4[j][0], m4[j][1], m4[j][2], m4[j][3]) : -2;
             n_act += node[j] >= 0;
             n_off += node[j] == -1;
         }
