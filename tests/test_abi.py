@@ -224,6 +224,17 @@ def test_record_gridding_workspace_and_rejections(args):
     # (plus one int per chunk of 2048 particle ids: 1 chunk)
     assert n.value == (2 * a256(8 * nb) + a256(8 * ((nb + 2047) // 2048)) + a256(4 * 1)
                        + a256(16 * 1500) + a256(4 * 1500))
+    # one int per chunk of 2048 recorded positions, counted over every local
+    # particle (a work-ordered launch records by queue position), however
+    # few are born by the recorded steps: 200000 particles, 98 chunks (of
+    # which the 20000 born by step 0 of the 10-step release fill 10)
+    big = L.Schedule.from_buffer_copy(sch)
+    big.n_total = big.n_local = 200_000
+    n2 = C.c_int64(-1)
+    assert code(L, "lpm_grid_records_workspace", big, ph, grid, 0, 1, 1, C.byref(n2)) == L.LPM_OK
+    nb1, born = nb // 2, 20_000  # one record step
+    assert n2.value == (2 * a256(8 * nb1) + a256(8 * ((nb1 + 2047) // 2048)) + a256(4 * 98)
+                        + a256(16 * born) + a256(4 * born))
     tall = L.Grid.from_buffer_copy(grid)
     tall.nz = 3073  # 2 nuclides x 3073 levels x 8 B: one column exceeds the block's LDS
     assert q(tall, 0, 1, 1) == L.LPM_EINVAL
